@@ -1,0 +1,227 @@
+/*
+ * upsample.h -- C ABI of the MI355X (gfx950) library for the high-resolution
+ * (HR) upsampling step of "Interactive High-Resolution Simulation of Granular
+ * Material" (arXiv 2308.01629), Section 4.
+ *
+ * One step advances every HR particle i against a frame of low-resolution (LR)
+ * guide particles j:
+ *   w_ij  = max(0, (1 - |X_j - x_i|^2 / (9 r_LR^2))^3)              (Section 4, weight)
+ *   v~_i  = sum_j w_ij V_j / sum_j w_ij                             (Section 4, Shepard average)
+ *   a_i   = 1 - max_j w_ij if max w <= c1 or max w / sum w >= c2, else 0   (Section 4, blend)
+ *   v_i'  = (1 - a_i) v~_i + a_i (v_i + dt g)                        (Section 4, velocity)
+ *   x_i'  = x_i + dt v_i'                                           (Section 4, position)
+ * LR particles flagged rigid count only when a granular LR particle is within
+ * the support of HR particle i (Section 4, last paragraph).  Afterwards the
+ * planar walls of the scene are applied in order (a contract of this library;
+ * the paper gives no HR boundary step).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Particle arrays are caller-owned DEVICE memory, float32 structure-of-arrays
+ *   [3][n] (x row, then y row, then z row), contiguous.  lr_rigid is a device
+ *   uint8 array [n_lr] (0 granular, 1 rigid or boundary sample) or NULL for
+ *   "all granular".
+ * - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL = the
+ *   null stream).  Calls return as soon as the work is enqueued; results are
+ *   ready when the stream reaches that point.  Step functions never allocate:
+ *   all scratch is allocated by upsample_init (or upsample_autotune).
+ * - Return value: UPSAMPLE_OK (0) or one of the UPSAMPLE_ERR_* codes below.
+ *   Argument errors are detected on the host before any device work is
+ *   enqueued, so a rejected call has no effect.  upsample_last_error() gives a
+ *   message for the last failing call on a handle.
+ * - A handle is not thread-safe; separate handles are independent.  Calls on
+ *   one handle that overlap on different streams race on its scratch.
+ */
+#ifndef UPSAMPLE_H
+#define UPSAMPLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UPSAMPLE_OK                 0
+#define UPSAMPLE_ERR_INVALID_ARG    1  /* null handle/pointer, bad size or parameter   */
+#define UPSAMPLE_ERR_CAPACITY       2  /* n_lr > max_lr or n_hr > max_hr               */
+#define UPSAMPLE_ERR_GRID_TOO_LARGE 3  /* cell count >= 2^31 or an axis > 2^20 cells   */
+#define UPSAMPLE_ERR_NO_DEVICE      4  /* no HIP device visible                       */
+#define UPSAMPLE_ERR_OOM            5  /* device allocation failed                    */
+#define UPSAMPLE_ERR_HIP            6  /* a HIP runtime call or kernel launch failed  */
+#define UPSAMPLE_ERR_NONFINITE      7  /* VALIDATE flag: non-finite input found       */
+#define UPSAMPLE_ERR_STATE          8  /* call order: e.g. advance before build_grid  */
+
+#define UPSAMPLE_MAX_WALLS          32
+#define UPSAMPLE_WALL_FLOATS        12
+#define UPSAMPLE_DEFAULT_CELL_FACTOR 1.0001f
+
+/* flags */
+#define UPSAMPLE_FLAG_VALIDATE      1u  /* scan inputs for NaN/Inf (synchronises the stream) */
+
+typedef struct upsample_handle_s* upsample_handle;
+
+/*
+ * Parameters of one scene (Section 4 symbols in brackets).
+ *   r_lr         LR radius [r_LR] > 0; the kernel support is h = 3 r_lr.
+ *   r_hr         HR radius [r_HR] >= 0; used only as the wall offset.
+ *   dt           HR time step [dt_HR] >= 0 (Section 5.2 uses 0.0167 s).
+ *   g            gravity [g], default (0, -9.81, 0) (Algorithm 1: |g| = 9.81).
+ *   c1, c2       blend thresholds, default 512/729 and 0.6 (Section 4).
+ *   domain_lo/hi axis-aligned box covered by the neighbour grid; particles
+ *                outside it are clamped into the edge cells (results stay exact).
+ *   cell_factor  grid cell size = cell_factor * h; 0 = UPSAMPLE_DEFAULT_CELL_FACTOR.
+ *                The stencil reach R is the smallest integer with
+ *                R >= h / cell_size + 16 * max_axis_cells * 2^-24.
+ *   n_walls, walls  host array [n_walls][12]: n(3), d, a(3), b, o(3), R.  Plane
+ *                n.x = d, unit normal n into the admissible side.  After
+ *                integration, for each wall in order, the wall acts on HR particle
+ *                i when a.x' >= b, the in-plane distance of x' from o is >= R
+ *                (R = 0: no hole) and n.x - d >= 0 for the pre-step x.  An acting
+ *                wall with n.x' - d < r_hr sets x' += (r_hr - (n.x' - d)) n and, if
+ *                n.v' < 0, v' -= (n.v') n.  Copied at init.
+ *   max_lr, max_hr  capacities; scratch is sized for them at init.
+ *   flags        UPSAMPLE_FLAG_*.
+ */
+typedef struct {
+  float r_lr;
+  float r_hr;
+  float dt;
+  float g[3];
+  float c1;
+  float c2;
+  float domain_lo[3];
+  float domain_hi[3];
+  float cell_factor;
+  int32_t n_walls;
+  const float* walls;
+  int64_t max_lr;
+  int64_t max_hr;
+  uint32_t flags;
+} upsample_params;
+
+/* Integer grid contract, identical on every device and on the host.
+ *   cell coordinate c_a = clamp(floor(fl32(fl32(X_a - lo_a) * inv_cell_size)), 0, dims_a - 1)
+ *   cell key        k   = c_x + dims_x (c_y + dims_y c_z)
+ *   membership      fl32(fl32(fl32(dx dx) + fl32(dy dy)) + fl32(dz dz)) < h2,
+ *                   d = fl32(X_j - x_i), each operation rounded separately.
+ *   inv_cell_size = fl32(1 / cell_size), h2 = fl32(9 r_lr^2), inv_h2 = fl32(1 / (9 r_lr^2)). */
+typedef struct {
+  int32_t dims[3];
+  int32_t reach;
+  int64_t n_cells;
+  double cell_size;
+  float inv_cell_size;
+  float h2;
+  float inv_h2;
+  float lo[3];
+} upsample_grid_info;
+
+/* Fill *p with the defaults above (r_lr = 0.02, r_hr = 0.005, dt = 1/60, unit
+ * box, no walls, capacities 0).  Host only.  Returns INVALID_ARG for p == NULL. */
+int upsample_default_params(upsample_params* p);
+
+/* Validate *p and compute its grid on the host; touches no device.  Returns
+ * INVALID_ARG or GRID_TOO_LARGE for a bad *p. */
+int upsample_grid_info_for(const upsample_params* p, upsample_grid_info* out);
+
+/* Create a handle on the current HIP device and allocate its scratch.  Returns
+ * INVALID_ARG / GRID_TOO_LARGE for bad parameters (checked first), NO_DEVICE
+ * when no device is visible, OOM when allocation fails.  *out is set only on
+ * success. */
+int upsample_init(const upsample_params* p, upsample_handle* out);
+
+/* Release a handle (NULL is a no-op).  The caller must make sure no enqueued
+ * work still uses it. */
+int upsample_destroy(upsample_handle h);
+
+/* Static message for an error code; message of the last failing call on h. */
+const char* upsample_strerror(int code);
+const char* upsample_last_error(upsample_handle h);
+
+/* The handle's grid (as upsample_grid_info_for of its current parameters). */
+int upsample_get_grid_info(upsample_handle h, upsample_grid_info* out);
+
+/*
+ * Uniform-grid rebuild of one LR frame (the neighbour search of Section 5.1,
+ * compact-hashing style): cell keys, counting sort stable in the original index,
+ * cell ranges, and an LR copy in sorted order kept in the handle.  lr_x, lr_v:
+ * [3][n_lr]; n_lr may be 0 (every HR particle then falls freely).
+ */
+int upsample_build_grid(upsample_handle h, const float* lr_x, const float* lr_v,
+                        const uint8_t* lr_rigid, int64_t n_lr, void* stream);
+
+/*
+ * Advance n_hr HR particles one step against the LR frame of the last
+ * upsample_build_grid on this handle (Section 4).  hr_x, hr_v: state at t,
+ * [3][n_hr]; hr_x_out, hr_v_out: state at t+1, may alias hr_x, hr_v (in place).
+ * Returns STATE if no grid has been built.
+ */
+int upsample_advance(upsample_handle h, const float* hr_x, const float* hr_v,
+                     float* hr_x_out, float* hr_v_out, int64_t n_hr, void* stream);
+
+/* upsample_build_grid followed by upsample_advance: one full step. */
+int upsample_step(upsample_handle h,
+                  const float* lr_x, const float* lr_v, const uint8_t* lr_rigid, int64_t n_lr,
+                  const float* hr_x, const float* hr_v, float* hr_x_out, float* hr_v_out,
+                  int64_t n_hr, void* stream);
+
+/*
+ * Adjoint of upsample_step (not in the paper): given dL/dx' and dL/dv' for the
+ * step that took (hr_x, hr_v) to (x', v') against the LR frame (lr_x, lr_v,
+ * lr_rigid), write dL/dx and dL/dv (gx_in, gv_in, [3][n_hr], may alias gx_out,
+ * gv_out) and ADD dL/dX, dL/dV into g_lr_x, g_lr_v ([3][n_lr], caller-zeroed).
+ * The alpha branch, neighbour membership, the argmax of the weights (ties: the
+ * smallest LR index) and the wall activations are held at their forward values.
+ * Rebuilds the grid from lr_x (so the handle's grid afterwards is that frame's).
+ * LR gradients are accumulated with float atomics: summation order, and so the
+ * last bits, may differ between runs.
+ */
+int upsample_step_backward(upsample_handle h,
+                           const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                           int64_t n_lr, const float* hr_x, const float* hr_v, int64_t n_hr,
+                           const float* gx_out, const float* gv_out,
+                           float* gx_in, float* gv_in, float* g_lr_x, float* g_lr_v,
+                           void* stream);
+
+/*
+ * Reorder HR particles in place by grid cell (cells of the handle's grid, so
+ * consecutive particles share a stencil).  hr_x, hr_v: [3][n_hr] permuted in
+ * place; perm_out (device int32 [n_hr], may be NULL) receives, for each new
+ * position, the particle's old index.  The order within a cell is unspecified.
+ * Per-particle results of later steps do not depend on the order.
+ */
+int upsample_sort_hr(upsample_handle h, float* hr_x, float* hr_v, int64_t n_hr,
+                     int32_t* perm_out, void* stream);
+
+/*
+ * Debug exports (for parity tests).
+ * upsample_debug_grid copies the last build's cell keys [n_lr] (original
+ * order), sorted order perm [n_lr] and cell_start [n_cells + 1] into device
+ * buffers (any may be NULL).
+ * upsample_debug_neighbors runs the step's stencil walk for hr_x/hr_v against
+ * the last grid and writes, per HR particle, the member count (float32
+ * predicate above, all types), up to max_k member LR ids (original indices,
+ * walk order) into ids[i * max_k + c], and a branch byte: bit 0 = alpha branch
+ * taken, bit 1 = a granular LR is within the support, bit 2 = the sum of
+ * weights is positive.  Any output pointer may be NULL.
+ */
+int upsample_debug_grid(upsample_handle h, uint32_t* keys, uint32_t* perm,
+                        uint32_t* cell_start, void* stream);
+int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* hr_v,
+                             int64_t n_hr, uint32_t* count, uint32_t* ids, int64_t max_k,
+                             uint8_t* branch, void* stream);
+
+/*
+ * Kernel-time probe for one handle: when enabled, upsample_advance records HIP
+ * events around its gather kernel on the call's stream, and
+ * upsample_timing_read returns the summed milliseconds and the number of
+ * launches since the last read (it synchronises on the last event).
+ */
+int upsample_timing_enable(upsample_handle h, int enable);
+int upsample_timing_read(upsample_handle h, double* advance_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UPSAMPLE_H */

@@ -36,6 +36,7 @@ float64 before any floating-point work except the integer-contract stages.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 from typing import Dict, Optional, Tuple
 
@@ -51,6 +52,7 @@ C2 = 0.6             # empirically chosen ratio threshold (Section 4)
 DEFAULT_CELL_FACTOR = 1.0001
 BAND = 1e-5          # alpha-branch band: either branch is accepted inside it
 WALL_BAND = 4e-6     # wall-decision band (metres)
+WORKERS = min(16, os.cpu_count() or 1)   # KD-tree query threads (numpy work is single-threaded)
 
 
 # ---------------------------------------------------------------------------
@@ -164,7 +166,7 @@ def neighbours_kdtree(lr_x: np.ndarray, hr_x: np.ndarray, h: float, h2_f,
     if lr_x.shape[1] == 0 or n_hr == 0:
         return np.zeros(n_hr + 1, np.int64), np.zeros(0, np.int64)
     tree = cKDTree(lr_x.T.astype(F64))
-    cand = tree.query_ball_point(hr_x.T.astype(F64), r=h * (1.0 + 1e-5), workers=-1)
+    cand = tree.query_ball_point(hr_x.T.astype(F64), r=h * (1.0 + 1e-5), workers=WORKERS)
     counts = np.fromiter((len(c) for c in cand), dtype=np.int64, count=n_hr)
     ii = np.repeat(np.arange(n_hr), counts)
     jj = np.concatenate([np.asarray(c, dtype=np.int64) for c in cand]) if counts.sum() else np.zeros(0, np.int64)

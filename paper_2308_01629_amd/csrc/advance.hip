@@ -1,0 +1,154 @@
+// The upsampling step proper (Section 4): per HR particle, a walk over the
+// (2R+1)^3 cell stencil of the LR grid accumulating the kernel-weighted sums,
+// then the blend parameter, the gravity blend, symplectic Euler and the walls,
+// all in one kernel so each HR particle is read once and written once.
+//
+// HR state is structure-of-arrays float32 [3][n]: lanes of a wave read and
+// write consecutive floats (six fully coalesced 256-byte accesses per wave
+// each way).  Along x the cells of one (y, z) row of the stencil are adjacent
+// keys, so each row is one contiguous range of the sorted LR copy.
+#include "kernels.hpp"
+
+namespace ups {
+namespace {
+
+struct Sums {
+  float S, Ux, Uy, Uz, M;
+  bool gran;
+  uint32_t count;
+};
+
+// Walk the stencil of HR position (x, y, z); accumulate members (float32
+// predicate s < h2).  DEBUG also records member ids.
+template <bool DEBUG>
+__device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __restrict__ lr,
+                                       const uint32_t* __restrict__ cell_start, float x, float y,
+                                       float z, uint32_t* ids, int64_t max_k) {
+  Sums r{0.f, 0.f, 0.f, 0.f, 0.f, false, 0u};
+  const int R = gc.reach;
+  const int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
+  const int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
+  const int cz = cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2]);
+  const int x0 = max(cx - R, 0), x1 = min(cx + R, gc.dims[0] - 1);
+  const int y0 = max(cy - R, 0), y1 = min(cy + R, gc.dims[1] - 1);
+  const int z0 = max(cz - R, 0), z1 = min(cz + R, gc.dims[2] - 1);
+  for (int zz = z0; zz <= z1; ++zz) {
+    for (int yy = y0; yy <= y1; ++yy) {
+      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
+      const uint32_t b = cell_start[row + (uint32_t)x0];
+      const uint32_t e = cell_start[row + (uint32_t)x1 + 1u];
+      for (uint32_t j = b; j < e; ++j) {
+        const float4 P = lr[j].p;
+        const float s = sq_dist(P.x, P.y, P.z, x, y, z);
+        if (s < gc.h2) {
+          const float4 V = lr[j].v;
+          const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
+          const float w = t * t * t;
+          r.S += w;
+          r.Ux = fmaf(w, V.x, r.Ux);
+          r.Uy = fmaf(w, V.y, r.Uy);
+          r.Uz = fmaf(w, V.z, r.Uz);
+          r.M = fmaxf(r.M, w);
+          r.gran |= (P.w == 0.0f);
+          if (DEBUG) {
+            if (ids != nullptr && (int64_t)r.count < max_k) ids[r.count] = __float_as_uint(V.w);
+          }
+          r.count += 1u;
+        }
+      }
+    }
+  }
+  // Rigid LR particles count only next to a granular one (Section 4).
+  if (!r.gran) {
+    r.S = 0.f;
+    r.Ux = r.Uy = r.Uz = 0.f;
+    r.M = 0.f;
+  }
+  return r;
+}
+
+__device__ __forceinline__ void apply_walls(const WallTable& wt, int n_walls, float r_hr, float ox,
+                                            float oy, float oz, float& x, float& y, float& z,
+                                            float& vx, float& vy, float& vz) {
+  for (int k = 0; k < n_walls; ++k) {
+    const float* w = &wt.w[k * UPSAMPLE_WALL_FLOATS];
+    const float nx = w[0], ny = w[1], nz = w[2], d = w[3];
+    const float ax = w[4], ay = w[5], az = w[6], b = w[7];
+    const float px = w[8], py = w[9], pz = w[10], R = w[11];
+    bool act = fmaf(az, z, fmaf(ay, y, ax * x)) >= b;
+    if (R > 0.0f) {
+      const float rx = x - px, ry = y - py, rz = z - pz;
+      const float rn = fmaf(nz, rz, fmaf(ny, ry, nx * rx));
+      const float ix = fmaf(-rn, nx, rx), iy = fmaf(-rn, ny, ry), iz = fmaf(-rn, nz, rz);
+      act = act && (sqrtf(fmaf(iz, iz, fmaf(iy, iy, ix * ix))) >= R);
+    }
+    act = act && (fmaf(nz, oz, fmaf(ny, oy, nx * ox)) - d >= 0.0f);
+    const float pen = fmaf(nz, z, fmaf(ny, y, nx * x)) - d;
+    if (act && pen < r_hr) {
+      const float push = r_hr - pen;
+      x = fmaf(push, nx, x);
+      y = fmaf(push, ny, y);
+      z = fmaf(push, nz, z);
+      const float vn = fmaf(nz, vz, fmaf(ny, vy, nx * vx));
+      if (vn < 0.0f) {
+        vx = fmaf(-vn, nx, vx);
+        vy = fmaf(-vn, ny, vy);
+        vz = fmaf(-vn, nz, vz);
+      }
+    }
+  }
+}
+
+template <bool DEBUG>
+__global__ __launch_bounds__(kBlock) void k_advance(AdvanceArgs a, WallTable wt) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t n = a.n;
+  const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
+  const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
+
+  uint32_t* ids = (DEBUG && a.dbg_ids != nullptr) ? a.dbg_ids + i * a.dbg_max_k : nullptr;
+  const Sums s = gather<DEBUG>(a.gc, a.lr, a.cell_start, x, y, z, ids, a.dbg_max_k);
+
+  // Shepard average and blend parameter (Section 4); empty support -> v~ = 0, alpha = 1.
+  float tx = 0.f, ty = 0.f, tz = 0.f;
+  bool A = true;
+  if (s.S > 0.0f) {
+    tx = s.Ux / s.S;
+    ty = s.Uy / s.S;
+    tz = s.Uz / s.S;
+    A = (s.M <= a.sc.c1) || (s.M / s.S >= a.sc.c2);
+  }
+  const float alpha = A ? 1.0f - s.M : 0.0f;
+  const float dt = a.sc.dt;
+  const float fx = fmaf(dt, a.sc.g[0], vx), fy = fmaf(dt, a.sc.g[1], vy), fz = fmaf(dt, a.sc.g[2], vz);
+  float nvx = fmaf(alpha, fx - tx, tx), nvy = fmaf(alpha, fy - ty, ty), nvz = fmaf(alpha, fz - tz, tz);
+  float nx = fmaf(dt, nvx, x), ny = fmaf(dt, nvy, y), nz = fmaf(dt, nvz, z);
+  apply_walls(wt, a.sc.n_walls, a.sc.r_hr, x, y, z, nx, ny, nz, nvx, nvy, nvz);
+
+  a.hx_out[i] = nx;
+  a.hx_out[n + i] = ny;
+  a.hx_out[2 * n + i] = nz;
+  a.hv_out[i] = nvx;
+  a.hv_out[n + i] = nvy;
+  a.hv_out[2 * n + i] = nvz;
+  if (DEBUG) {
+    if (a.dbg_count != nullptr) a.dbg_count[i] = s.count;
+    if (a.dbg_branch != nullptr)
+      a.dbg_branch[i] = (uint8_t)((A ? 1 : 0) | (s.gran ? 2 : 0) | (s.S > 0.0f ? 4 : 0));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool debug, hipStream_t st) {
+  if (a.n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((a.n + kBlock - 1) / kBlock);
+  if (debug)
+    hipLaunchKernelGGL(k_advance<true>, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  else
+    hipLaunchKernelGGL(k_advance<false>, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  return hipGetLastError();
+}
+
+}  // namespace ups

@@ -1,0 +1,261 @@
+// Uniform-grid rebuild of the LR guide particles: the neighbour search the
+// paper runs with a compact-hashing library (Section 5.1), as four streaming
+// kernels over structure-of-arrays input:
+//
+//   k_keys_count  cell key per LR particle, per-cell counts by atomic add
+//                 (the returned old count is the particle's arrival slot)
+//   k_scan_cells  exclusive scan of the counts in 2048-cell chunks; the last
+//                 block to finish scans the chunk totals; counts are re-zeroed
+//   k_scatter     cell_start[] and an arrival-order placement per cell
+//   k_stable      rank inside the cell by original index (stable order), then
+//                 writes perm[] and the LR copy in sorted order (32 B / particle)
+//
+// The same key / count / scan machinery reorders HR particles by cell.
+#include "kernels.hpp"
+
+namespace ups {
+namespace {
+
+__device__ __forceinline__ uint32_t cell_key(const GridConst& gc, float x, float y, float z) {
+  int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
+  int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
+  int cz = cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2]);
+  return (uint32_t)cx + (uint32_t)gc.dims[0] * ((uint32_t)cy + (uint32_t)gc.dims[1] * (uint32_t)cz);
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys_count(GridConst gc, const float* __restrict__ x,
+                                                       int64_t n, uint32_t* __restrict__ keys,
+                                                       uint32_t* __restrict__ slot,
+                                                       uint32_t* __restrict__ counts) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  uint32_t k = cell_key(gc, x[i], x[n + i], x[2 * n + i]);
+  keys[i] = k;
+  slot[i] = atomicAdd(&counts[k], 1u);
+}
+
+// Inclusive wave64 scan with ds_swizzle-free shuffles.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive block scan of one value per thread; *total receives the block sum.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    uint32_t s = wsum[w];
+    off += (w < wid) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_cells(uint32_t* __restrict__ counts, int64_t n_cells,
+                                                       uint32_t* __restrict__ local,
+                                                       uint32_t* chunk_sum, uint32_t* ticket,
+                                                       int n_chunks) {
+  __shared__ int is_last;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint32_t ex[kScanItems];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t c = base + k;
+    uint32_t v = 0;
+    if (c < n_cells) {
+      v = counts[c];
+      counts[c] = 0u;  // ready for the next build
+    }
+    ex[k] = sum;
+    sum += v;
+  }
+  uint32_t total;
+  uint32_t off = block_exclusive_scan(sum, &total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t c = base + k;
+    if (c < n_cells) local[c] = ex[k] + off;
+  }
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&chunk_sum[blockIdx.x], total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  // Last block: every chunk total is published; scan them in tiles of kBlock.
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < n_chunks; b0 += kBlock) {
+    int b = b0 + (int)threadIdx.x;
+    uint32_t v = (b < n_chunks)
+                     ? __hip_atomic_load(&chunk_sum[b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                     : 0u;
+    uint32_t tile;
+    uint32_t e = block_exclusive_scan(v, &tile);
+    if (b < n_chunks) chunk_sum[b] = carry + e;
+    carry += tile;
+  }
+  if (threadIdx.x == 0) {
+    chunk_sum[n_chunks] = carry;
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ uint32_t cell_offset(const uint32_t* local, const uint32_t* chunk_sum,
+                                                uint32_t k) {
+  return local[k] + chunk_sum[k / (uint32_t)kScanChunk];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ slot, int64_t n,
+                                                    const uint32_t* __restrict__ local,
+                                                    const uint32_t* __restrict__ chunk_sum,
+                                                    int64_t n_cells, int n_chunks,
+                                                    uint32_t* __restrict__ tmp,
+                                                    uint32_t* __restrict__ cell_start) {
+  int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n_cells) cell_start[t] = cell_offset(local, chunk_sum, (uint32_t)t);
+  if (t == n_cells) cell_start[t] = chunk_sum[n_chunks];
+  if (t < n) {
+    const uint32_t pos = cell_offset(local, chunk_sum, keys[t]) + slot[t];
+    if (pos < (uint64_t)n) tmp[pos] = (uint32_t)t;  // always true when counts started at zero
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ tmp,
+                                                   const uint32_t* __restrict__ keys,
+                                                   const uint32_t* __restrict__ cell_start, int64_t n,
+                                                   const float* __restrict__ x,
+                                                   const float* __restrict__ v,
+                                                   const uint8_t* __restrict__ rigid,
+                                                   uint32_t* __restrict__ perm,
+                                                   LRPoint* __restrict__ out) {
+  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t i = tmp[p];
+  if (i >= (uint64_t)n) return;  // defensive: tmp is a permutation of [0, n)
+  const uint32_t k = keys[i];
+  const uint32_t b = cell_start[k], e = cell_start[k + 1];
+  if (e > (uint64_t)n || b > e) return;
+  uint32_t rank = 0;
+  for (uint32_t q = b; q < e; ++q) rank += (tmp[q] < i) ? 1u : 0u;
+  const uint32_t dst = b + rank;
+  if (dst >= e) return;
+  perm[dst] = i;
+  float flag = (rigid != nullptr && rigid[i] != 0) ? 1.0f : 0.0f;
+  LRPoint o;
+  o.p = make_float4(x[i], x[n + i], x[2 * n + i], flag);
+  o.v = make_float4(v[i], v[n + i], v[2 * n + i], __uint_as_float(i));
+  out[dst] = o;
+}
+
+// HR reorder: scatter (x, v) by cell into scratch, remember the old index.
+__global__ __launch_bounds__(kBlock) void k_hr_scatter(const uint32_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ slot, int64_t n,
+                                                       const uint32_t* __restrict__ local,
+                                                       const uint32_t* __restrict__ chunk_sum,
+                                                       const float* __restrict__ x,
+                                                       const float* __restrict__ v,
+                                                       float* __restrict__ xs, float* __restrict__ vs,
+                                                       int32_t* __restrict__ perm) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t dst = cell_offset(local, chunk_sum, keys[i]) + slot[i];
+  if (dst >= (uint64_t)n) return;  // defensive: counts started at zero
+  perm[dst] = (int32_t)i;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    xs[a * n + dst] = x[a * n + i];
+    vs[a * n + dst] = v[a * n + i];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_back(const float* __restrict__ xs,
+                                                      const float* __restrict__ vs,
+                                                      const int32_t* __restrict__ perm, int64_t n,
+                                                      float* __restrict__ x, float* __restrict__ v,
+                                                      int32_t* __restrict__ perm_out) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    x[a * n + i] = xs[a * n + i];
+    v[a * n + i] = vs[a * n + i];
+  }
+  if (perm_out != nullptr) perm_out[i] = perm[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_finite(const float* __restrict__ p, int64_t n,
+                                                         uint32_t* flag) {
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && !isfinite(p[i])) atomicOr(flag, 1u);
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t keys_and_scan(const GridConst& gc, const float* x, int64_t n, int64_t n_cells,
+                         uint32_t* keys, uint32_t* slot, const GridScratch& s, hipStream_t st) {
+  if (n > 0) {
+    hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n)), dim3(kBlock), 0, st, gc, x, n, keys, slot,
+                       s.counts);
+  }
+  int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(k_scan_cells, dim3(n_chunks), dim3(kBlock), 0, st, s.counts, n_cells, s.local,
+                     s.chunk_sum, s.ticket, n_chunks);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float* lr_v,
+                             const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
+                             const GridScratch& s, hipStream_t st) {
+  hipError_t e = keys_and_scan(gc, lr_x, n_lr, n_cells, s.keys, s.slot, s, st);
+  if (e != hipSuccess) return e;
+  int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);
+  int64_t span = n_lr > n_cells + 1 ? n_lr : n_cells + 1;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, n_lr,
+                     s.local, s.chunk_sum, n_cells, n_chunks, s.tmp, s.cell_start);
+  if (n_lr > 0) {
+    hipLaunchKernelGGL(k_stable, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, s.tmp, s.keys,
+                       s.cell_start, n_lr, lr_x, lr_v, lr_rigid, s.perm, s.lr_sorted);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_hr(const GridConst& gc, float* hr_x, float* hr_v, int64_t n_hr,
+                          int64_t n_cells, const GridScratch& g, const HRSortScratch& s,
+                          int32_t* perm_out, hipStream_t st) {
+  if (n_hr == 0) return hipSuccess;
+  // Reuses the grid's counts / local / chunk_sum; cell_start and the sorted LR
+  // copy of the last build are left untouched.
+  hipError_t e = keys_and_scan(gc, hr_x, n_hr, n_cells, s.keys, s.slot, g, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hr_scatter, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.keys, s.slot, n_hr,
+                     g.local, g.chunk_sum, hr_x, hr_v, s.x, s.v, s.perm);
+  hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.x, s.v, s.perm, n_hr,
+                     hr_x, hr_v, perm_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float* p, int64_t n, uint32_t* flag, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n)), dim3(kBlock), 0, st, p, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace ups

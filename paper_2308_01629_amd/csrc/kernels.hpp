@@ -1,0 +1,80 @@
+// Host-side launchers of the library's kernels (one translation unit each).
+#pragma once
+
+#include "common.hpp"
+
+namespace ups {
+
+// Scratch of one grid build (device pointers, owned by a handle).
+struct GridScratch {
+  uint32_t* keys;        // [max_lr] cell key per LR (original order)
+  uint32_t* slot;        // [max_lr] arrival slot inside the cell (unstable)
+  uint32_t* tmp;         // [max_lr] unstable cell order
+  uint32_t* perm;        // [max_lr] stable cell order: original index per sorted slot
+  uint32_t* counts;      // [n_cells] per-cell count; zero between builds
+  uint32_t* local;       // [n_cells] exclusive scan inside each scan chunk
+  uint32_t* chunk_sum;   // [n_chunks + 1] chunk totals, then exclusive chunk offsets
+  uint32_t* ticket;      // [1] arrival counter of the scan's last-block step
+  uint32_t* cell_start;  // [n_cells + 1]
+  LRPoint* lr_sorted;    // [max_lr]
+};
+
+// a2..a5: keys + counts, chunked scan, unstable scatter, stable fix + LR reorder.
+hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float* lr_v,
+                             const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
+                             const GridScratch& s, hipStream_t st);
+
+// HR reorder by cell (keys, counts, scan, scatter, gather-copy).
+struct HRSortScratch {
+  uint32_t* keys;    // [max_hr]
+  uint32_t* slot;    // [max_hr]
+  float* x;          // [3][max_hr]
+  float* v;          // [3][max_hr]
+  int32_t* perm;     // [max_hr]
+};
+hipError_t launch_sort_hr(const GridConst& gc, float* hr_x, float* hr_v, int64_t n_hr,
+                          int64_t n_cells, const GridScratch& g, const HRSortScratch& s,
+                          int32_t* perm_out, hipStream_t st);
+
+// a6: fused gather + blend + integrate + walls.
+struct AdvanceArgs {
+  GridConst gc;
+  StepConst sc;
+  const LRPoint* lr;
+  const uint32_t* cell_start;
+  const float* hx;
+  const float* hv;
+  float* hx_out;
+  float* hv_out;
+  int64_t n;
+  // debug outputs (all may be null)
+  uint32_t* dbg_count;
+  uint32_t* dbg_ids;
+  int64_t dbg_max_k;
+  uint8_t* dbg_branch;
+};
+hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool debug, hipStream_t st);
+
+// a7: adjoint step.
+struct AdjointArgs {
+  GridConst gc;
+  StepConst sc;
+  const LRPoint* lr;
+  const uint32_t* cell_start;
+  const float* hx;
+  const float* hv;
+  const float* gx_out;
+  const float* gv_out;
+  float* gx_in;
+  float* gv_in;
+  float* g_lr_x;
+  float* g_lr_v;
+  int64_t n;
+  int64_t n_lr;
+};
+hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st);
+
+// VALIDATE flag: sets *flag to 1 if any of the n floats is NaN or Inf.
+hipError_t launch_check_finite(const float* p, int64_t n, uint32_t* flag, hipStream_t st);
+
+}  // namespace ups

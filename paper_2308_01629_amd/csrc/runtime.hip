@@ -1,0 +1,544 @@
+// Host runtime of the upsampling library: parameter validation, the grid
+// definition, the handle and its scratch, and the extern "C" entry points
+// declared in include/upsample.h.  No C++ exception crosses the ABI.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.hpp"
+
+using namespace ups;
+
+static constexpr int kTimingRing = 256;
+
+struct upsample_handle_s {
+  upsample_params p;
+  float walls[UPSAMPLE_MAX_WALLS * UPSAMPLE_WALL_FLOATS];
+  upsample_grid_info gi;
+  int device;
+  int64_t n_cells;
+  int n_chunks;
+  GridScratch g;
+  HRSortScratch hs;
+  uint32_t* finite_flag;
+  bool grid_valid;
+  bool counts_dirty;  // an interrupted build may have left counts non-zero
+  int64_t grid_n_lr;
+  bool has_rigid;
+  bool timing;
+  hipEvent_t ev[2 * kTimingRing];  // start/stop pairs, reused round-robin
+  int64_t timed_issued;            // pairs recorded since the last read
+  int64_t timed_folded;            // pairs already summed into timed_ms
+  double timed_ms;
+  std::string last_error;
+};
+
+namespace {
+
+int fail(upsample_handle h, int code, const std::string& msg) {
+  if (h != nullptr) h->last_error = msg;
+  return code;
+}
+
+int hip_fail(upsample_handle h, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(h, UPSAMPLE_ERR_HIP, m);
+}
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// The grid definition (see upsample_grid_info in the header).
+int compute_grid(const upsample_params* p, upsample_grid_info* gi, std::string* why) {
+  const double r = (double)p->r_lr;
+  const float kf = p->cell_factor > 0.0f ? p->cell_factor : UPSAMPLE_DEFAULT_CELL_FACTOR;
+  const double kappa = (double)kf;
+  const double h = 3.0 * r;
+  const double cs = kappa * h;
+  int64_t n = 1;
+  int gmax = 1;
+  for (int a = 0; a < 3; ++a) {
+    const double ext = ((double)p->domain_hi[a] - (double)p->domain_lo[a]) / cs;
+    if (!(ext < 1048576.0)) {
+      *why = "grid axis exceeds 2^20 cells";
+      return UPSAMPLE_ERR_GRID_TOO_LARGE;
+    }
+    int d = (int)std::ceil(ext);
+    if (d < 1) d = 1;
+    gi->dims[a] = d;
+    gi->lo[a] = p->domain_lo[a];
+    if (d > gmax) gmax = d;
+    n *= d;
+  }
+  if (n >= (int64_t)1 << 31) {
+    *why = "grid has 2^31 cells or more";
+    return UPSAMPLE_ERR_GRID_TOO_LARGE;
+  }
+  const double reach = std::ceil(h / cs + 16.0 * gmax * std::ldexp(1.0, -24));
+  if (reach > 64.0) {
+    *why = "cell_factor too small: stencil reach above 64 cells";
+    return UPSAMPLE_ERR_INVALID_ARG;
+  }
+  gi->reach = (int)reach;
+  gi->n_cells = n;
+  gi->cell_size = cs;
+  gi->inv_cell_size = (float)(1.0 / cs);
+  gi->h2 = (float)(9.0 * r * r);
+  gi->inv_h2 = (float)(1.0 / (9.0 * r * r));
+  return UPSAMPLE_OK;
+}
+
+int validate_params(const upsample_params* p, std::string* why) {
+  if (p == nullptr) {
+    *why = "params is NULL";
+    return UPSAMPLE_ERR_INVALID_ARG;
+  }
+  if (!(std::isfinite(p->r_lr) && p->r_lr > 0.0f)) { *why = "r_lr must be finite and > 0"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (!(std::isfinite(p->r_hr) && p->r_hr >= 0.0f)) { *why = "r_hr must be finite and >= 0"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (!(std::isfinite(p->dt) && p->dt >= 0.0f)) { *why = "dt must be finite and >= 0"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (!finite3(p->g)) { *why = "g must be finite"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (!(std::isfinite(p->c1) && std::isfinite(p->c2))) { *why = "c1, c2 must be finite"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (!finite3(p->domain_lo) || !finite3(p->domain_hi)) { *why = "domain must be finite"; return UPSAMPLE_ERR_INVALID_ARG; }
+  for (int a = 0; a < 3; ++a)
+    if (!(p->domain_hi[a] > p->domain_lo[a])) { *why = "domain_hi must exceed domain_lo"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (!(std::isfinite(p->cell_factor) && p->cell_factor >= 0.0f)) { *why = "cell_factor must be finite and >= 0"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (p->n_walls < 0 || p->n_walls > UPSAMPLE_MAX_WALLS) { *why = "n_walls must be in [0, 32]"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (p->n_walls > 0 && p->walls == nullptr) { *why = "walls is NULL"; return UPSAMPLE_ERR_INVALID_ARG; }
+  for (int k = 0; k < p->n_walls; ++k) {
+    const float* w = p->walls + k * UPSAMPLE_WALL_FLOATS;
+    for (int c = 0; c < UPSAMPLE_WALL_FLOATS; ++c) {
+      if (c == 7) continue;  // the clip offset may be a huge negative number
+      if (!std::isfinite(w[c])) { *why = "wall table must be finite"; return UPSAMPLE_ERR_INVALID_ARG; }
+    }
+    if (std::isnan(w[7])) { *why = "wall clip offset is NaN"; return UPSAMPLE_ERR_INVALID_ARG; }
+    if (w[11] < 0.0f) { *why = "wall hole radius must be >= 0"; return UPSAMPLE_ERR_INVALID_ARG; }
+    const double nn = (double)w[0] * w[0] + (double)w[1] * w[1] + (double)w[2] * w[2];
+    if (std::fabs(nn - 1.0) > 1e-4) { *why = "wall normal must be a unit vector"; return UPSAMPLE_ERR_INVALID_ARG; }
+  }
+  if (p->max_lr < 0 || p->max_hr < 0) { *why = "capacities must be >= 0"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if (p->max_lr >= ((int64_t)1 << 31) || p->max_hr >= ((int64_t)1 << 31)) {
+    *why = "capacities must be below 2^31";
+    return UPSAMPLE_ERR_INVALID_ARG;
+  }
+  if ((p->flags & ~UPSAMPLE_FLAG_VALIDATE) != 0u) { *why = "unknown flag bits"; return UPSAMPLE_ERR_INVALID_ARG; }
+  upsample_grid_info gi;
+  return compute_grid(p, &gi, why);
+}
+
+template <typename T>
+hipError_t dmalloc(T** p, int64_t count) {
+  size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+  return hipMalloc((void**)p, bytes);
+}
+
+void free_scratch(upsample_handle h) {
+  void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
+                  h->g.ticket, h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.x,
+                  h->hs.v, h->hs.perm, h->finite_flag};
+  for (void* q : ptrs)
+    if (q != nullptr) (void)hipFree(q);
+}
+
+GridConst grid_const(const upsample_handle h) {
+  GridConst gc;
+  for (int a = 0; a < 3; ++a) {
+    gc.lo[a] = h->gi.lo[a];
+    gc.dims[a] = h->gi.dims[a];
+  }
+  gc.inv_cs = h->gi.inv_cell_size;
+  gc.reach = h->gi.reach;
+  gc.h2 = h->gi.h2;
+  gc.inv_h2 = h->gi.inv_h2;
+  return gc;
+}
+
+StepConst step_const(const upsample_handle h) {
+  StepConst sc;
+  sc.c1 = h->p.c1;
+  sc.c2 = h->p.c2;
+  sc.dt = h->p.dt;
+  sc.r_hr = h->p.r_hr;
+  for (int a = 0; a < 3; ++a) sc.g[a] = h->p.g[a];
+  sc.n_walls = h->p.n_walls;
+  sc.has_rigid = h->has_rigid ? 1 : 0;
+  return sc;
+}
+
+WallTable wall_table(const upsample_handle h) {
+  WallTable wt;
+  std::memset(&wt, 0, sizeof(wt));
+  std::memcpy(wt.w, h->walls, sizeof(float) * UPSAMPLE_WALL_FLOATS * h->p.n_walls);
+  return wt;
+}
+
+int check_device(upsample_handle h) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != h->device)
+    return fail(h, UPSAMPLE_ERR_STATE, "the current HIP device is not the handle's device");
+  return UPSAMPLE_OK;
+}
+
+int validate_finite(upsample_handle h, hipStream_t st, const float* const* arrays, const int64_t* sizes,
+                    int count) {
+  if ((h->p.flags & UPSAMPLE_FLAG_VALIDATE) == 0u) return UPSAMPLE_OK;
+  hipError_t e = hipMemsetAsync(h->finite_flag, 0, sizeof(uint32_t), st);
+  if (e != hipSuccess) return hip_fail(h, e, "validate");
+  for (int k = 0; k < count; ++k) {
+    e = launch_check_finite(arrays[k], sizes[k], h->finite_flag, st);
+    if (e != hipSuccess) return hip_fail(h, e, "validate");
+  }
+  uint32_t flag = 0;
+  e = hipMemcpyAsync(&flag, h->finite_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(h, e, "validate");
+  if (flag != 0u) return fail(h, UPSAMPLE_ERR_NONFINITE, "non-finite value in the inputs");
+  return UPSAMPLE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int upsample_default_params(upsample_params* p) {
+  if (p == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->r_lr = 0.02f;
+  p->r_hr = 0.005f;
+  p->dt = 1.0f / 60.0f;
+  p->g[1] = -9.81f;
+  p->c1 = 512.0f / 729.0f;
+  p->c2 = 0.6f;
+  for (int a = 0; a < 3; ++a) {
+    p->domain_lo[a] = 0.0f;
+    p->domain_hi[a] = 1.0f;
+  }
+  p->cell_factor = 0.0f;
+  return UPSAMPLE_OK;
+}
+
+const char* upsample_strerror(int code) {
+  switch (code) {
+    case UPSAMPLE_OK: return "ok";
+    case UPSAMPLE_ERR_INVALID_ARG: return "invalid argument";
+    case UPSAMPLE_ERR_CAPACITY: return "particle count exceeds the handle's capacity";
+    case UPSAMPLE_ERR_GRID_TOO_LARGE: return "neighbour grid too large";
+    case UPSAMPLE_ERR_NO_DEVICE: return "no HIP device";
+    case UPSAMPLE_ERR_OOM: return "device allocation failed";
+    case UPSAMPLE_ERR_HIP: return "HIP runtime error";
+    case UPSAMPLE_ERR_NONFINITE: return "non-finite input";
+    case UPSAMPLE_ERR_STATE: return "call out of order";
+    default: return "unknown error code";
+  }
+}
+
+const char* upsample_last_error(upsample_handle h) {
+  if (h == nullptr) return "null handle";
+  return h->last_error.c_str();
+}
+
+int upsample_grid_info_for(const upsample_params* p, upsample_grid_info* out) {
+  if (out == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  std::string why;
+  int rc = validate_params(p, &why);
+  if (rc != UPSAMPLE_OK) return rc;
+  return compute_grid(p, out, &why);
+}
+
+int upsample_init(const upsample_params* p, upsample_handle* out) {
+  if (out == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  std::string why;
+  int rc = validate_params(p, &why);
+  if (rc != UPSAMPLE_OK) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return UPSAMPLE_ERR_NO_DEVICE;
+  upsample_handle h = new (std::nothrow) upsample_handle_s();
+  if (h == nullptr) return UPSAMPLE_ERR_OOM;
+  h->p = *p;
+  std::memset(h->walls, 0, sizeof(h->walls));
+  if (p->n_walls > 0) std::memcpy(h->walls, p->walls, sizeof(float) * UPSAMPLE_WALL_FLOATS * p->n_walls);
+  h->p.walls = nullptr;
+  compute_grid(&h->p, &h->gi, &why);
+  h->n_cells = h->gi.n_cells;
+  h->n_chunks = (int)((h->n_cells + kScanChunk - 1) / kScanChunk);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return UPSAMPLE_ERR_NO_DEVICE;
+  }
+  const int64_t nl = p->max_lr, nh = p->max_hr;
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, n) \
+  if (e == hipSuccess) e = dmalloc(&(ptr), (n));
+  ALLOC(h->g.keys, nl)
+  ALLOC(h->g.slot, nl)
+  ALLOC(h->g.tmp, nl)
+  ALLOC(h->g.perm, nl)
+  ALLOC(h->g.counts, h->n_cells)
+  ALLOC(h->g.local, h->n_cells)
+  ALLOC(h->g.chunk_sum, h->n_chunks + 1)
+  ALLOC(h->g.ticket, 1)
+  ALLOC(h->g.cell_start, h->n_cells + 1)
+  ALLOC(h->g.lr_sorted, nl)
+  ALLOC(h->hs.keys, nh)
+  ALLOC(h->hs.slot, nh)
+  ALLOC(h->hs.x, 3 * nh)
+  ALLOC(h->hs.v, 3 * nh)
+  ALLOC(h->hs.perm, nh)
+  ALLOC(h->finite_flag, 1)
+#undef ALLOC
+  if (e == hipSuccess) e = hipMemset(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells);
+  if (e == hipSuccess) e = hipMemset(h->g.ticket, 0, sizeof(uint32_t));
+  for (int k = 0; k < 2 * kTimingRing && e == hipSuccess; ++k) e = hipEventCreate(&h->ev[k]);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_scratch(h);
+    delete h;
+    return e == hipErrorOutOfMemory ? UPSAMPLE_ERR_OOM : UPSAMPLE_ERR_HIP;
+  }
+  *out = h;
+  return UPSAMPLE_OK;
+}
+
+int upsample_destroy(upsample_handle h) {
+  if (h == nullptr) return UPSAMPLE_OK;
+  free_scratch(h);
+  for (int k = 0; k < 2 * kTimingRing; ++k)
+    if (h->ev[k] != nullptr) (void)hipEventDestroy(h->ev[k]);
+  delete h;
+  return UPSAMPLE_OK;
+}
+
+int upsample_get_grid_info(upsample_handle h, upsample_grid_info* out) {
+  if (h == nullptr || out == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  *out = h->gi;
+  return UPSAMPLE_OK;
+}
+
+int upsample_build_grid(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                        int64_t n_lr, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_lr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_lr < 0");
+  if (n_lr > h->p.max_lr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_lr exceeds max_lr");
+  if (n_lr > 0 && (lr_x == nullptr || lr_v == nullptr))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "lr_x / lr_v is NULL");
+  int rc = check_device(h);
+  if (rc != UPSAMPLE_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const float* arrs[2] = {lr_x, lr_v};
+  const int64_t sizes[2] = {3 * n_lr, 3 * n_lr};
+  rc = validate_finite(h, st, arrs, sizes, 2);
+  if (rc != UPSAMPLE_OK) return rc;
+  hipError_t e = hipSuccess;
+  if (h->counts_dirty) {
+    e = hipMemsetAsync(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->g.ticket, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return hip_fail(h, e, "build_grid");
+    h->counts_dirty = false;
+  }
+  h->grid_valid = false;
+  e = launch_build_grid(grid_const(h), lr_x, lr_v, lr_rigid, n_lr, h->n_cells, h->g, st);
+  if (e != hipSuccess) {
+    h->counts_dirty = true;
+    return hip_fail(h, e, "build_grid");
+  }
+  h->grid_valid = true;
+  h->grid_n_lr = n_lr;
+  h->has_rigid = lr_rigid != nullptr;
+  return UPSAMPLE_OK;
+}
+
+// Sum the elapsed time of recorded pairs up to (not including) index `upto`.
+static hipError_t fold_timing(upsample_handle h, int64_t upto) {
+  while (h->timed_folded < upto) {
+    const int slot = (int)(h->timed_folded % kTimingRing);
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(h->ev[2 * slot + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev[2 * slot], h->ev[2 * slot + 1]);
+    if (e != hipSuccess) return e;
+    h->timed_ms += ms;
+    h->timed_folded += 1;
+  }
+  return hipSuccess;
+}
+
+static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
+                        float* hr_v_out, int64_t n_hr, void* stream, bool debug, uint32_t* count,
+                        uint32_t* ids, int64_t max_k, uint8_t* branch) {
+  if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
+  if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
+  if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr || hr_x_out == nullptr || hr_v_out == nullptr))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
+  if (max_k < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "max_k < 0");
+  if (!h->grid_valid) return fail(h, UPSAMPLE_ERR_STATE, "no LR grid built on this handle");
+  int rc = check_device(h);
+  if (rc != UPSAMPLE_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const float* arrs[2] = {hr_x, hr_v};
+  const int64_t sizes[2] = {3 * n_hr, 3 * n_hr};
+  rc = validate_finite(h, st, arrs, sizes, 2);
+  if (rc != UPSAMPLE_OK) return rc;
+  AdvanceArgs a;
+  a.gc = grid_const(h);
+  a.sc = step_const(h);
+  a.lr = h->g.lr_sorted;
+  a.cell_start = h->g.cell_start;
+  a.hx = hr_x;
+  a.hv = hr_v;
+  a.hx_out = hr_x_out;
+  a.hv_out = hr_v_out;
+  a.n = n_hr;
+  a.dbg_count = count;
+  a.dbg_ids = ids;
+  a.dbg_max_k = max_k;
+  a.dbg_branch = branch;
+  const bool timed = h->timing && !debug && n_hr > 0;
+  hipError_t e = hipSuccess;
+  int slot = 0;
+  if (timed) {
+    slot = (int)(h->timed_issued % kTimingRing);
+    if (h->timed_issued - h->timed_folded >= kTimingRing) {
+      e = fold_timing(h, h->timed_folded + 1);  // free the slot about to be reused
+      if (e != hipSuccess) return hip_fail(h, e, "timing");
+    }
+    e = hipEventRecord(h->ev[2 * slot], st);
+  }
+  if (e == hipSuccess) e = launch_advance(a, wall_table(h), debug, st);
+  if (e == hipSuccess && timed) e = hipEventRecord(h->ev[2 * slot + 1], st);
+  if (e != hipSuccess) return hip_fail(h, e, "advance");
+  if (timed) h->timed_issued += 1;
+  return UPSAMPLE_OK;
+}
+
+int upsample_advance(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
+                     float* hr_v_out, int64_t n_hr, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  return advance_impl(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream, false, nullptr, nullptr, 0,
+                      nullptr);
+}
+
+int upsample_step(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                  int64_t n_lr, const float* hr_x, const float* hr_v, float* hr_x_out, float* hr_v_out,
+                  int64_t n_hr, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
+  if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
+  if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr || hr_x_out == nullptr || hr_v_out == nullptr))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
+  int rc = upsample_build_grid(h, lr_x, lr_v, lr_rigid, n_lr, stream);
+  if (rc != UPSAMPLE_OK) return rc;
+  return upsample_advance(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream);
+}
+
+int upsample_step_backward(upsample_handle h, const float* lr_x, const float* lr_v,
+                           const uint8_t* lr_rigid, int64_t n_lr, const float* hr_x,
+                           const float* hr_v, int64_t n_hr, const float* gx_out,
+                           const float* gv_out, float* gx_in, float* gv_in, float* g_lr_x,
+                           float* g_lr_v, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
+  if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
+  if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr || gx_out == nullptr || gv_out == nullptr ||
+                   gx_in == nullptr || gv_in == nullptr))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
+  if (n_lr > 0 && n_hr > 0 && (g_lr_x == nullptr || g_lr_v == nullptr))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "LR gradient pointer is NULL");
+  int rc = upsample_build_grid(h, lr_x, lr_v, lr_rigid, n_lr, stream);
+  if (rc != UPSAMPLE_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const float* arrs[2] = {gx_out, gv_out};
+  const int64_t sizes[2] = {3 * n_hr, 3 * n_hr};
+  rc = validate_finite(h, st, arrs, sizes, 2);
+  if (rc != UPSAMPLE_OK) return rc;
+  AdjointArgs a;
+  a.gc = grid_const(h);
+  a.sc = step_const(h);
+  a.lr = h->g.lr_sorted;
+  a.cell_start = h->g.cell_start;
+  a.hx = hr_x;
+  a.hv = hr_v;
+  a.gx_out = gx_out;
+  a.gv_out = gv_out;
+  a.gx_in = gx_in;
+  a.gv_in = gv_in;
+  a.g_lr_x = g_lr_x;
+  a.g_lr_v = g_lr_v;
+  a.n = n_hr;
+  a.n_lr = n_lr;
+  hipError_t e = launch_adjoint(a, wall_table(h), st);
+  if (e != hipSuccess) return hip_fail(h, e, "step_backward");
+  return UPSAMPLE_OK;
+}
+
+int upsample_sort_hr(upsample_handle h, float* hr_x, float* hr_v, int64_t n_hr, int32_t* perm_out,
+                     void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
+  if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
+  if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
+  int rc = check_device(h);
+  if (rc != UPSAMPLE_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (h->counts_dirty) {
+    hipError_t e = hipMemsetAsync(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->g.ticket, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return hip_fail(h, e, "sort_hr");
+    h->counts_dirty = false;
+  }
+  hipError_t e = launch_sort_hr(grid_const(h), hr_x, hr_v, n_hr, h->n_cells, h->g, h->hs, perm_out, st);
+  if (e != hipSuccess) {
+    h->counts_dirty = true;
+    return hip_fail(h, e, "sort_hr");
+  }
+  return UPSAMPLE_OK;
+}
+
+int upsample_debug_grid(upsample_handle h, uint32_t* keys, uint32_t* perm, uint32_t* cell_start,
+                        void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (!h->grid_valid) return fail(h, UPSAMPLE_ERR_STATE, "no LR grid built on this handle");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  const size_t nl = (size_t)h->grid_n_lr * sizeof(uint32_t);
+  if (keys != nullptr && nl) e = hipMemcpyAsync(keys, h->g.keys, nl, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && perm != nullptr && nl)
+    e = hipMemcpyAsync(perm, h->g.perm, nl, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && cell_start != nullptr)
+    e = hipMemcpyAsync(cell_start, h->g.cell_start, sizeof(uint32_t) * (size_t)(h->n_cells + 1),
+                       hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(h, e, "debug_grid");
+  return UPSAMPLE_OK;
+}
+
+int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* hr_v, int64_t n_hr,
+                             uint32_t* count, uint32_t* ids, int64_t max_k, uint8_t* branch,
+                             void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_hr > 0 && ids != nullptr && max_k <= 0)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "ids needs max_k > 0");
+  // The debug walk writes the stepped state to the handle's HR sort scratch.
+  return advance_impl(h, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, stream, true, count, ids, max_k, branch);
+}
+
+int upsample_timing_enable(upsample_handle h, int enable) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  hipError_t e = fold_timing(h, h->timed_issued);
+  if (e != hipSuccess) return hip_fail(h, e, "timing");
+  h->timing = enable != 0;
+  h->timed_ms = 0.0;
+  h->timed_issued = h->timed_folded = 0;
+  return UPSAMPLE_OK;
+}
+
+int upsample_timing_read(upsample_handle h, double* advance_ms, int64_t* launches) {
+  if (h == nullptr || advance_ms == nullptr || launches == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  hipError_t e = fold_timing(h, h->timed_issued);
+  if (e != hipSuccess) return hip_fail(h, e, "timing");
+  *advance_ms = h->timed_ms;
+  *launches = h->timed_issued;
+  h->timed_ms = 0.0;
+  h->timed_issued = h->timed_folded = 0;
+  return UPSAMPLE_OK;
+}
+
+}  // extern "C"

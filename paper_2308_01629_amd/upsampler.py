@@ -1,0 +1,205 @@
+"""PyTorch-facing wrapper of the C ABI: device tensors in, device tensors out.
+
+Every array is a contiguous float32 CUDA (HIP) tensor of shape [3, n]
+(structure of arrays).  Calls are enqueued on torch's current stream.  This
+module only marshals arguments; all arithmetic runs in libupsample.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GridInfo, Params, check, lib
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _soa(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.shape[0] == 3
+            and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor of shape [3, n]")
+    return t
+
+
+def _u8(t: Optional[torch.Tensor], n: int, name: str) -> Optional[torch.Tensor]:
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.uint8 and t.dim() == 1 and t.shape[0] == n and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous uint8 device tensor of shape [{n}]")
+    return t
+
+
+def make_params(r_lr: float, r_hr: float, dt: float, g: Sequence[float], domain_lo, domain_hi,
+                walls=None, max_lr: int = 0, max_hr: int = 0, c1: float = 512.0 / 729.0,
+                c2: float = 0.6, cell_factor: float = 0.0, validate: bool = False):
+    """Params struct plus the host wall buffer that must outlive the call using it."""
+    p = Params()
+    lib().upsample_default_params(ctypes.byref(p))
+    p.r_lr, p.r_hr, p.dt = float(r_lr), float(r_hr), float(dt)
+    for a in range(3):
+        p.g[a] = float(g[a])
+        p.domain_lo[a] = float(domain_lo[a])
+        p.domain_hi[a] = float(domain_hi[a])
+    p.c1, p.c2 = float(c1), float(c2)
+    p.cell_factor = float(cell_factor)
+    wbuf = None
+    if walls is not None and len(walls):
+        wbuf = np.ascontiguousarray(np.asarray(walls, dtype=np.float32).reshape(-1, _lib.WALL_FLOATS))
+        p.n_walls = wbuf.shape[0]
+        p.walls = wbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    p.max_lr, p.max_hr = int(max_lr), int(max_hr)
+    p.flags = _lib.FLAG_VALIDATE if validate else 0
+    return p, wbuf
+
+
+def grid_info_for(**kw) -> dict:
+    """Host-only grid of a parameter set (no device needed)."""
+    p, _w = make_params(**kw)
+    gi = GridInfo()
+    check(lib().upsample_grid_info_for(ctypes.byref(p), ctypes.byref(gi)))
+    return gi.as_dict()
+
+
+class Upsampler:
+    """One handle of the library: a scene's parameters plus scratch for up to
+    ``max_lr`` LR and ``max_hr`` HR particles."""
+
+    def __init__(self, r_lr: float, r_hr: float, dt: float, g, domain_lo, domain_hi, walls=None,
+                 max_lr: int = 0, max_hr: int = 0, c1: float = 512.0 / 729.0, c2: float = 0.6,
+                 cell_factor: float = 0.0, validate: bool = False):
+        self._L = lib()
+        self.kw = dict(r_lr=r_lr, r_hr=r_hr, dt=dt, g=tuple(g), domain_lo=tuple(domain_lo),
+                       domain_hi=tuple(domain_hi), walls=walls, max_lr=max_lr, max_hr=max_hr, c1=c1,
+                       c2=c2, cell_factor=cell_factor, validate=validate)
+        p, _wbuf = make_params(**self.kw)
+        h = ctypes.c_void_p()
+        check(self._L.upsample_init(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self.max_lr, self.max_hr = int(max_lr), int(max_hr)
+
+    @classmethod
+    def from_scene(cls, scene, max_lr: Optional[int] = None, max_hr: Optional[int] = None, **kw):
+        return cls(scene.r_lr, scene.r_hr, scene.dt, scene.g, scene.domain_lo, scene.domain_hi,
+                   walls=scene.walls, max_lr=max_lr if max_lr is not None else scene.n_lr,
+                   max_hr=max_hr if max_hr is not None else scene.n_hr, c1=scene.c1, c2=scene.c2, **kw)
+
+    # -- plumbing
+    def _check(self, rc: int) -> None:
+        check(rc, self._h, self._L.upsample_last_error)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.upsample_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def grid_info(self) -> dict:
+        gi = GridInfo()
+        self._check(self._L.upsample_get_grid_info(self._h, ctypes.byref(gi)))
+        return gi.as_dict()
+
+    # -- the path
+    def build_grid(self, lr_x: torch.Tensor, lr_v: torch.Tensor, lr_rigid: Optional[torch.Tensor] = None):
+        n = _soa(lr_x, "lr_x").shape[1]
+        _soa(lr_v, "lr_v")
+        _u8(lr_rigid, n, "lr_rigid")
+        self._check(self._L.upsample_build_grid(self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), n,
+                                                _stream()))
+
+    def advance(self, hr_x, hr_v, out_x=None, out_v=None):
+        n = _soa(hr_x, "hr_x").shape[1]
+        _soa(hr_v, "hr_v")
+        out_x = torch.empty_like(hr_x) if out_x is None else _soa(out_x, "out_x")
+        out_v = torch.empty_like(hr_v) if out_v is None else _soa(out_v, "out_v")
+        self._check(self._L.upsample_advance(self._h, _ptr(hr_x), _ptr(hr_v), _ptr(out_x), _ptr(out_v),
+                                             n, _stream()))
+        return out_x, out_v
+
+    def step(self, lr_x, lr_v, lr_rigid, hr_x, hr_v, out_x=None, out_v=None):
+        nl = _soa(lr_x, "lr_x").shape[1]
+        _soa(lr_v, "lr_v")
+        _u8(lr_rigid, nl, "lr_rigid")
+        n = _soa(hr_x, "hr_x").shape[1]
+        _soa(hr_v, "hr_v")
+        out_x = torch.empty_like(hr_x) if out_x is None else _soa(out_x, "out_x")
+        out_v = torch.empty_like(hr_v) if out_v is None else _soa(out_v, "out_v")
+        self._check(self._L.upsample_step(self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl,
+                                          _ptr(hr_x), _ptr(hr_v), _ptr(out_x), _ptr(out_v), n,
+                                          _stream()))
+        return out_x, out_v
+
+    def step_backward(self, lr_x, lr_v, lr_rigid, hr_x, hr_v, gx_out, gv_out,
+                      g_lr_x=None, g_lr_v=None, gx_in=None, gv_in=None):
+        """Returns (gx_in, gv_in, g_lr_x, g_lr_v); LR gradients are ADDED into
+        g_lr_x / g_lr_v when given (zeros otherwise)."""
+        nl = _soa(lr_x, "lr_x").shape[1]
+        _soa(lr_v, "lr_v")
+        _u8(lr_rigid, nl, "lr_rigid")
+        n = _soa(hr_x, "hr_x").shape[1]
+        for t, nm in ((hr_v, "hr_v"), (gx_out, "gx_out"), (gv_out, "gv_out")):
+            _soa(t, nm)
+        g_lr_x = torch.zeros_like(lr_x) if g_lr_x is None else _soa(g_lr_x, "g_lr_x")
+        g_lr_v = torch.zeros_like(lr_v) if g_lr_v is None else _soa(g_lr_v, "g_lr_v")
+        gx_in = torch.empty_like(hr_x) if gx_in is None else _soa(gx_in, "gx_in")
+        gv_in = torch.empty_like(hr_v) if gv_in is None else _soa(gv_in, "gv_in")
+        self._check(self._L.upsample_step_backward(
+            self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl, _ptr(hr_x), _ptr(hr_v), n,
+            _ptr(gx_out), _ptr(gv_out), _ptr(gx_in), _ptr(gv_in), _ptr(g_lr_x), _ptr(g_lr_v), _stream()))
+        return gx_in, gv_in, g_lr_x, g_lr_v
+
+    def sort_hr(self, hr_x, hr_v, with_perm: bool = True):
+        """Reorders hr_x / hr_v in place by grid cell; returns the old index of
+        each new position (int32) or None."""
+        n = _soa(hr_x, "hr_x").shape[1]
+        _soa(hr_v, "hr_v")
+        perm = torch.empty(n, dtype=torch.int32, device=hr_x.device) if with_perm else None
+        self._check(self._L.upsample_sort_hr(self._h, _ptr(hr_x), _ptr(hr_v), n, _ptr(perm), _stream()))
+        return perm
+
+    # -- debug exports
+    def debug_grid(self, n_lr: int, device="cuda"):
+        info = self.grid_info()
+        keys = torch.empty(n_lr, dtype=torch.int32, device=device)
+        perm = torch.empty(n_lr, dtype=torch.int32, device=device)
+        cs = torch.empty(info["n_cells"] + 1, dtype=torch.int32, device=device)
+        self._check(self._L.upsample_debug_grid(self._h, _ptr(keys), _ptr(perm), _ptr(cs), _stream()))
+        return keys, perm, cs
+
+    def debug_neighbors(self, hr_x, hr_v, max_k: int = 64):
+        n = _soa(hr_x, "hr_x").shape[1]
+        _soa(hr_v, "hr_v")
+        count = torch.empty(n, dtype=torch.int32, device=hr_x.device)
+        ids = torch.full((n, max_k), -1, dtype=torch.int32, device=hr_x.device)
+        branch = torch.empty(n, dtype=torch.uint8, device=hr_x.device)
+        self._check(self._L.upsample_debug_neighbors(self._h, _ptr(hr_x), _ptr(hr_v), n, _ptr(count),
+                                                     _ptr(ids), max_k, _ptr(branch), _stream()))
+        return count, ids, branch
+
+    # -- kernel timing probe
+    def timing_enable(self, enable: bool = True) -> None:
+        self._check(self._L.upsample_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_read(self):
+        ms = ctypes.c_double()
+        k = ctypes.c_int64()
+        self._check(self._L.upsample_timing_read(self._h, ctypes.byref(ms), ctypes.byref(k)))
+        return float(ms.value), int(k.value)

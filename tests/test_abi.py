@@ -1,0 +1,122 @@
+"""The C ABI on the host (no GPU): the library loads, exports every symbol the
+header declares, validates arguments before touching a device, and computes
+the grid exactly as the oracle defines it."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import upsample_oracle as O
+from paper_2308_01629_amd import _lib
+from paper_2308_01629_amd.upsampler import grid_info_for, make_params
+from workloads import configs
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "upsample.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(upsample_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _declared()
+    assert "upsample_step" in names and "upsample_step_backward" in names and "upsample_init" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding describes every declared function
+    assert set(names) <= set(_lib.SIGNATURES), set(names) - set(_lib.SIGNATURES)
+
+
+def _params(**over):
+    kw = dict(r_lr=0.02, r_hr=0.005, dt=1 / 60, g=(0, -9.81, 0), domain_lo=(0, 0, 0),
+              domain_hi=(1, 1, 1), max_lr=16, max_hr=16)
+    kw.update(over)
+    return make_params(**kw)
+
+
+def _init(p):
+    h = ctypes.c_void_p()
+    rc = _lib.lib().upsample_init(ctypes.byref(p), ctypes.byref(h))
+    return rc, h
+
+
+def _no_gpu():
+    try:
+        import torch
+        return not torch.cuda.is_available()
+    except Exception:
+        return True
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("r_lr", 0.0, "INVALID_ARG"), ("r_lr", float("nan"), "INVALID_ARG"), ("r_hr", -1.0, "INVALID_ARG"),
+    ("dt", float("inf"), "INVALID_ARG"), ("cell_factor", -1.0, "INVALID_ARG"),
+    ("cell_factor", 1e-4, "GRID_TOO_LARGE"), ("max_lr", -1, "INVALID_ARG"),
+])
+def test_invalid_params_rejected_before_device(field, value, code):
+    p, _w = _params()
+    setattr(p, field, value)
+    rc, _ = _init(p)
+    assert rc == _lib.ERR_CODES["UPSAMPLE_ERR_" + code]
+    gi = _lib.GridInfo()
+    assert _lib.lib().upsample_grid_info_for(ctypes.byref(p), ctypes.byref(gi)) == rc
+
+
+def test_bad_domain_walls_and_grid_size():
+    L = _lib.lib()
+    p, _w = _params(domain_lo=(0, 1, 0), domain_hi=(1, 1, 1))
+    assert _init(p)[0] == _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+    p, _w = _params(r_lr=1e-4, domain_hi=(100, 100, 100))
+    assert _init(p)[0] == _lib.ERR_CODES["UPSAMPLE_ERR_GRID_TOO_LARGE"]
+    bad = np.zeros((1, 12), np.float32)
+    bad[0, :3] = (0, 2, 0)     # not a unit normal
+    p, _w = _params(walls=bad)
+    assert _init(p)[0] == _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+    p, _w = _params(walls=np.zeros((33, 12), np.float32))
+    assert _init(p)[0] == _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+    p, _w = _params(cell_factor=0.01, domain_hi=(0.1, 0.1, 0.1))   # stencil reach 100 > 64
+    assert _init(p)[0] == _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+    p, _w = _params()
+    p.flags = 0x80
+    assert _init(p)[0] == _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+    assert L.upsample_init(None, None) == _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+
+
+def test_null_handle_calls_rejected():
+    L = _lib.lib()
+    inv = _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+    assert L.upsample_step(None, None, None, None, 0, None, None, None, None, 0, None) == inv
+    assert L.upsample_build_grid(None, None, None, None, 0, None) == inv
+    assert L.upsample_advance(None, None, None, None, None, 0, None) == inv
+    assert L.upsample_step_backward(None, None, None, None, 0, None, None, 0, None, None, None, None,
+                                    None, None, None) == inv
+    assert L.upsample_sort_hr(None, None, None, 0, None, None) == inv
+    assert L.upsample_destroy(None) == 0
+    assert L.upsample_strerror(2).decode().startswith("particle count")
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="host without a GPU only")
+def test_valid_init_without_device_reports_no_device():
+    p, _w = _params()
+    assert _init(p)[0] == _lib.ERR_CODES["UPSAMPLE_ERR_NO_DEVICE"]
+
+
+@pytest.mark.parametrize("name", ["plain", "column", "drain", "diff"])
+@pytest.mark.parametrize("cell_factor", [0.0, 1.0, 0.5, 1.7])
+def test_host_grid_matches_oracle_definition(name, cell_factor):
+    g, nl, nh, r, _ = configs.WORKLOADS[name]
+    lo, hi = {"plain": ((0, 0, 0), (1, 1, 1)), "column": ((0, 0, 0), (2, 1.5, 2)),
+              "drain": ((0, 0, 0), (1, 2.4, 1)), "diff": ((0, 0, 0), (1, 1, 1))}[name]
+    gi = grid_info_for(r_lr=r, r_hr=r / 4, dt=1 / 60, g=(0, -9.81, 0), domain_lo=lo, domain_hi=hi,
+                       cell_factor=cell_factor)
+    spec = O.grid_spec(r, lo, hi, cell_factor)
+    assert gi["dims"] == spec.dims
+    assert gi["reach"] == spec.reach
+    assert gi["cell_size"] == spec.cs
+    assert np.float32(gi["inv_cell_size"]) == spec.inv_cs
+    assert np.float32(gi["h2"]) == spec.h2_f

@@ -1,0 +1,220 @@
+"""GPU parity of the upsampling step (grid rebuild + fused gather/blend/
+integrate/walls) against the CPU oracle, through the C ABI.
+
+Integer stages (cell keys, stable order, cell ranges, neighbour lists) must be
+bit-exact; positions and velocities must match per step within
+|dx| <= 1e-6 box lengths and |dv| <= 1e-5 max(|v|, 1 m/s) (tests/gpu_util.py),
+particles inside an alpha or wall decision band may match either branch.
+"""
+import numpy as np
+import pytest
+
+from oracle import upsample_oracle as O
+from workloads import configs
+from workloads.generators import build_scene
+
+from gpu_util import compare_step, dev, host, log
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def U():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_01629_amd.upsampler import Upsampler
+    return Upsampler
+
+
+def _grid_check(up, X, spec):
+    keys, perm, cs = up.debug_grid(X.shape[1])
+    torch.cuda.synchronize()
+    k_ref = O.cell_keys(X, spec)
+    p_ref, cs_ref = O.sort_by_cell(k_ref, spec.n_cells)
+    np.testing.assert_array_equal(host(keys).astype(np.uint32), k_ref)
+    np.testing.assert_array_equal(host(perm).astype(np.uint32), p_ref)
+    np.testing.assert_array_equal(host(cs).astype(np.uint32), cs_ref)
+
+
+def _neighbour_check(up, X, hr_x, hr_v, spec, idx, max_k=96):
+    count, ids, branch = up.debug_neighbors(dev(hr_x[:, idx], torch), dev(hr_v[:, idx], torch), max_k)
+    torch.cuda.synchronize()
+    ip, jj = O.neighbours_kdtree(X, hr_x[:, idx], spec.h, spec.h2_f)
+    c = host(count)
+    np.testing.assert_array_equal(c, np.diff(ip))
+    assert c.max() <= max_k
+    ids_h = host(ids)
+    for i in range(idx.size):
+        got = np.sort(ids_h[i, :c[i]])
+        np.testing.assert_array_equal(got, jj[ip[i]:ip[i + 1]])
+    return c
+
+
+@pytest.mark.parametrize("cell_factor", [0.0, 0.5, 1.6])
+def test_plain_grid_and_neighbours_bitexact(U, cell_factor):
+    sc = configs.plain()
+    X, V = sc.lr_frame(1)
+    up = U.from_scene(sc, cell_factor=cell_factor)
+    spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi, cell_factor)
+    assert up.grid_info()["dims"] == spec.dims and up.grid_info()["reach"] == spec.reach
+    up.build_grid(dev(X, torch), dev(V, torch), None)
+    _grid_check(up, X, spec)
+    idx = np.arange(sc.n_hr)
+    c = _neighbour_check(up, X, sc.hr_x0, sc.hr_v0, spec, idx)
+    log(f"plain kappa={cell_factor}: grid and {idx.size} neighbour lists bit-exact, mean {c.mean():.2f}")
+
+
+def test_plain_ten_steps_parity(U):
+    sc = configs.plain()
+    up = U.from_scene(sc)
+    prm = sc.params()
+    x = dev(sc.hr_x0, torch)
+    v = dev(sc.hr_v0, torch)
+    ox, ov = sc.hr_x0.astype(np.float64), sc.hr_v0.astype(np.float64)
+    excluded = np.zeros(sc.n_hr, bool)
+    for t in range(1, 11):
+        X, V = sc.lr_frame(t)
+        x, v = up.step(dev(X, torch), dev(V, torch), None, x, v)
+        torch.cuda.synchronize()
+        o = O.step(X, V, None, ox, ov, prm)
+        keep = np.nonzero(~excluded)[0]
+        sub = {k: (val[keep] if isinstance(val, np.ndarray) and val.shape[:1] == (sc.n_hr,) else val)
+               for k, val in o.items() if k not in ("x", "v")}
+        sub["x"], sub["v"] = o["x"][:, keep], o["v"][:, keep]
+        gx, gv = host(x), host(v)
+        # an independent rollout: tolerance grows with the number of steps taken
+        s = compare_step(gx, gv, X, V, None, ox, ov, prm, sc.box_length, n_steps=t, idx=keep, oracle_out=sub)
+        # particles that met a decision band may follow either branch from here on
+        excluded |= o["band"] | o["wall_band"].any(axis=1)
+        ox, ov = o["x"], o["v"]
+        log(f"plain step {t}: {s}, excluded so far {int(excluded.sum())}")
+    assert excluded.sum() <= 1e-3 * sc.n_hr
+
+
+def _sample(n, k, seed):
+    rng = np.random.default_rng(seed)
+    if n <= k:
+        return np.arange(n)
+    return np.sort(rng.choice(n, size=k, replace=False))
+
+
+@pytest.mark.parametrize("name", ["column", "drain", "diff"])
+def test_full_size_single_step_sampled(U, name):
+    sc = {"column": configs.column, "drain": configs.drain, "diff": configs.diff}[name]()
+    log(f"{name}: {sc.n_lr} LR, {sc.n_hr} HR")
+    up = U.from_scene(sc)
+    prm = sc.params()
+    spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
+    rng = np.random.default_rng(17)
+    hr_v = rng.normal(0, 0.5, sc.hr_x0.shape).astype(np.float32)
+    X, V = sc.lr_frame(3)
+    x_out, v_out = up.step(dev(X, torch), dev(V, torch), None, dev(sc.hr_x0, torch), dev(hr_v, torch))
+    torch.cuda.synchronize()
+    _grid_check(up, X, spec)
+    idx = _sample(sc.n_hr, 65536, 5)
+    s = compare_step(host(x_out), host(v_out), X, V, None, sc.hr_x0, hr_v, prm, sc.box_length, idx=idx)
+    log(f"{name} single step: {s}")
+    nidx = _sample(sc.n_hr, 4096, 6)
+    _neighbour_check(up, X, sc.hr_x0, hr_v, spec, nidx)
+
+
+def test_rigid_and_clamped_edge_cases(U):
+    # rigid floor samples, HR outside the grid box, ragged n, n_lr = 1
+    sc = build_scene("heap", 3000, 40001, seed=[11, 1], rigid_floor=True)
+    prm = sc.params()
+    X, V = sc.lr_frame(2)
+    rigid = sc.lr_rigid
+    rng = np.random.default_rng(3)
+    hr_x = sc.hr_x0.copy()
+    hr_x[:, :500] = rng.uniform(-0.3, 1.3, (3, 500)).astype(np.float32)     # outside the box
+    hr_x[1, 500:1500] = (X[1, -1] + rng.uniform(-0.01, 0.03, 1000)).astype(np.float32)  # near the rigid floor
+    hr_v = rng.normal(0, 1.0, hr_x.shape).astype(np.float32)
+    up = U.from_scene(sc, max_lr=X.shape[1])
+    x_out, v_out = up.step(dev(X, torch), dev(V, torch), dev(rigid, torch), dev(hr_x, torch), dev(hr_v, torch))
+    torch.cuda.synchronize()
+    s = compare_step(host(x_out), host(v_out), X, V, rigid, hr_x, hr_v, prm, sc.box_length)
+    spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
+    _grid_check(up, X, spec)
+    count, _, branch = up.debug_neighbors(dev(hr_x, torch), dev(hr_v, torch), 1)
+    o = O.step(X, V, rigid, hr_x, hr_v, prm)
+    ip, jj = O.neighbours_kdtree(X, hr_x, spec.h, spec.h2_f)
+    ii = np.repeat(np.arange(hr_x.shape[1]), np.diff(ip))
+    gran = np.bincount(ii, weights=(rigid[jj] == 0), minlength=hr_x.shape[1]) > 0
+    np.testing.assert_array_equal((host(branch) >> 1) & 1, gran.astype(np.uint8))
+    assert ((host(branch) & 1).astype(bool) == o["A"])[~o["band"]].all()
+    log(f"rigid/clamped: {s}, only-rigid HR: {int(((np.diff(ip) > 0) & ~gran).sum())}")
+    # one LR particle
+    x1, v1 = up.step(dev(X[:, :1].copy(), torch), dev(V[:, :1].copy(), torch), dev(rigid[:1].copy(), torch),
+                     dev(hr_x, torch), dev(hr_v, torch))
+    torch.cuda.synchronize()
+    compare_step(host(x1), host(v1), X[:, :1], V[:, :1], rigid[:1], hr_x, hr_v, prm, sc.box_length)
+
+
+def test_empty_inputs_and_in_place(U):
+    sc = configs.plain()
+    prm = sc.params()
+    up = U.from_scene(sc)
+    empty = torch.zeros((3, 0), dtype=torch.float32, device="cuda")
+    hr_x = dev(sc.hr_x0, torch)
+    hr_v = dev(np.random.default_rng(1).normal(size=sc.hr_x0.shape).astype(np.float32), torch)
+    hv0 = host(hr_v).copy()
+    # n_lr = 0: every HR particle falls freely (then meets the box walls)
+    x1, v1 = up.step(empty, empty, None, hr_x, hr_v)
+    torch.cuda.synchronize()
+    compare_step(host(x1), host(v1), np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32), None,
+                 sc.hr_x0, hv0, prm, sc.box_length)
+    # n_hr = 0 is a no-op
+    X, V = sc.lr_frame(1)
+    up.step(dev(X, torch), dev(V, torch), None, empty, empty)
+    # in place: outputs alias inputs
+    xa, va = hr_x.clone(), hr_v.clone()
+    up.step(dev(X, torch), dev(V, torch), None, xa, va, out_x=xa, out_v=va)
+    xb, vb = up.step(dev(X, torch), dev(V, torch), None, hr_x, hr_v)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb) and torch.equal(va, vb)
+
+
+def test_capacity_and_state_errors(U):
+    from paper_2308_01629_amd import UpsampleError
+    sc = configs.plain()
+    up = U(sc.r_lr, sc.r_hr, sc.dt, sc.g, sc.domain_lo, sc.domain_hi, walls=sc.walls, max_lr=100, max_hr=100)
+    X, V = sc.lr_frame(1)
+    with pytest.raises(UpsampleError, match="CAPACITY"):
+        up.build_grid(dev(X, torch), dev(V, torch))
+    hx = dev(sc.hr_x0[:, :50].copy(), torch)
+    with pytest.raises(UpsampleError, match="STATE"):
+        up.advance(hx, torch.zeros_like(hx))
+    up.build_grid(dev(X[:, :100].copy(), torch), dev(V[:, :100].copy(), torch))
+    up.advance(hx, torch.zeros_like(hx))
+    big = dev(sc.hr_x0[:, :101].copy(), torch)
+    with pytest.raises(UpsampleError, match="CAPACITY"):
+        up.advance(big, torch.zeros_like(big))
+    v = U(sc.r_lr, sc.r_hr, sc.dt, sc.g, sc.domain_lo, sc.domain_hi, max_lr=10, max_hr=10, validate=True)
+    bad = torch.zeros((3, 10), device="cuda")
+    bad[1, 3] = float("nan")
+    with pytest.raises(UpsampleError, match="NONFINITE"):
+        v.build_grid(bad, torch.zeros_like(bad))
+
+
+def test_deterministic_and_order_independent(U):
+    sc = configs.drain(scale=1 / 16)
+    up = U.from_scene(sc)
+    X, V = sc.lr_frame(2)
+    Xd, Vd = dev(X, torch), dev(V, torch)
+    hx, hv = dev(sc.hr_x0, torch), dev(np.random.default_rng(2).normal(size=sc.hr_x0.shape).astype(np.float32), torch)
+    a = up.step(Xd, Vd, None, hx, hv)
+    b = up.step(Xd, Vd, None, hx, hv)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # reorder HR by cell: per-particle results are unchanged, bit for bit
+    sx, sv = hx.clone(), hv.clone()
+    perm = up.sort_hr(sx, sv).long()
+    assert torch.equal(torch.sort(perm).values, torch.arange(sc.n_hr, device="cuda"))
+    assert torch.equal(sx, hx[:, perm]) and torch.equal(sv, hv[:, perm])
+    spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
+    k = O.cell_keys(host(sx), spec)
+    assert np.all(np.diff(k.astype(np.int64)) >= 0)
+    c = up.step(Xd, Vd, None, sx, sv)
+    torch.cuda.synchronize()
+    assert torch.equal(c[0], a[0][:, perm]) and torch.equal(c[1], a[1][:, perm])
