@@ -42,7 +42,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--sort-every", type=int, default=25)
+    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--sort-sub", type=int, default=0, help="HR reorder sub-cells per axis (0: library default)")
+    ap.add_argument("--groups", type=int, default=0, help="gather lane groups per wave (0: library default)")
     ap.add_argument("--cell-factor", type=float, default=0.0)
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -85,36 +87,48 @@ def drain_leg(args, torch, Upsampler):
     hx = torch.from_numpy(sc.hr_x0).cuda()
     hv = torch.from_numpy(sc.hr_v0).cuda()
     up = Upsampler.from_scene(sc, cell_factor=args.cell_factor)
+    if args.sort_sub:
+        up.set_tuning(sort_sub=args.sort_sub)
+    if args.groups:
+        up.set_tuning(gather_groups=args.groups)
     gi = up.grid_info()
-    log(f"drain: setup {time.time() - t0:.1f}s, grid {gi['dims']} reach {gi['reach']}")
+    log(f"drain: setup {time.time() - t0:.1f}s, grid {gi['dims']} reach {gi['reach']} tuning {up.get_tuning()}")
     up.sort_hr(hx, hv, with_perm=False)
+    # HR state ping-pongs between two buffer pairs: the reorder writes the other pair
+    state = [hx, hv, torch.empty_like(hx), torch.empty_like(hv)]
 
     def run(first, count, timed_kernel=False):
         up.timing_enable(timed_kernel)
         for k in range(count):
             t = first + k
             if args.sort_every and t % args.sort_every == 0:
-                up.sort_hr(hx, hv, with_perm=False)
-            up.step(LX[t], LV[t], None, hx, hv, out_x=hx, out_v=hv)
+                up.sort_hr(state[0], state[1], with_perm=False, out_x=state[2], out_v=state[3])
+                state[0], state[1], state[2], state[3] = state[2], state[3], state[0], state[1]
+            up.step(LX[t], LV[t], None, state[0], state[1], out_x=state[0], out_v=state[1])
 
     run(0, args.warmup)
     torch.cuda.synchronize()
+    # every repeat replays the same K steps from the same post-warm-up state
+    x_snap, v_snap = state[0].clone(), state[1].clone()
     times = []
-    for rep in range(args.repeats):
-        # the trajectory is replayed from the warm-up frames on: same work each repeat
+    for rep in range(args.repeats + 1):
+        state[0].copy_(x_snap)
+        state[1].copy_(v_snap)
+        timed_kernel = rep == args.repeats   # last pass: per-launch events on the gather kernel
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         s0.record()
-        run(args.warmup, args.steps)
+        run(args.warmup, args.steps, timed_kernel=timed_kernel)
         s1.record()
         torch.cuda.synchronize()
-        times.append(s0.elapsed_time(s1) / 1e3)
-        log(f"drain: repeat {rep}: {times[-1] * 1e3 / args.steps:.4f} ms/step")
-    # dominant kernel: the fused gather, events on the stream it runs on
-    run(args.warmup, args.steps, timed_kernel=True)
-    adv_ms, launches = up.timing_read()
-    up.timing_enable(False)
+        if timed_kernel:
+            adv_ms, launches = up.timing_read()
+            up.timing_enable(False)
+            log(f"drain: gather kernel {adv_ms * 1e3 / max(launches, 1):.1f} us/launch over {launches}")
+        else:
+            times.append(s0.elapsed_time(s1) / 1e3)
+            log(f"drain: repeat {rep}: {times[-1] * 1e3 / args.steps:.4f} ms/step")
     elapsed = float(np.median(times))
     ms_step = elapsed * 1e3 / args.steps
     n_cells = gi["n_cells"]
@@ -130,7 +144,8 @@ def drain_leg(args, torch, Upsampler):
            "step_hbm_frac": step_bytes / (ms_step / 1e3) / HBM_PEAK,
            "config": {"workload": "drain", "n_lr": sc.n_lr, "n_hr": sc.n_hr, "r_lr": sc.r_lr,
                       "r_hr": sc.r_hr, "dt": sc.dt, "walls": int(sc.walls.shape[0]),
-                      "grid": list(gi["dims"]), "reach": gi["reach"], "sort_every": args.sort_every},
+                      "grid": list(gi["dims"]), "reach": gi["reach"], "sort_every": args.sort_every,
+                      "tuning": up.get_tuning()},
            "roofline": rf, "scene": sc, "frames": frames}
     up.close()
     return res

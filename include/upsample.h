@@ -184,14 +184,17 @@ int upsample_step_backward(upsample_handle h,
                            void* stream);
 
 /*
- * Reorder HR particles in place by grid cell (cells of the handle's grid, so
- * consecutive particles share a stencil).  hr_x, hr_v: [3][n_hr] permuted in
- * place; perm_out (device int32 [n_hr], may be NULL) receives, for each new
- * position, the particle's old index.  The order within a cell is unspecified.
+ * Reorder HR particles by grid cell and, inside a cell, by the Morton order of
+ * sort_sub^3 sub-cells (upsample_tuning), so that consecutive particles -- the
+ * lanes of one wave of the step kernel -- occupy a compact box.  Reads hr_x,
+ * hr_v [3][n_hr]; writes the reordered arrays to hr_x_out, hr_v_out (both
+ * alias their inputs for an in-place reorder through scratch, or neither).
+ * perm_out (device int32 [n_hr], may be NULL) receives, for each new position,
+ * the particle's old index.  The order inside a sub-cell is unspecified.
  * Per-particle results of later steps do not depend on the order.
  */
-int upsample_sort_hr(upsample_handle h, float* hr_x, float* hr_v, int64_t n_hr,
-                     int32_t* perm_out, void* stream);
+int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
+                     float* hr_v_out, int64_t n_hr, int32_t* perm_out, void* stream);
 
 /*
  * Debug exports (for parity tests).
@@ -210,6 +213,20 @@ int upsample_debug_grid(upsample_handle h, uint32_t* keys, uint32_t* perm,
 int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* hr_v,
                              int64_t n_hr, uint32_t* count, uint32_t* ids, int64_t max_k,
                              uint8_t* branch, void* stream);
+
+/*
+ * Launch-shape knobs of a handle (results do not depend on them beyond float
+ * summation order).  gather_groups: lane groups per wave in the gather kernel
+ * (1, 2 or 4); each group of 64/G lanes walks its own LDS candidate list, culled
+ * against the group's bounding box.  Default 1.  sort_sub: sub-cells per axis
+ * of the HR reorder key (1, 2 or 4, at most what the grid's bins allow).
+ */
+typedef struct {
+  int32_t gather_groups;
+  int32_t sort_sub;
+} upsample_tuning;
+int upsample_set_tuning(upsample_handle h, const upsample_tuning* t);
+int upsample_get_tuning(upsample_handle h, upsample_tuning* t);
 
 /*
  * Kernel-time probe for one handle: when enabled, upsample_advance records HIP

@@ -57,6 +57,10 @@ class GridInfo(ctypes.Structure):
                 "h2": float(self.h2), "inv_h2": float(self.inv_h2), "lo": tuple(self.lo)}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("gather_groups", ctypes.c_int32), ("sort_sub", ctypes.c_int32)]
+
+
 class SceneDesc(ctypes.Structure):
     """upsample_scene: one scene of a batch."""
     _fields_ = [("params", Params), ("lr_offset", ctypes.c_int64), ("n_lr", ctypes.c_int64),
@@ -81,9 +85,11 @@ SIGNATURES = {
     "upsample_advance": (_INT, [_P, _P, _P, _P, _P, _I64, _P]),
     "upsample_step": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P]),
     "upsample_step_backward": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
-    "upsample_sort_hr": (_INT, [_P, _P, _P, _I64, _P, _P]),
+    "upsample_sort_hr": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _P]),
     "upsample_debug_grid": (_INT, [_P, _P, _P, _P, _P]),
     "upsample_debug_neighbors": (_INT, [_P, _P, _P, _I64, _P, _P, _I64, _P, _P]),
+    "upsample_set_tuning": (_INT, [_P, ctypes.POINTER(Tuning)]),
+    "upsample_get_tuning": (_INT, [_P, ctypes.POINTER(Tuning)]),
     "upsample_timing_enable": (_INT, [_P, _INT]),
     "upsample_timing_read": (_INT, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "upsample_batch_init": (_INT, [ctypes.POINTER(SceneDesc), _I32, ctypes.c_uint32, ctypes.POINTER(_P)]),

@@ -23,15 +23,38 @@ __device__ __forceinline__ uint32_t cell_key(const GridConst& gc, float x, float
   return (uint32_t)cx + (uint32_t)gc.dims[0] * ((uint32_t)cy + (uint32_t)gc.dims[1] * (uint32_t)cz);
 }
 
+// Arrival slot of key k inside its bin.  Lanes whose key equals the key of the
+// lane before them join that lane's run; the first lane of each run claims
+// the whole run with one atomic add.  Nearly sorted input (the HR reorder)
+// then costs a handful of atomics per wave instead of 64.
+__device__ __forceinline__ uint32_t claim_slot(uint32_t k, bool valid, uint32_t* counts) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t kk = valid ? k : 0xffffffffu;
+  const uint32_t prev = __shfl_up(kk, 1, 64);
+  const bool head = (lane == 0) || (prev != kk);
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int start = 63 - __clzll(heads & upto);
+  const uint64_t above = heads & ~upto;
+  const int next = above ? (__ffsll((long long)above) - 1) : 64;
+  uint32_t base = 0u;
+  if (head && valid) base = atomicAdd(&counts[kk], (uint32_t)(next - lane));
+  base = __shfl(base, start, 64);
+  return base + (uint32_t)(lane - start);
+}
+
 __global__ __launch_bounds__(kBlock) void k_keys_count(GridConst gc, const float* __restrict__ x,
                                                        int64_t n, uint32_t* __restrict__ keys,
                                                        uint32_t* __restrict__ slot,
                                                        uint32_t* __restrict__ counts) {
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  uint32_t k = cell_key(gc, x[i], x[n + i], x[2 * n + i]);
-  keys[i] = k;
-  slot[i] = atomicAdd(&counts[k], 1u);
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = i < n;
+  const uint32_t k = valid ? cell_key(gc, x[i], x[n + i], x[2 * n + i]) : 0u;
+  const uint32_t sl = claim_slot(k, valid, counts);
+  if (valid) {
+    keys[i] = k;
+    slot[i] = sl;
+  }
 }
 
 // Inclusive wave64 scan with ds_swizzle-free shuffles.
@@ -207,15 +230,44 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const float* __restrict
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-hipError_t keys_and_scan(const GridConst& gc, const float* x, int64_t n, int64_t n_cells,
-                         uint32_t* keys, uint32_t* slot, const GridScratch& s, hipStream_t st) {
-  if (n > 0) {
-    hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n)), dim3(kBlock), 0, st, gc, x, n, keys, slot,
-                       s.counts);
+// Interleave the low two bits of three sub-cell indices (Morton order).
+__device__ __forceinline__ uint32_t morton2(uint32_t a, uint32_t b, uint32_t c) {
+  return (a & 1u) | ((b & 1u) << 1) | ((c & 1u) << 2) | ((a & 2u) << 2) | ((b & 2u) << 3) | ((c & 2u) << 4);
+}
+
+__device__ __forceinline__ uint32_t sub_index(float x, float lo, float inv_cs, int G, int sub) {
+  const float t = (x - lo) * inv_cs;
+  const float c = fminf(fmaxf(floorf(t), 0.0f), (float)(G - 1));
+  const float f = floorf((t - c) * (float)sub);
+  return (uint32_t)fminf(fmaxf(f, 0.0f), (float)(sub - 1));
+}
+
+__global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const float* __restrict__ x,
+                                                          int64_t n, int sub,
+                                                          uint32_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ slot,
+                                                          uint32_t* __restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = i < n;
+  const int64_t ii = valid ? i : 0;
+  const float px = x[ii], py = x[n + ii], pz = x[2 * n + ii];
+  const uint32_t cell = cell_key(gc, px, py, pz);
+  const uint32_t sx = sub_index(px, gc.lo[0], gc.inv_cs, gc.dims[0], sub);
+  const uint32_t sy = sub_index(py, gc.lo[1], gc.inv_cs, gc.dims[1], sub);
+  const uint32_t sz = sub_index(pz, gc.lo[2], gc.inv_cs, gc.dims[2], sub);
+  const uint32_t k = cell * (uint32_t)(sub * sub * sub) + morton2(sx, sy, sz);
+  const uint32_t sl = claim_slot(k, valid, counts);
+  if (valid) {
+    keys[i] = k;
+    slot[i] = sl;
   }
-  int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);
-  hipLaunchKernelGGL(k_scan_cells, dim3(n_chunks), dim3(kBlock), 0, st, s.counts, n_cells, s.local,
-                     s.chunk_sum, s.ticket, n_chunks);
+}
+
+hipError_t scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t* chunk_sum,
+                     uint32_t* ticket, hipStream_t st) {
+  int n_chunks = (int)((n_bins + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(k_scan_cells, dim3(n_chunks), dim3(kBlock), 0, st, counts, n_bins, local,
+                     chunk_sum, ticket, n_chunks);
   return hipGetLastError();
 }
 
@@ -224,7 +276,11 @@ hipError_t keys_and_scan(const GridConst& gc, const float* x, int64_t n, int64_t
 hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float* lr_v,
                              const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
                              const GridScratch& s, hipStream_t st) {
-  hipError_t e = keys_and_scan(gc, lr_x, n_lr, n_cells, s.keys, s.slot, s, st);
+  if (n_lr > 0) {
+    hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, gc, lr_x, n_lr,
+                       s.keys, s.slot, s.counts);
+  }
+  hipError_t e = scan_bins(s.counts, n_cells, s.local, s.chunk_sum, s.ticket, st);
   if (e != hipSuccess) return e;
   int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);
   int64_t span = n_lr > n_cells + 1 ? n_lr : n_cells + 1;
@@ -237,18 +293,24 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
   return hipGetLastError();
 }
 
-hipError_t launch_sort_hr(const GridConst& gc, float* hr_x, float* hr_v, int64_t n_hr,
-                          int64_t n_cells, const GridScratch& g, const HRSortScratch& s,
+hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
+                          float* out_v, int64_t n_hr, int sub, const HRSortScratch& s,
                           int32_t* perm_out, hipStream_t st) {
   if (n_hr == 0) return hipSuccess;
-  // Reuses the grid's counts / local / chunk_sum; cell_start and the sorted LR
-  // copy of the last build are left untouched.
-  hipError_t e = keys_and_scan(gc, hr_x, n_hr, n_cells, s.keys, s.slot, g, st);
+  const int64_t n_bins = s.n_cells * sub * sub * sub;
+  hipLaunchKernelGGL(k_hr_keys_count, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, gc, hr_x, n_hr,
+                     sub, s.keys, s.slot, s.counts);
+  hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, s.ticket, st);
   if (e != hipSuccess) return e;
+  const bool in_place = out_x == hr_x || out_v == hr_v;
+  int32_t* perm = (perm_out != nullptr && !in_place) ? perm_out : s.perm;
   hipLaunchKernelGGL(k_hr_scatter, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.keys, s.slot, n_hr,
-                     g.local, g.chunk_sum, hr_x, hr_v, s.x, s.v, s.perm);
-  hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.x, s.v, s.perm, n_hr,
-                     hr_x, hr_v, perm_out);
+                     s.local, s.chunk_sum, hr_x, hr_v, in_place ? s.x : out_x, in_place ? s.v : out_v,
+                     perm);
+  if (in_place) {
+    hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.x, s.v, s.perm,
+                       n_hr, out_x, out_v, perm_out);
+  }
   return hipGetLastError();
 }
 

@@ -24,16 +24,24 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
                              const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
                              const GridScratch& s, hipStream_t st);
 
-// HR reorder by cell (keys, counts, scan, scatter, gather-copy).
+// HR reorder by (cell, Morton order of sub x sub x sub sub-cells), so that a
+// wave's 64 consecutive particles sit in a compact box.
 struct HRSortScratch {
-  uint32_t* keys;    // [max_hr]
-  uint32_t* slot;    // [max_hr]
-  float* x;          // [3][max_hr]
-  float* v;          // [3][max_hr]
-  int32_t* perm;     // [max_hr]
+  uint32_t* keys;       // [max_hr]
+  uint32_t* slot;       // [max_hr]
+  float* x;             // [3][max_hr]
+  float* v;             // [3][max_hr]
+  int32_t* perm;        // [max_hr]
+  uint32_t* counts;     // [n_bins], zero between sorts
+  uint32_t* local;      // [n_bins]
+  uint32_t* chunk_sum;  // [n_bins / kScanChunk + 2]
+  uint32_t* ticket;     // [1]
+  int64_t n_cells;      // grid cells
+  int max_sub;          // largest sub-cell count per axis the bins are sized for (4, 2 or 1)
 };
-hipError_t launch_sort_hr(const GridConst& gc, float* hr_x, float* hr_v, int64_t n_hr,
-                          int64_t n_cells, const GridScratch& g, const HRSortScratch& s,
+// out_x / out_v may alias hr_x / hr_v (then the permuted copy goes through scratch).
+hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
+                          float* out_v, int64_t n_hr, int sub, const HRSortScratch& s,
                           int32_t* perm_out, hipStream_t st);
 
 // a6: fused gather + blend + integrate + walls.
@@ -52,6 +60,7 @@ struct AdvanceArgs {
   uint32_t* dbg_ids;
   int64_t dbg_max_k;
   uint8_t* dbg_branch;
+  int groups;  // lane groups per wave in the tiled gather: 1, 2 or 4 (a tuning knob)
 };
 hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool debug, hipStream_t st);
 

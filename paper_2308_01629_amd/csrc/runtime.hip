@@ -24,9 +24,11 @@ struct upsample_handle_s {
   HRSortScratch hs;
   uint32_t* finite_flag;
   bool grid_valid;
-  bool counts_dirty;  // an interrupted build may have left counts non-zero
+  bool counts_dirty;     // an interrupted build may have left counts non-zero
+  bool hr_counts_dirty;  // same for the HR sort bins
   int64_t grid_n_lr;
   bool has_rigid;
+  upsample_tuning tune;
   bool timing;
   hipEvent_t ev[2 * kTimingRing];  // start/stop pairs, reused round-robin
   int64_t timed_issued;            // pairs recorded since the last read
@@ -135,7 +137,8 @@ hipError_t dmalloc(T** p, int64_t count) {
 void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
                   h->g.ticket, h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.x,
-                  h->hs.v, h->hs.perm, h->finite_flag};
+                  h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum, h->hs.ticket,
+                  h->finite_flag};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
 }
@@ -259,6 +262,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   if (p->n_walls > 0) std::memcpy(h->walls, p->walls, sizeof(float) * UPSAMPLE_WALL_FLOATS * p->n_walls);
   h->p.walls = nullptr;
   compute_grid(&h->p, &h->gi, &why);
+  h->tune.gather_groups = 1;
   h->n_cells = h->gi.n_cells;
   h->n_chunks = (int)((h->n_cells + kScanChunk - 1) / kScanChunk);
   if (hipGetDevice(&h->device) != hipSuccess) {
@@ -284,10 +288,23 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->hs.x, 3 * nh)
   ALLOC(h->hs.v, 3 * nh)
   ALLOC(h->hs.perm, nh)
+  // HR sort bins: sub^3 Morton sub-cells per grid cell, at most 2^24 bins
+  h->hs.n_cells = h->n_cells;
+  h->hs.max_sub = 4;
+  while (h->hs.max_sub > 1 && h->n_cells * h->hs.max_sub * h->hs.max_sub * h->hs.max_sub > ((int64_t)1 << 24))
+    h->hs.max_sub /= 2;
+  const int64_t n_bins = nh > 0 ? h->n_cells * h->hs.max_sub * h->hs.max_sub * h->hs.max_sub : 1;
+  h->tune.sort_sub = h->hs.max_sub >= 2 ? 2 : 1;
+  ALLOC(h->hs.counts, n_bins)
+  ALLOC(h->hs.local, n_bins)
+  ALLOC(h->hs.chunk_sum, n_bins / kScanChunk + 2)
+  ALLOC(h->hs.ticket, 1)
   ALLOC(h->finite_flag, 1)
 #undef ALLOC
   if (e == hipSuccess) e = hipMemset(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells);
   if (e == hipSuccess) e = hipMemset(h->g.ticket, 0, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(h->hs.counts, 0, sizeof(uint32_t) * (size_t)n_bins);
+  if (e == hipSuccess) e = hipMemset(h->hs.ticket, 0, sizeof(uint32_t));
   for (int k = 0; k < 2 * kTimingRing && e == hipSuccess; ++k) e = hipEventCreate(&h->ev[k]);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -391,6 +408,7 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
   a.dbg_ids = ids;
   a.dbg_max_k = max_k;
   a.dbg_branch = branch;
+  a.groups = h->tune.gather_groups;
   const bool timed = h->timing && !debug && n_hr > 0;
   hipError_t e = hipSuccess;
   int slot = 0;
@@ -469,25 +487,29 @@ int upsample_step_backward(upsample_handle h, const float* lr_x, const float* lr
   return UPSAMPLE_OK;
 }
 
-int upsample_sort_hr(upsample_handle h, float* hr_x, float* hr_v, int64_t n_hr, int32_t* perm_out,
-                     void* stream) {
+int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
+                     float* hr_v_out, int64_t n_hr, int32_t* perm_out, void* stream) {
   if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
   if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
   if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
-  if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr))
+  if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr || hr_x_out == nullptr || hr_v_out == nullptr))
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
+  if (n_hr > 0 && ((hr_x_out == hr_x) != (hr_v_out == hr_v)))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "outputs must both alias their inputs or neither");
   int rc = check_device(h);
   if (rc != UPSAMPLE_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
-  if (h->counts_dirty) {
-    hipError_t e = hipMemsetAsync(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
-    if (e == hipSuccess) e = hipMemsetAsync(h->g.ticket, 0, sizeof(uint32_t), st);
+  if (h->hr_counts_dirty) {
+    const int64_t n_bins = h->n_cells * h->hs.max_sub * h->hs.max_sub * h->hs.max_sub;
+    hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)n_bins, st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->hs.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "sort_hr");
-    h->counts_dirty = false;
+    h->hr_counts_dirty = false;
   }
-  hipError_t e = launch_sort_hr(grid_const(h), hr_x, hr_v, n_hr, h->n_cells, h->g, h->hs, perm_out, st);
+  hipError_t e = launch_sort_hr(grid_const(h), hr_x, hr_v, hr_x_out, hr_v_out, n_hr, h->tune.sort_sub,
+                                h->hs, perm_out, st);
   if (e != hipSuccess) {
-    h->counts_dirty = true;
+    h->hr_counts_dirty = true;
     return hip_fail(h, e, "sort_hr");
   }
   return UPSAMPLE_OK;
@@ -518,6 +540,24 @@ int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* 
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "ids needs max_k > 0");
   // The debug walk writes the stepped state to the handle's HR sort scratch.
   return advance_impl(h, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, stream, true, count, ids, max_k, branch);
+}
+
+int upsample_set_tuning(upsample_handle h, const upsample_tuning* t) {
+  if (h == nullptr || t == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (t->gather_groups != 1 && t->gather_groups != 2 && t->gather_groups != 4)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "gather_groups must be 1, 2 or 4");
+  if (t->sort_sub != 1 && t->sort_sub != 2 && t->sort_sub != 4)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_sub must be 1, 2 or 4");
+  if (t->sort_sub > h->hs.max_sub)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_sub exceeds the bins allocated for this grid");
+  h->tune = *t;
+  return UPSAMPLE_OK;
+}
+
+int upsample_get_tuning(upsample_handle h, upsample_tuning* t) {
+  if (h == nullptr || t == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  *t = h->tune;
+  return UPSAMPLE_OK;
 }
 
 int upsample_timing_enable(upsample_handle h, int enable) {

@@ -166,13 +166,17 @@ class Upsampler:
             _ptr(gx_out), _ptr(gv_out), _ptr(gx_in), _ptr(gv_in), _ptr(g_lr_x), _ptr(g_lr_v), _stream()))
         return gx_in, gv_in, g_lr_x, g_lr_v
 
-    def sort_hr(self, hr_x, hr_v, with_perm: bool = True):
-        """Reorders hr_x / hr_v in place by grid cell; returns the old index of
-        each new position (int32) or None."""
+    def sort_hr(self, hr_x, hr_v, with_perm: bool = True, out_x=None, out_v=None):
+        """Reorders the HR state by grid cell / Morton sub-cell: in place by
+        default, or into out_x / out_v.  Returns the old index of each new
+        position (int32) or None."""
         n = _soa(hr_x, "hr_x").shape[1]
         _soa(hr_v, "hr_v")
+        ox = hr_x if out_x is None else _soa(out_x, "out_x")
+        ov = hr_v if out_v is None else _soa(out_v, "out_v")
         perm = torch.empty(n, dtype=torch.int32, device=hr_x.device) if with_perm else None
-        self._check(self._L.upsample_sort_hr(self._h, _ptr(hr_x), _ptr(hr_v), n, _ptr(perm), _stream()))
+        self._check(self._L.upsample_sort_hr(self._h, _ptr(hr_x), _ptr(hr_v), _ptr(ox), _ptr(ov), n,
+                                             _ptr(perm), _stream()))
         return perm
 
     # -- debug exports
@@ -193,6 +197,21 @@ class Upsampler:
         self._check(self._L.upsample_debug_neighbors(self._h, _ptr(hr_x), _ptr(hr_v), n, _ptr(count),
                                                      _ptr(ids), max_k, _ptr(branch), _stream()))
         return count, ids, branch
+
+    # -- launch-shape knobs
+    def set_tuning(self, gather_groups: Optional[int] = None, sort_sub: Optional[int] = None) -> None:
+        t = _lib.Tuning()
+        self._check(self._L.upsample_get_tuning(self._h, ctypes.byref(t)))
+        if gather_groups is not None:
+            t.gather_groups = int(gather_groups)
+        if sort_sub is not None:
+            t.sort_sub = int(sort_sub)
+        self._check(self._L.upsample_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = _lib.Tuning()
+        self._check(self._L.upsample_get_tuning(self._h, ctypes.byref(t)))
+        return {"gather_groups": int(t.gather_groups), "sort_sub": int(t.sort_sub)}
 
     # -- kernel timing probe
     def timing_enable(self, enable: bool = True) -> None:

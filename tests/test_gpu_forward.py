@@ -218,3 +218,38 @@ def test_deterministic_and_order_independent(U):
     c = up.step(Xd, Vd, None, sx, sv)
     torch.cuda.synchronize()
     assert torch.equal(c[0], a[0][:, perm]) and torch.equal(c[1], a[1][:, perm])
+
+
+@pytest.mark.parametrize("groups", [1, 2, 4])
+def test_gather_group_variants_match_oracle(U, groups):
+    sc = configs.drain(scale=1 / 16)
+    prm = sc.params()
+    up = U.from_scene(sc)
+    up.set_tuning(gather_groups=groups)
+    assert up.get_tuning()["gather_groups"] == groups
+    X, V = sc.lr_frame(4)
+    hx, hv = dev(sc.hr_x0, torch), dev(sc.hr_v0, torch)
+    up.sort_hr(hx, hv, with_perm=False)
+    hx0, hv0 = host(hx).copy(), host(hv).copy()
+    x1, v1 = up.step(dev(X, torch), dev(V, torch), None, hx, hv)
+    torch.cuda.synchronize()
+    s = compare_step(host(x1), host(v1), X, V, None, hx0, hv0, prm, sc.box_length,
+                     idx=_sample(sc.n_hr, 65536, 9))
+    log(f"groups={groups}: {s}")
+
+
+@pytest.mark.parametrize("sub", [1, 2, 4])
+def test_sort_hr_out_of_place_and_sub_cells(U, sub):
+    sc = configs.drain(scale=1 / 32)
+    up = U.from_scene(sc)
+    up.set_tuning(sort_sub=sub)
+    hx = dev(sc.hr_x0[:, ::-1].copy(), torch)        # reversed: far from sorted
+    hv = dev(np.random.default_rng(4).normal(size=sc.hr_x0.shape).astype(np.float32), torch)
+    ox, ov = torch.empty_like(hx), torch.empty_like(hv)
+    perm = up.sort_hr(hx, hv, out_x=ox, out_v=ov).long()
+    torch.cuda.synchronize()
+    assert torch.equal(torch.sort(perm).values, torch.arange(sc.n_hr, device="cuda"))
+    assert torch.equal(ox, hx[:, perm]) and torch.equal(ov, hv[:, perm])
+    spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
+    k = O.cell_keys(host(ox), spec)
+    assert np.all(np.diff(k.astype(np.int64)) >= 0)
