@@ -151,6 +151,89 @@ def drain_leg(args, torch, Upsampler):
     return res
 
 
+def diff_leg(args, torch, Upsampler, steps=40, every=8):
+    """Backward/forward time ratio on the differentiation workload (heap, 16,384
+    LR, 1,048,576 HR): per step (step vs step_backward, each with its grid
+    rebuild) and over a checkpointed 40-step rollout with its loss."""
+    from workloads import configs
+    from paper_2308_01629_amd.autograd import rollout
+    sc = configs.diff()
+    log(f"diff: {sc.n_lr} LR, {sc.n_hr} HR, {steps} steps, checkpoint every {every}")
+    frames = [sc.lr_frame(t) for t in range(1, steps + 1)]
+    LX = torch.from_numpy(np.stack([f[0] for f in frames])).cuda()
+    LV = torch.from_numpy(np.stack([f[1] for f in frames])).cuda()
+    up = Upsampler.from_scene(sc)
+    x0 = torch.from_numpy(sc.hr_x0).cuda()
+    v0 = torch.from_numpy(sc.hr_v0).cuda()
+    y = torch.from_numpy(sc.target).cuda()
+    # per-step states of the trajectory, reordered at every checkpoint as the
+    # rollout does
+    xs, vs = [x0], [v0]
+    for t in range(steps):
+        x, v = xs[-1], vs[-1]
+        if t % every == 0:
+            sx, sv = torch.empty_like(x), torch.empty_like(v)
+            up.sort_hr(x, v, with_perm=False, out_x=sx, out_v=sv)
+            xs[-1], vs[-1] = x, v = sx, sv
+        x1, v1 = up.step(LX[t], LV[t], None, x, v)
+        xs.append(x1)
+        vs.append(v1)
+    gx = torch.randn_like(x0)
+    gv = torch.randn_like(v0)
+    glx = torch.zeros_like(LX[0])
+    glv = torch.zeros_like(LV[0])
+    ox, ov = torch.empty_like(x0), torch.empty_like(v0)
+    bx, bv = torch.empty_like(x0), torch.empty_like(v0)
+
+    def timed(fn, reps=3):
+        best = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best.append(e0.elapsed_time(e1))
+        return float(np.median(best))
+
+    def fwd():
+        for t in range(steps):
+            up.step(LX[t], LV[t], None, xs[t], vs[t], out_x=ox, out_v=ov)
+
+    def bwd():
+        for t in range(steps - 1, -1, -1):
+            up.step_backward(LX[t], LV[t], None, xs[t], vs[t], gx, gv, g_lr_x=glx, g_lr_v=glv,
+                             gx_in=bx, gv_in=bv)
+
+    fwd()
+    bwd()
+    t_f = timed(fwd) / steps
+    t_b = timed(bwd) / steps
+    LXg = LX.clone().requires_grad_(True)
+    LVg = LV.clone().requires_grad_(True)
+
+    def roll_fwd():
+        with torch.no_grad():
+            rollout(up, x0, v0, LX, LV, checkpoint_every=every)
+
+    def roll_fb():
+        xT, _ = rollout(up, x0, v0, LXg, LVg, checkpoint_every=every)
+        (((xT - y) ** 2).sum() / sc.n_hr).backward()
+
+    roll_fb()
+    t_rf = timed(roll_fwd, 2)
+    t_rfb = timed(roll_fb, 2)
+    up.close()
+    log(f"diff: forward {t_f * 1e3:.1f} us/step, backward {t_b * 1e3:.1f} us/step, ratio {t_b / t_f:.2f}; "
+        f"rollout fwd {t_rf:.2f} ms, fwd+bwd {t_rfb:.2f} ms")
+    return {"workload": "diff", "n_lr": sc.n_lr, "n_hr": sc.n_hr, "forward_us_per_step": t_f * 1e3,
+            "backward_us_per_step": t_b * 1e3, "ratio": t_b / t_f,
+            "rollout_steps": steps, "checkpoint_every": every, "rollout_forward_ms": t_rf,
+            "rollout_forward_backward_ms": t_rfb, "rollout_backward_over_forward": (t_rfb - t_rf) / t_rf}
+
+
 def cpu_baseline(sc, frames, budget_s=12.0):
     """The oracle as it stands on a bounded sample of the drain workload: the
     full LR frame, a seeded sample of HR particles, one step."""
@@ -190,6 +273,8 @@ def main():
            "dtype": "f32", "data": "synthetic"}
     d = drain_leg(args, torch, Upsampler)
     out.update({k: d[k] for k in ("value", "ms_per_step", "config", "roofline", "step_hbm_frac")})
+    if not args.no_extras:
+        out["backward_forward"] = diff_leg(args, torch, Upsampler)
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the oracle")
         out["cpu_baseline"] = cpu_baseline(d["scene"], d["frames"])

@@ -197,6 +197,23 @@ int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, fl
                      float* hr_v_out, int64_t n_hr, int32_t* perm_out, void* stream);
 
 /*
+ * Apply a permutation to the columns of a [3][n] array a and, optionally, of
+ * a second one b (positions and velocities, or their gradients), so that a
+ * caller can keep HR particles in reordered form between steps and map
+ * results and gradients back.  mode UPSAMPLE_PERMUTE_GATHER:
+ * a_out[:, i] = a[:, perm[i]]; UPSAMPLE_PERMUTE_SCATTER: a_out[:, perm[i]] =
+ * a[:, i] (the inverse; the adjoint of the gather).  perm (device int32 [n])
+ * must be a permutation of 0..n-1, as upsample_sort_hr writes; columns whose
+ * index lies outside [0, n) are skipped, and with UPSAMPLE_FLAG_VALIDATE the
+ * call then synchronises and returns UPSAMPLE_ERR_INVALID_ARG.  b and b_out
+ * are both NULL or both set; outputs alias no input.  All device pointers.
+ */
+#define UPSAMPLE_PERMUTE_GATHER 0
+#define UPSAMPLE_PERMUTE_SCATTER 1
+int upsample_permute(upsample_handle h, const float* a, const float* b, float* a_out, float* b_out,
+                     int64_t n, const int32_t* perm, int mode, void* stream);
+
+/*
  * Debug exports (for parity tests).
  * upsample_debug_grid copies the last build's cell keys [n_lr] (original
  * order), sorted order perm [n_lr] and cell_start [n_cells + 1] into device
@@ -220,10 +237,20 @@ int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* 
  * (1, 2 or 4); each group of 64/G lanes walks its own LDS candidate list, culled
  * against the group's bounding box.  Default 1.  sort_sub: sub-cells per axis
  * of the HR reorder key (1, 2 or 4, at most what the grid's bins allow).
+ * sort_mode: 0 orders HR by grid cell then by the Morton order of its
+ * sub-cells, 1 by the global Morton (Z-order) code of the sub-cells.
+ * adjoint_tiled: 1 (default) runs the adjoint as wave tiles with block-summed
+ * LR gradients, 0 one particle per lane with per-pair atomics (scenes with
+ * rigid LR particles always use the latter).  tile_max / adjoint_tile_max: a
+ * wave whose stencil rows hold more LR candidates than this walks per lane.
  */
 typedef struct {
   int32_t gather_groups;
   int32_t sort_sub;
+  int32_t adjoint_tiled;
+  int32_t sort_mode;
+  int32_t tile_max;
+  int32_t adjoint_tile_max;
 } upsample_tuning;
 int upsample_set_tuning(upsample_handle h, const upsample_tuning* t);
 int upsample_get_tuning(upsample_handle h, upsample_tuning* t);

@@ -58,7 +58,9 @@ class GridInfo(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("gather_groups", ctypes.c_int32), ("sort_sub", ctypes.c_int32)]
+    _fields_ = [("gather_groups", ctypes.c_int32), ("sort_sub", ctypes.c_int32),
+                ("adjoint_tiled", ctypes.c_int32), ("sort_mode", ctypes.c_int32),
+                ("tile_max", ctypes.c_int32), ("adjoint_tile_max", ctypes.c_int32)]
 
 
 class SceneDesc(ctypes.Structure):
@@ -86,6 +88,7 @@ SIGNATURES = {
     "upsample_step": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P]),
     "upsample_step_backward": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "upsample_sort_hr": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _P]),
+    "upsample_permute": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _INT, _P]),
     "upsample_debug_grid": (_INT, [_P, _P, _P, _P, _P]),
     "upsample_debug_neighbors": (_INT, [_P, _P, _P, _I64, _P, _P, _I64, _P, _P]),
     "upsample_set_tuning": (_INT, [_P, ctypes.POINTER(Tuning)]),

@@ -1,124 +1,86 @@
 // Adjoint of the upsampling step (an extension: the paper does not
-// differentiate it).  Per HR particle: a first stencil walk recomputes the
-// weighted sums, the argmax of the weights and the alpha branch; the forward
-// blend, integration and walls are replayed to record which walls acted; the
-// upstream gradient is pulled back through the walls, the integration and the
-// blend; a second stencil walk distributes the weight gradients to the LR
-// particles (float atomics into the caller's [3][n_lr] arrays, by original
-// index) and to the HR position.
+// differentiate it).  Per HR particle: a first pass over the LR neighbours
+// recomputes the weighted sums, the argmax of the weights and the alpha
+// branch; the forward blend, integration and walls are replayed to record
+// which walls acted; the upstream gradient is pulled back through the walls,
+// the integration and the blend; a second pass distributes the weight
+// gradients to the LR particles and to the HR position.
 //
 // Held fixed (piecewise differentiation): alpha branch, neighbour membership,
 // argmax of w (ties: smallest original LR index), wall activations.
+//
+// Two kernels share that arithmetic:
+//   k_adjoint_tiled  waves of spatially compact HR particles (tile.hpp): each
+//                    LR candidate's six gradient components are summed over
+//                    the wave with a permlane-swap transpose reduction and added
+//                    to global memory by six lanes (two atomic instructions);
+//   k_adjoint        one particle per lane, its own stencil walk, atomics per
+//                    pair: spread-out waves and scenes with rigid LR particles.
 #include "kernels.hpp"
+#include "tile.hpp"
 
 namespace ups {
 namespace {
 
-struct Pass1 {
-  float S, Ux, Uy, Uz, M;
-  uint32_t arg;
-  bool gran;
+// Per-particle adjoint state between the two passes.
+struct Back {
+  float gUx, gUy, gUz, gS, gM;  // dL/dU, dL/dS, dL/dM
+  float gx, gy, gz;             // dL/dx (direct part; the pair terms are added in pass 2)
+  float gvx, gvy, gvz;          // dL/dv
 };
 
-__device__ __forceinline__ void stencil_bounds(const GridConst& gc, float x, float y, float z,
-                                               int lo[3], int hi[3]) {
-  const int c[3] = {cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]),
-                    cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]),
-                    cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2])};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = max(c[a] - gc.reach, 0);
-    hi[a] = min(c[a] + gc.reach, gc.dims[a] - 1);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a, WallTable wt) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= a.n) return;
-  const int64_t n = a.n;
-  const GridConst& gc = a.gc;
-  const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
-  const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
-  int lo[3], hi[3];
-  stencil_bounds(gc, x, y, z, lo, hi);
-
-  // ---- pass 1: sums, argmax
-  Pass1 p{0.f, 0.f, 0.f, 0.f, 0.f, 0xffffffffu, false};
-  for (int zz = lo[2]; zz <= hi[2]; ++zz)
-    for (int yy = lo[1]; yy <= hi[1]; ++yy) {
-      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
-      const uint32_t b = a.cell_start[row + (uint32_t)lo[0]], e = a.cell_start[row + (uint32_t)hi[0] + 1u];
-      for (uint32_t j = b; j < e; ++j) {
-        const float4 P = a.lr[j].p;
-        const float s = sq_dist(P.x, P.y, P.z, x, y, z);
-        if (s < gc.h2) {
-          const float4 V = a.lr[j].v;
-          const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
-          const float w = t * t * t;
-          const uint32_t id = __float_as_uint(V.w);
-          p.S += w;
-          p.Ux = fmaf(w, V.x, p.Ux);
-          p.Uy = fmaf(w, V.y, p.Uy);
-          p.Uz = fmaf(w, V.z, p.Uz);
-          if (w > p.M || (w == p.M && id < p.arg)) {
-            p.M = w;
-            p.arg = id;
-          }
-          p.gran |= (P.w == 0.0f);
-        }
-      }
-    }
-  if (!p.gran) {
-    p.S = p.Ux = p.Uy = p.Uz = p.M = 0.f;
-  }
-
-  // ---- forward replay
+// Forward replay of blend, integration and walls, then the pull-back of the
+// upstream gradient (gx_out, gv_out) to the sums S, U, M and to x, v.
+__device__ __forceinline__ Back backprop(const StepConst& sc, const WallTable& wt, float x, float y,
+                                         float z, float vx, float vy, float vz, float S, float Ux,
+                                         float Uy, float Uz, float M, float gxo, float gyo, float gzo,
+                                         float hxo, float hyo, float hzo) {
   float tx = 0.f, ty = 0.f, tz = 0.f;
   bool A = true;
-  if (p.S > 0.0f) {
-    tx = p.Ux / p.S;
-    ty = p.Uy / p.S;
-    tz = p.Uz / p.S;
-    A = (p.M <= a.sc.c1) || (p.M / p.S >= a.sc.c2);
+  if (S > 0.0f) {
+    tx = Ux / S;
+    ty = Uy / S;
+    tz = Uz / S;
+    A = (M <= sc.c1) || (M / S >= sc.c2);
   }
-  const float alpha = A ? 1.0f - p.M : 0.0f;
-  const float dt = a.sc.dt;
-  const float fx = fmaf(dt, a.sc.g[0], vx), fy = fmaf(dt, a.sc.g[1], vy), fz = fmaf(dt, a.sc.g[2], vz);
+  const float alpha = A ? 1.0f - M : 0.0f;
+  const float dt = sc.dt;
+  const float fx = fmaf(dt, sc.g[0], vx), fy = fmaf(dt, sc.g[1], vy), fz = fmaf(dt, sc.g[2], vz);
   float nvx = fmaf(alpha, fx - tx, tx), nvy = fmaf(alpha, fy - ty, ty), nvz = fmaf(alpha, fz - tz, tz);
   float nx = fmaf(dt, nvx, x), ny = fmaf(dt, nvy, y), nz = fmaf(dt, nvz, z);
   uint32_t pushed = 0u, clipped = 0u;
-  for (int k = 0; k < a.sc.n_walls; ++k) {
+  for (int k = 0; k < sc.n_walls; ++k) {
     const float* w = &wt.w[k * UPSAMPLE_WALL_FLOATS];
     const float wnx = w[0], wny = w[1], wnz = w[2], d = w[3];
-    bool act = fmaf(w[6], nz, fmaf(w[5], ny, w[4] * nx)) >= w[7];
-    if (w[11] > 0.0f) {
-      const float rx = nx - w[8], ry = ny - w[9], rz = nz - w[10];
-      const float rn = fmaf(wnz, rz, fmaf(wny, ry, wnx * rx));
-      const float ix = fmaf(-rn, wnx, rx), iy = fmaf(-rn, wny, ry), iz = fmaf(-rn, wnz, rz);
-      act = act && (sqrtf(fmaf(iz, iz, fmaf(iy, iy, ix * ix))) >= w[11]);
-    }
-    act = act && (fmaf(wnz, z, fmaf(wny, y, wnx * x)) - d >= 0.0f);
     const float pen = fmaf(wnz, nz, fmaf(wny, ny, wnx * nx)) - d;
-    if (act && pen < a.sc.r_hr) {
-      pushed |= 1u << k;
-      const float push = a.sc.r_hr - pen;
-      nx = fmaf(push, wnx, nx);
-      ny = fmaf(push, wny, ny);
-      nz = fmaf(push, wnz, nz);
-      const float vn = fmaf(wnz, nvz, fmaf(wny, nvy, wnx * nvx));
-      if (vn < 0.0f) {
-        clipped |= 1u << k;
-        nvx = fmaf(-vn, wnx, nvx);
-        nvy = fmaf(-vn, wny, nvy);
-        nvz = fmaf(-vn, wnz, nvz);
+    if (pen < sc.r_hr) {
+      bool act = fmaf(w[6], nz, fmaf(w[5], ny, w[4] * nx)) >= w[7];
+      if (w[11] > 0.0f) {
+        const float rx = nx - w[8], ry = ny - w[9], rz = nz - w[10];
+        const float rn = fmaf(wnz, rz, fmaf(wny, ry, wnx * rx));
+        const float ix = fmaf(-rn, wnx, rx), iy = fmaf(-rn, wny, ry), iz = fmaf(-rn, wnz, rz);
+        act = act && (fmaf(iz, iz, fmaf(iy, iy, ix * ix)) >= w[11] * w[11]);
+      }
+      act = act && (fmaf(wnz, z, fmaf(wny, y, wnx * x)) - d >= 0.0f);
+      if (act) {
+        pushed |= 1u << k;
+        const float push = sc.r_hr - pen;
+        nx = fmaf(push, wnx, nx);
+        ny = fmaf(push, wny, ny);
+        nz = fmaf(push, wnz, nz);
+        const float vn = fmaf(wnz, nvz, fmaf(wny, nvy, wnx * nvx));
+        if (vn < 0.0f) {
+          clipped |= 1u << k;
+          nvx = fmaf(-vn, wnx, nvx);
+          nvy = fmaf(-vn, wny, nvy);
+          nvz = fmaf(-vn, wnz, nvz);
+        }
       }
     }
   }
-
-  // ---- pull the upstream gradient back
-  float gx = a.gx_out[i], gy = a.gx_out[n + i], gz = a.gx_out[2 * n + i];
-  float hx = a.gv_out[i], hy = a.gv_out[n + i], hz = a.gv_out[2 * n + i];
-  for (int k = a.sc.n_walls - 1; k >= 0; --k) {
+  // walls, last first: a push or a clip has Jacobian I - n n^T
+  float gx = gxo, gy = gyo, gz = gzo, hx = hxo, hy = hyo, hz = hzo;
+  for (int k = sc.n_walls - 1; k >= 0; --k) {
     const float* w = &wt.w[k * UPSAMPLE_WALL_FLOATS];
     if (pushed & (1u << k)) {
       const float gn = fmaf(w[2], gz, fmaf(w[1], gy, w[0] * gx));
@@ -137,20 +99,78 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a, WallTable wt)
   const float qx = fmaf(dt, gx, hx), qy = fmaf(dt, gy, hy), qz = fmaf(dt, gz, hz);
   // v' = (1 - alpha) v~ + alpha (v + dt g)
   const float g_alpha = qx * (fx - tx) + qy * (fy - ty) + qz * (fz - tz);
-  const float om = 1.0f - alpha;
-  const float gM = A ? -g_alpha : 0.0f;
-  float gUx = 0.f, gUy = 0.f, gUz = 0.f, gS = 0.f;
-  if (p.S > 0.0f) {
-    const float inv = 1.0f / p.S;
-    gUx = om * qx * inv;
-    gUy = om * qy * inv;
-    gUz = om * qz * inv;
-    gS = -(gUx * tx + gUy * ty + gUz * tz);
+  Back b;
+  b.gM = A ? -g_alpha : 0.0f;
+  b.gUx = b.gUy = b.gUz = b.gS = 0.f;
+  if (S > 0.0f) {
+    const float om = (1.0f - alpha) / S;
+    b.gUx = om * qx;
+    b.gUy = om * qy;
+    b.gUz = om * qz;
+    b.gS = -(b.gUx * tx + b.gUy * ty + b.gUz * tz);
   }
+  b.gx = gx;
+  b.gy = gy;
+  b.gz = gz;
+  b.gvx = alpha * qx;
+  b.gvy = alpha * qy;
+  b.gvz = alpha * qz;
+  return b;
+}
 
-  // ---- pass 2: weight gradients to LR and HR positions, LR velocities
-  if (p.gran) {
-    const float k2 = -6.0f * gc.inv_h2;  // dw/ds = -3 t^2 / h2, times 2 for d(s)/d(X)
+__device__ __forceinline__ void stencil_bounds(const GridConst& gc, float x, float y, float z,
+                                               int lo[3], int hi[3]) {
+  const int c[3] = {cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]),
+                    cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]),
+                    cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2])};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = max(c[a] - gc.reach, 0);
+    hi[a] = min(c[a] + gc.reach, gc.dims[a] - 1);
+  }
+}
+
+// One particle, its own stencil walk, float atomics per member pair.
+__device__ __forceinline__ void adjoint_lane(const AdjointArgs& a, const WallTable& wt, int64_t i) {
+  const int64_t n = a.n;
+  const GridConst& gc = a.gc;
+  const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
+  const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
+  int lo[3], hi[3];
+  stencil_bounds(gc, x, y, z, lo, hi);
+
+  float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
+  uint32_t arg = 0xffffffffu;
+  bool gran = false;
+  for (int zz = lo[2]; zz <= hi[2]; ++zz)
+    for (int yy = lo[1]; yy <= hi[1]; ++yy) {
+      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
+      const uint32_t b = a.cell_start[row + (uint32_t)lo[0]], e = a.cell_start[row + (uint32_t)hi[0] + 1u];
+      for (uint32_t j = b; j < e; ++j) {
+        const float4 P = a.lr[j].p;
+        const float s = sq_dist(P.x, P.y, P.z, x, y, z);
+        if (s < gc.h2) {
+          const float4 V = a.lr[j].v;
+          const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
+          const float w = t * t * t;
+          const uint32_t id = __float_as_uint(V.w);
+          S += w;
+          Ux = fmaf(w, V.x, Ux);
+          Uy = fmaf(w, V.y, Uy);
+          Uz = fmaf(w, V.z, Uz);
+          if (w > M || (w == M && id < arg)) {
+            M = w;
+            arg = id;
+          }
+          gran |= (P.w == 0.0f);
+        }
+      }
+    }
+  if (!gran) S = Ux = Uy = Uz = M = 0.f;  // rigid LR count only next to a granular one
+  Back bk = backprop(a.sc, wt, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, a.gx_out[i], a.gx_out[n + i],
+                     a.gx_out[2 * n + i], a.gv_out[i], a.gv_out[n + i], a.gv_out[2 * n + i]);
+  if (gran) {
+    const float k2 = -6.0f * gc.inv_h2;  // dw/ds = -3 t^2 / h2, times 2 for ds/dX
     const int64_t nl = a.n_lr;
     for (int zz = lo[2]; zz <= hi[2]; ++zz)
       for (int yy = lo[1]; yy <= hi[1]; ++yy) {
@@ -164,29 +184,344 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a, WallTable wt)
             const uint32_t id = __float_as_uint(V.w);
             const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
             const float w = t * t * t;
-            float gw = fmaf(gUz, V.z, fmaf(gUy, V.y, gUx * V.x)) + gS;
-            if (id == p.arg) gw += gM;
-            unsafeAtomicAdd(&a.g_lr_v[id], w * gUx);
-            unsafeAtomicAdd(&a.g_lr_v[nl + id], w * gUy);
-            unsafeAtomicAdd(&a.g_lr_v[2 * nl + id], w * gUz);
+            float gw = fmaf(bk.gUz, V.z, fmaf(bk.gUy, V.y, bk.gUx * V.x)) + bk.gS;
+            if (id == arg) gw += bk.gM;
+            unsafeAtomicAdd(&a.g_lr_v[id], w * bk.gUx);
+            unsafeAtomicAdd(&a.g_lr_v[nl + id], w * bk.gUy);
+            unsafeAtomicAdd(&a.g_lr_v[2 * nl + id], w * bk.gUz);
             const float c = gw * k2 * t * t;
             const float dx = P.x - x, dy = P.y - y, dz = P.z - z;
             unsafeAtomicAdd(&a.g_lr_x[id], c * dx);
             unsafeAtomicAdd(&a.g_lr_x[nl + id], c * dy);
             unsafeAtomicAdd(&a.g_lr_x[2 * nl + id], c * dz);
-            gx = fmaf(-c, dx, gx);
-            gy = fmaf(-c, dy, gy);
-            gz = fmaf(-c, dz, gz);
+            bk.gx = fmaf(-c, dx, bk.gx);
+            bk.gy = fmaf(-c, dy, bk.gy);
+            bk.gz = fmaf(-c, dz, bk.gz);
           }
         }
       }
   }
-  a.gx_in[i] = gx;
-  a.gx_in[n + i] = gy;
-  a.gx_in[2 * n + i] = gz;
-  a.gv_in[i] = alpha * qx;
-  a.gv_in[n + i] = alpha * qy;
-  a.gv_in[2 * n + i] = alpha * qz;
+  a.gx_in[i] = bk.gx;
+  a.gx_in[n + i] = bk.gy;
+  a.gx_in[2 * n + i] = bk.gz;
+  a.gv_in[i] = bk.gvx;
+  a.gv_in[n + i] = bk.gvy;
+  a.gv_in[2 * n + i] = bk.gvz;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a, WallTable wt) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  adjoint_lane(a, wt, i);
+}
+
+// Sum over 16 lanes of a row; lane 15 of the row receives it.
+__device__ __forceinline__ float row_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));
+  return v;
+}
+
+__device__ __forceinline__ float swap_sum32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wave sums of six per-lane values.  Returns q0, q1 such that lane 15 / 31 /
+// 47 / 63 of q0 hold the totals of a0 / a1 / a3 / a4 and lanes 15 / 47 of q1
+// hold the totals of a2 / a5.
+//   permlane32_swap(u, w) -> [u.lo, w.lo] and [u.hi, w.hi]: their sum carries
+//   u's 32-lane partials in lanes 0-31 and w's in lanes 32-63;
+//   permlane16_swap(u, w) -> [u.r0, w.r0, u.r2, w.r2] and [u.r1, w.r1, u.r3, w.r3]
+//   (rows of 16 lanes): their sum halves the partials again; a DPP row sum ends it.
+__device__ __forceinline__ void reduce6(float a0, float a1, float a2, float a3, float a4, float a5,
+                                        float* q0, float* q1) {
+  const float p0 = swap_sum32(a0, a3);
+  const float p1 = swap_sum32(a1, a4);
+  const float p2 = swap_sum32(a2, a5);
+  const auto t01 = __builtin_amdgcn_permlane16_swap(__float_as_uint(p0), __float_as_uint(p1), false, false);
+  const auto t22 = __builtin_amdgcn_permlane16_swap(__float_as_uint(p2), __float_as_uint(p2), false, false);
+  *q0 = row_sum(__uint_as_float(t01[0]) + __uint_as_float(t01[1]));
+  *q1 = row_sum(__uint_as_float(t22[0]) + __uint_as_float(t22[1]));
+}
+
+// Wave sums of twelve per-lane values (two candidates a, b; six components
+// each).  After the 32- and 16-lane swap levels the three registers hold,
+// row by row (rows of 16 lanes),
+//   r0: a0 a1 a3 a4     r1: a2 b0 a5 b3     r2: b1 b2 b4 b5
+// and a DPP row sum leaves each total on lane 15 of its row.
+struct Six {
+  float v[6];
+};
+
+__device__ __forceinline__ void reduce12(const Six& av, const Six& bv, float* r0, float* r1, float* r2) {
+  const float p0 = swap_sum32(av.v[0], av.v[3]);
+  const float p1 = swap_sum32(av.v[1], av.v[4]);
+  const float p2 = swap_sum32(av.v[2], av.v[5]);
+  const float p3 = swap_sum32(bv.v[0], bv.v[3]);
+  const float p4 = swap_sum32(bv.v[1], bv.v[4]);
+  const float p5 = swap_sum32(bv.v[2], bv.v[5]);
+  const auto t0 = __builtin_amdgcn_permlane16_swap(__float_as_uint(p0), __float_as_uint(p1), false, false);
+  const auto t1 = __builtin_amdgcn_permlane16_swap(__float_as_uint(p2), __float_as_uint(p3), false, false);
+  const auto t2 = __builtin_amdgcn_permlane16_swap(__float_as_uint(p4), __float_as_uint(p5), false, false);
+  *r0 = row_sum(__uint_as_float(t0[0]) + __uint_as_float(t0[1]));
+  *r1 = row_sum(__uint_as_float(t1[0]) + __uint_as_float(t1[1]));
+  *r2 = row_sum(__uint_as_float(t2[0]) + __uint_as_float(t2[1]));
+}
+
+// Gradient contributions of one (HR particle, LR candidate) pair: the six LR
+// components (dL/dV, dL/dX) are returned, the HR position term is subtracted
+// from bk.g{x,y,z}.
+__device__ __forceinline__ Six pair_contrib(float4 Q, float4 W, float x, float y, float z, float inv_h2,
+                                            float k2, uint32_t arg, Back& bk) {
+  const uint32_t id = __float_as_uint(W.w);
+  const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
+  const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const float t = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
+  const float t2 = t * t;
+  const float w = t2 * t;
+  const float gw = fmaf(bk.gUz, W.z, fmaf(bk.gUy, W.y, bk.gUx * W.x)) + bk.gS + (id == arg ? bk.gM : 0.0f);
+  const float cf = gw * k2 * t2;
+  Six o;
+  o.v[0] = w * bk.gUx;
+  o.v[1] = w * bk.gUy;
+  o.v[2] = w * bk.gUz;
+  o.v[3] = cf * dx;
+  o.v[4] = cf * dy;
+  o.v[5] = cf * dz;
+  bk.gx -= o.v[3];
+  bk.gy -= o.v[4];
+  bk.gz -= o.v[5];
+  return o;
+}
+
+// Block accumulation of LR gradients: the four waves of a block cover one
+// compact region, so their candidates share LR particles.  The block lists
+// the (y, z) rows of the union of its waves' stencils; slot s of the
+// flattened rows is one LR particle (sorted order).  Waves add their
+// wave-summed contributions to an LDS accumulator acc[component][slot] and the
+// block adds the non-zero slots to global memory once at the end.
+constexpr int kAccCap = 768;        // accumulator slots per block
+constexpr int kBlockRows = 256;     // at most one row per thread
+constexpr int kAdjListCap = 128;    // LDS candidate entries per wave and flush
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* wsum) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(v, lane);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t s = wsum[w];
+    off += (w < wid) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTable wt) {
+  __shared__ TileLDS<1, kAdjListCap> lds;
+  __shared__ float acc[6][kAccCap];
+  __shared__ uint32_t brb[kBlockRows];       // first sorted index of each block row
+  __shared__ uint32_t brp[kBlockRows + 1];   // exclusive prefix of block row lengths
+  __shared__ uint32_t sbase[kWaves][kMaxRows];  // block slot of each wave row's first entry
+  __shared__ int wbox[kWaves][6];
+  __shared__ int bmeta[8];
+  __shared__ uint32_t wsum[kWaves];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t n = a.n;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + tid;
+  const bool live = i0 < n;
+  const int64_t i = live ? i0 : n - 1;  // idle lanes shadow the last particle
+  const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
+  const GridConst& gc = a.gc;
+  const int64_t nl = a.n_lr;
+
+  const TileSetup<1> ts = tile_setup<1>(gc, a.cell_start, x, y, z, lane, wid, lds);
+  const bool wave_tiled = ts.nrows <= kMaxRows && ts.total <= (uint32_t)a.tile_max;
+
+  // ---- block box and block rows
+  if (lane == 0) {
+    wbox[wid][0] = ord(ts.gb[0].lo[0]); wbox[wid][1] = ord(ts.gb[0].lo[1]); wbox[wid][2] = ord(ts.gb[0].lo[2]);
+    wbox[wid][3] = ord(ts.gb[0].hi[0]); wbox[wid][4] = ord(ts.gb[0].hi[1]); wbox[wid][5] = ord(ts.gb[0].hi[2]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int lo[3] = {wbox[0][0], wbox[0][1], wbox[0][2]}, hi[3] = {wbox[0][3], wbox[0][4], wbox[0][5]};
+    for (int w = 1; w < kWaves; ++w)
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = min(lo[c], wbox[w][c]);
+        hi[c] = max(hi[c], wbox[w][3 + c]);
+      }
+    int c0[3], c1[3];
+    for (int c = 0; c < 3; ++c) {
+      c0[c] = max(cell_coord(unord(lo[c]), gc.lo[c], gc.inv_cs, gc.dims[c]) - gc.reach, 0);
+      c1[c] = min(cell_coord(unord(hi[c]), gc.lo[c], gc.inv_cs, gc.dims[c]) + gc.reach, gc.dims[c] - 1);
+    }
+    bmeta[0] = c0[0]; bmeta[1] = c1[0]; bmeta[2] = c0[1]; bmeta[3] = c1[1]; bmeta[4] = c0[2];
+    bmeta[5] = (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
+  }
+  __syncthreads();
+  const int bX0 = bmeta[0], bX1 = bmeta[1], bY0 = bmeta[2], bY1 = bmeta[3], bZ0 = bmeta[4];
+  const int bny = bY1 - bY0 + 1;
+  const int bnrows = bmeta[5];
+  bool block_acc = bnrows <= kBlockRows;
+  uint32_t btotal = 0;
+  if (block_acc) {
+    uint32_t rb = 0, rl = 0;
+    if (tid < bnrows) {
+      const int yy = bY0 + tid % bny, zz = bZ0 + tid / bny;
+      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
+      rb = a.cell_start[row + (uint32_t)bX0];
+      rl = a.cell_start[row + (uint32_t)bX1 + 1u] - rb;
+    }
+    const uint32_t ex = block_exclusive_scan(rl, &btotal, wsum);
+    if (tid < bnrows) {
+      brb[tid] = rb;
+      brp[tid] = ex;
+    }
+    if (tid == 0) brp[bnrows] = btotal;
+    block_acc = btotal <= (uint32_t)kAccCap;
+  }
+  if (block_acc) {
+    for (uint32_t t = tid; t < btotal; t += kBlock)
+      for (int c = 0; c < 6; ++c) acc[c][t] = 0.0f;
+  }
+  __syncthreads();
+  if (block_acc && wave_tiled) {
+    for (int r = lane; r < ts.nrows; r += 64) {
+      const int yy = ts.Y0 + r % ts.ny, zz = ts.Z0 + r / ts.ny;
+      const int br = (yy - bY0) + bny * (zz - bZ0);
+      sbase[wid][r] = brp[br] + (lds.rb[wid][r] - brb[br]);
+    }
+  }
+  wave_lds_sync();
+
+  if (!wave_tiled) {
+    if (live) adjoint_lane(a, wt, i);
+  } else {
+    const float inv_h2 = gc.inv_h2;
+    // ---- pass 1: sums and argmax (ties: smallest original index)
+    float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
+    uint32_t arg = 0xffffffffu;
+    tile_visit<1>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
+      for (uint32_t c = 0; c < nc; ++c) {
+        const float4 Q = lp[c];
+        const float4 W = lv[c];
+        const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
+        const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
+        const float w = u * u * u;
+        const uint32_t id = __float_as_uint(W.w);
+        S += w;
+        Ux = fmaf(w, W.x, Ux);
+        Uy = fmaf(w, W.y, Uy);
+        Uz = fmaf(w, W.z, Uz);
+        const bool better = (w > M) || (w == M && id < arg);
+        M = better ? w : M;
+        arg = better ? id : arg;
+      }
+    });
+    // ---- replay and pull-back; idle lanes carry a zero upstream gradient
+    const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
+    const float z0 = 0.0f;
+    Back bk = backprop(a.sc, wt, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M,
+                       live ? a.gx_out[i] : z0, live ? a.gx_out[n + i] : z0, live ? a.gx_out[2 * n + i] : z0,
+                       live ? a.gv_out[i] : z0, live ? a.gv_out[n + i] : z0, live ? a.gv_out[2 * n + i] : z0);
+    // ---- pass 2: pair gradients; LR parts summed over the wave, then over the block
+    const float k2 = -6.0f * inv_h2;  // dw/ds = -3 t^2 / h2, times 2 for ds/dX
+    const int row = lane >> 4;
+    const bool row_tail = (lane & 15) == 15;
+    // components of the twelve reduced values (reduce12 layout), per row
+    const int ca0 = row < 2 ? row : row + 1;               // r0: a0 a1 a3 a4
+    const int ca1 = (row == 0) ? 2 : (row == 1) ? 0 : (row == 2) ? 5 : 3;  // r1: a2 b0 a5 b3
+    const bool cb1 = (row == 1) || (row == 3);             //     (b entries in rows 1, 3)
+    const int ca2 = (row == 0) ? 1 : (row == 1) ? 2 : (row == 2) ? 4 : 5;  // r2: b1 b2 b4 b5
+    auto add_out = [&](int comp, uint32_t slot, uint32_t id, float v) {
+      if (block_acc) {
+        atomicAdd(&acc[comp][slot], v);
+      } else {
+        float* dst = comp < 3 ? a.g_lr_v + (int64_t)comp * nl : a.g_lr_x + (int64_t)(comp - 3) * nl;
+        unsafeAtomicAdd(dst + id, v);
+      }
+    };
+    auto pair_pass = [&](uint32_t nc, const float4* lp, const float4* lv) {
+      // two candidates per iteration; the next pair is read ahead
+      float4 QA = lp[0], WA = lv[0];
+      float4 QB = lp[nc > 1 ? 1 : 0], WB = lv[nc > 1 ? 1 : 0];
+      for (uint32_t c = 0; c < nc; c += 2) {
+        const bool has_b = c + 1 < nc;
+        const uint32_t cn = c + 2 < nc ? c + 2 : c;
+        const uint32_t cn1 = cn + 1 < nc ? cn + 1 : cn;
+        const float4 QA2 = lp[cn], WA2 = lv[cn];
+        const float4 QB2 = lp[cn1], WB2 = lv[cn1];
+        const Six va = pair_contrib(QA, WA, x, y, z, inv_h2, k2, arg, bk);
+        Six vb;
+        if (has_b) {
+          vb = pair_contrib(QB, WB, x, y, z, inv_h2, k2, arg, bk);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 6; ++q) vb.v[q] = 0.0f;
+        }
+        float r0, r1, r2;
+        reduce12(va, vb, &r0, &r1, &r2);
+        if (row_tail) {
+          const uint32_t sa = __float_as_uint(QA.w), sbb = __float_as_uint(QB.w);
+          const uint32_t ia = __float_as_uint(WA.w), ib = __float_as_uint(WB.w);
+          add_out(ca0, sa, ia, r0);
+          if (!cb1) add_out(ca1, sa, ia, r1);
+          else if (has_b) add_out(ca1, sbb, ib, r1);
+          if (has_b) add_out(ca2, sbb, ib, r2);
+        }
+        QA = QA2; WA = WA2; QB = QB2; WB = WB2;
+      }
+    };
+    if (block_acc) {
+      const uint32_t* sb = &sbase[wid][0];
+      const uint32_t* rp = &lds.rp[wid][0];
+      tile_visit<1>(ts, gc, a.lr, lane, wid, lds, pair_pass,
+                    [=](int r, uint32_t k, uint32_t, float) { return sb[r] + (k - rp[r]); });
+    } else {
+      tile_visit<1>(ts, gc, a.lr, lane, wid, lds, pair_pass);
+    }
+    if (live) {
+      a.gx_in[i] = bk.gx;
+      a.gx_in[n + i] = bk.gy;
+      a.gx_in[2 * n + i] = bk.gz;
+      a.gv_in[i] = bk.gvx;
+      a.gv_in[n + i] = bk.gvy;
+      a.gv_in[2 * n + i] = bk.gvz;
+    }
+  }
+  __syncthreads();
+  // ---- flush the block accumulator: one atomic per non-zero (slot, component)
+  if (block_acc) {
+    for (uint32_t t = tid; t < btotal; t += kBlock) {
+      int lo = 0, hi = bnrows;  // largest block row r with brp[r] <= t
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (brp[mid] <= t) lo = mid; else hi = mid;
+      }
+      const uint32_t j = brb[lo] + (t - brp[lo]);
+      const uint32_t id = __float_as_uint(a.lr[j].v.w);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const float v = acc[c][t];
+        if (v != 0.0f) {
+          float* dst = c < 3 ? a.g_lr_v + (int64_t)c * nl : a.g_lr_x + (int64_t)(c - 3) * nl;
+          unsafeAtomicAdd(dst + id, v);
+        }
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -194,7 +529,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a, WallTable wt)
 hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st) {
   if (a.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((a.n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  if (a.sc.has_rigid || !a.tiled)
+    hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  else
+    hipLaunchKernelGGL(k_adjoint_tiled, dim3(blocks), dim3(kBlock), 0, st, a, walls);
   return hipGetLastError();
 }
 

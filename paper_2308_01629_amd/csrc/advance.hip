@@ -8,6 +8,7 @@
 // each way).  Along x the cells of one (y, z) row of the stencil are adjacent
 // keys, so each row is one contiguous range of the sorted LR copy.
 #include "kernels.hpp"
+#include "tile.hpp"
 
 namespace ups {
 namespace {
@@ -18,9 +19,12 @@ struct Sums {
   uint32_t count;
 };
 
-// Walk the stencil of HR position (x, y, z); accumulate members (float32
-// predicate s < h2).  DEBUG also records member ids.
-template <bool DEBUG>
+// Walk the stencil of HR position (x, y, z) and accumulate the weighted sums
+// over candidates of positive weight.  The float32 membership predicate
+// s < h2 decides the rigid rule; DEBUG also records the member ids.
+// RIGID: the scene has rigid LR particles, so their contributions are dropped
+// when no granular LR particle is in the support.
+template <bool DEBUG, bool RIGID>
 __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __restrict__ lr,
                                        const uint32_t* __restrict__ cell_start, float x, float y,
                                        float z, uint32_t* ids, int64_t max_k) {
@@ -39,27 +43,37 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
       const uint32_t e = cell_start[row + (uint32_t)x1 + 1u];
       for (uint32_t j = b; j < e; ++j) {
         const float4 P = lr[j].p;
-        const float s = sq_dist(P.x, P.y, P.z, x, y, z);
-        if (s < gc.h2) {
+        // the same weight arithmetic, candidate order and zero test as the
+        // wave-tiled path, so a particle's sums do not depend on which path
+        // its wave takes
+        const float dx = P.x - x, dy = P.y - y, dz = P.z - z;
+        const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float t = fmaxf(fmaf(-sq, gc.inv_h2, 1.0f), 0.0f);
+        if (t > 0.0f) {
           const float4 V = lr[j].v;
-          const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
           const float w = t * t * t;
           r.S += w;
           r.Ux = fmaf(w, V.x, r.Ux);
           r.Uy = fmaf(w, V.y, r.Uy);
           r.Uz = fmaf(w, V.z, r.Uz);
           r.M = fmaxf(r.M, w);
-          r.gran |= (P.w == 0.0f);
-          if (DEBUG) {
-            if (ids != nullptr && (int64_t)r.count < max_k) ids[r.count] = __float_as_uint(V.w);
+        }
+        // support membership (the exact predicate) decides the rigid rule
+        // and the neighbour lists
+        if (DEBUG || (RIGID && !r.gran && P.w == 0.0f)) {
+          if (sq_dist(P.x, P.y, P.z, x, y, z) < gc.h2) {
+            r.gran |= (P.w == 0.0f);
+            if (DEBUG) {
+              if (ids != nullptr && (int64_t)r.count < max_k) ids[r.count] = __float_as_uint(lr[j].v.w);
+              r.count += 1u;
+            }
           }
-          r.count += 1u;
         }
       }
     }
   }
   // Rigid LR particles count only next to a granular one (Section 4).
-  if (!r.gran) {
+  if (RIGID && !r.gran) {
     r.S = 0.f;
     r.Ux = r.Uy = r.Uz = 0.f;
     r.M = 0.f;
@@ -141,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_advance(AdvanceArgs a, WallTable wt)
   const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
   const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
   uint32_t* ids = (DEBUG && a.dbg_ids != nullptr) ? a.dbg_ids + i * a.dbg_max_k : nullptr;
-  const Sums s = gather<DEBUG>(a.gc, a.lr, a.cell_start, x, y, z, ids, a.dbg_max_k);
+  const Sums s = gather<DEBUG, true>(a.gc, a.lr, a.cell_start, x, y, z, ids, a.dbg_max_k);
   bool A;
   finish(a, wt, i, x, y, z, vx, vy, vz, s.S, s.Ux, s.Uy, s.Uz, s.M, &A);
   if (DEBUG) {
@@ -151,83 +165,13 @@ __global__ __launch_bounds__(kBlock) void k_advance(AdvanceArgs a, WallTable wt)
   }
 }
 
-// ---------------------------------------------------------------------------
-// Wave-tiled gather.  A wave holds 64 consecutive HR particles, kept spatially
-// compact by the HR reorder, as G groups of 64/G lanes (G = 1, 2 or 4; a group
-// is one or more 16-lane DPP rows).
-// The LR particles of the cells in the union of the lanes' stencils are
-// streamed through the wave once; each is kept in a group's LDS list when its
-// distance to that group's bounding box is below the support.  Every lane
-// then walks its group's list with (four-address) broadcast LDS reads:
-//     d = X_j - x_i,  t = 1 - |d|^2 / h^2,  w = max(t, 0)^3.
-// Lists are padded to a common length with far-away dummies (w = 0).
-// ---------------------------------------------------------------------------
-
-constexpr int kWaves = kBlock / 64;
-constexpr int kListBytes = 8192;  // LDS per wave for the candidate lists (32 B per entry)
-
-// Order-preserving map float -> int (non-NaN), an involution.
-__device__ __forceinline__ int ord(float f) {
-  const int i = __float_as_int(f);
-  return i ^ ((i >> 31) & 0x7fffffff);
-}
-__device__ __forceinline__ float unord(int i) { return __int_as_float(i ^ ((i >> 31) & 0x7fffffff)); }
-
-// Min / max over each 16-lane row; lane 15 of the row holds the result.
-__device__ __forceinline__ int row_min(int v) {
-  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x111, 0xf, 0xf, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x112, 0xf, 0xf, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x114, 0xf, 0xf, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x118, 0xf, 0xf, false));
-  return v;
-}
-__device__ __forceinline__ int row_max(int v) {
-  const int lo = (int)0x80000000;
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x111, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x112, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x118, 0xf, 0xf, false));
-  return v;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
-  return v;
-}
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-struct Box {
-  float lo[3], hi[3];
-};
-
-// Squared distance from point p to box b (0 inside).
-__device__ __forceinline__ float box_dist2(const Box& b, float px, float py, float pz) {
-  const float dx = fmaxf(fmaxf(b.lo[0] - px, px - b.hi[0]), 0.0f);
-  const float dy = fmaxf(fmaxf(b.lo[1] - py, py - b.hi[1]), 0.0f);
-  const float dz = fmaxf(fmaxf(b.lo[2] - pz, pz - b.hi[2]), 0.0f);
-  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-}
-
+// Wave-tiled gather (tile.hpp): every lane walks its group's LDS candidate
+// list,   d = X_j - x_i,  t = 1 - |d|^2 / h^2,  w = max(t, 0)^3,
+// accumulating S, U, M; the per-lane stencil walk covers spread-out waves.
 template <bool RIGID, int G>
 __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
-  constexpr int kGroups = G;
-  constexpr int kListCap = kListBytes / 32 / G;      // entries per group list
-  constexpr int kRowsPerGroup = 4 / G;               // 16-lane rows per group
-  __shared__ float4 s_p[kWaves][kGroups][kListCap];  // (X_j, sorted index | rigid << 31)
-  __shared__ float4 s_v[kWaves][kGroups][kListCap];  // (V_j, unused)
-  __shared__ uint32_t s_rb[kWaves][64];              // first sorted index of each stencil row
-  __shared__ uint32_t s_rp[kWaves][65];              // exclusive prefix of row lengths
-
+  __shared__ TileLDS<G> lds;
   const int lane = threadIdx.x & 63;
-  const int grp = lane / (64 / G);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t n = a.n;
   const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -237,122 +181,16 @@ __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTab
   const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
   const GridConst& gc = a.gc;
 
-  // group boxes (per 16-lane row), then the wave box
-  const int e0 = row_min(ord(x)), e1 = row_min(ord(y)), e2 = row_min(ord(z));
-  const int f0 = row_max(ord(x)), f1 = row_max(ord(y)), f2 = row_max(ord(z));
-  Box gb[kGroups];
-  int w0x = 0x7fffffff, w0y = 0x7fffffff, w0z = 0x7fffffff;
-  int w1x = (int)0x80000000, w1y = (int)0x80000000, w1z = (int)0x80000000;
-#pragma unroll
-  for (int g = 0; g < kGroups; ++g) {
-    int a0 = 0x7fffffff, a1 = 0x7fffffff, a2 = 0x7fffffff;
-    int b0 = (int)0x80000000, b1 = (int)0x80000000, b2 = (int)0x80000000;
-#pragma unroll
-    for (int r = 0; r < kRowsPerGroup; ++r) {
-      const int l = 16 * (g * kRowsPerGroup + r) + 15;
-      a0 = min(a0, __builtin_amdgcn_readlane(e0, l));
-      a1 = min(a1, __builtin_amdgcn_readlane(e1, l));
-      a2 = min(a2, __builtin_amdgcn_readlane(e2, l));
-      b0 = max(b0, __builtin_amdgcn_readlane(f0, l));
-      b1 = max(b1, __builtin_amdgcn_readlane(f1, l));
-      b2 = max(b2, __builtin_amdgcn_readlane(f2, l));
-    }
-    gb[g].lo[0] = unord(a0); gb[g].lo[1] = unord(a1); gb[g].lo[2] = unord(a2);
-    gb[g].hi[0] = unord(b0); gb[g].hi[1] = unord(b1); gb[g].hi[2] = unord(b2);
-    w0x = min(w0x, a0); w0y = min(w0y, a1); w0z = min(w0z, a2);
-    w1x = max(w1x, b0); w1y = max(w1y, b1); w1z = max(w1z, b2);
-  }
-  // cell coordinates are monotone in position: the cells of the wave box
-  // corners bound every lane's cell
-  const int R = gc.reach;
-  const int X0 = max(cell_coord(unord(w0x), gc.lo[0], gc.inv_cs, gc.dims[0]) - R, 0);
-  const int X1 = min(cell_coord(unord(w1x), gc.lo[0], gc.inv_cs, gc.dims[0]) + R, gc.dims[0] - 1);
-  const int Y0 = max(cell_coord(unord(w0y), gc.lo[1], gc.inv_cs, gc.dims[1]) - R, 0);
-  const int Y1 = min(cell_coord(unord(w1y), gc.lo[1], gc.inv_cs, gc.dims[1]) + R, gc.dims[1] - 1);
-  const int Z0 = max(cell_coord(unord(w0z), gc.lo[2], gc.inv_cs, gc.dims[2]) - R, 0);
-  const int Z1 = min(cell_coord(unord(w1z), gc.lo[2], gc.inv_cs, gc.dims[2]) + R, gc.dims[2] - 1);
-  const int ny = Y1 - Y0 + 1;
-  const int nrows = ny * (Z1 - Z0 + 1);
-
   float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
-  bool gran = !RIGID;
-  if (nrows > 64) {
+  const TileSetup<G> ts = tile_setup<G>(gc, a.cell_start, x, y, z, lane, wid, lds);
+  if (ts.nrows > kMaxRows || ts.total > (uint32_t)a.tile_max) {
     // spread-out wave: every lane walks its own stencil
-    const Sums s = gather<false>(gc, a.lr, a.cell_start, x, y, z, nullptr, 0);
+    const Sums s = gather<false, RIGID>(gc, a.lr, a.cell_start, x, y, z, nullptr, 0);
     S = s.S; Ux = s.Ux; Uy = s.Uy; Uz = s.Uz; M = s.M;
-    gran = true;  // gather() already applied the rigid rule
   } else {
-    // one stencil row per lane: sorted range [rb, rb + rl)
-    uint32_t rb = 0, rl = 0;
-    if (lane < nrows) {
-      const int yy = Y0 + lane % ny, zz = Z0 + lane / ny;
-      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
-      rb = a.cell_start[row + (uint32_t)X0];
-      rl = a.cell_start[row + (uint32_t)X1 + 1u] - rb;
-    }
-    const uint32_t incl = wave_incl_scan(rl, lane);
-    const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
-    s_rb[wid][lane] = rb;
-    s_rp[wid][lane + 1] = incl;
-    if (lane == 0) s_rp[wid][0] = 0u;
-    wave_lds_sync();
-
     const float inv_h2 = gc.inv_h2;
-    const float cull2 = gc.h2 * 1.001f;
-    const float4 far_p = make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f);
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-
-    uint32_t cnt[kGroups];
-#pragma unroll
-    for (int g = 0; g < kGroups; ++g) cnt[g] = 0u;
-    for (uint32_t k0 = 0; k0 < total; k0 += 64u) {
-      // -- stage: one candidate per lane, kept per group
-      const uint32_t k = k0 + (uint32_t)lane;
-      bool keep[kGroups];
-#pragma unroll
-      for (int g = 0; g < kGroups; ++g) keep[g] = false;
-      float4 P = zero4, V = zero4;
-      uint32_t j = 0;
-      if (k < total) {
-        int lo = 0, hi = nrows;  // largest row r with s_rp[r] <= k
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_rp[wid][mid] <= k) lo = mid; else hi = mid;
-        }
-        j = s_rb[wid][lo] + (k - s_rp[wid][lo]);
-        P = a.lr[j].p;
-        V = a.lr[j].v;
-#pragma unroll
-        for (int g = 0; g < kGroups; ++g) keep[g] = box_dist2(gb[g], P.x, P.y, P.z) <= cull2;
-      }
-      const float4 pj = make_float4(P.x, P.y, P.z, __uint_as_float(j | (P.w != 0.0f ? 0x80000000u : 0u)));
-      uint32_t nmax = 0;
-#pragma unroll
-      for (int g = 0; g < kGroups; ++g) {
-        const uint64_t m = __ballot(keep[g]);
-        if (keep[g]) {
-          const uint32_t pos = cnt[g] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          s_p[wid][g][pos] = pj;
-          s_v[wid][g][pos] = V;
-        }
-        cnt[g] += (uint32_t)__popcll(m);
-        nmax = max(nmax, cnt[g]);
-      }
-      if (nmax + 64u <= (uint32_t)kListCap && k0 + 64u < total) continue;  // room for another pass
-      // pad the shorter lists with far-away dummies
-#pragma unroll
-      for (int g = 0; g < kGroups; ++g) {
-        for (uint32_t q = cnt[g] + (uint32_t)lane; q < nmax; q += 64u) {
-          s_p[wid][g][q] = far_p;
-          s_v[wid][g][q] = zero4;
-        }
-      }
-      wave_lds_sync();
-      // -- accumulate: each lane walks its group's list
-      const uint32_t nc = __builtin_amdgcn_readfirstlane(nmax);
-      const float4* lp = &s_p[wid][grp][0];
-      const float4* lv = &s_v[wid][grp][0];
+    bool gran = !RIGID;
+    tile_visit<G>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
       for (uint32_t c = 0; c < nc; ++c) {
         const float4 Q = lp[c];
         const float4 W = lv[c];
@@ -371,13 +209,8 @@ __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTab
           if ((bits & 0x80000000u) == 0u && Q.x < 1.0e38f) gran |= sq_dist(Q.x, Q.y, Q.z, x, y, z) < gc.h2;
         }
       }
-#pragma unroll
-      for (int g = 0; g < kGroups; ++g) cnt[g] = 0u;
-      wave_lds_sync();
-    }
-    if (RIGID && !gran) {
-      S = Ux = Uy = Uz = M = 0.f;
-    }
+    });
+    if (RIGID && !gran) S = Ux = Uy = Uz = M = 0.f;
   }
   if (live) {
     bool A;

@@ -230,20 +230,35 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const float* __restrict
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// Interleave the low two bits of three sub-cell indices (Morton order).
-__device__ __forceinline__ uint32_t morton2(uint32_t a, uint32_t b, uint32_t c) {
+// Fine coordinate of one axis: cell * sub + sub-cell index, from the same
+// float32 arithmetic as the cell coordinate.
+__device__ __forceinline__ uint32_t fine_coord(float x, float lo, float inv_cs, int G, int sub) {
+  const float t = (x - lo) * inv_cs;
+  const float c = fminf(fmaxf(floorf(t), 0.0f), (float)(G - 1));
+  const float f = fminf(fmaxf(floorf((t - c) * (float)sub), 0.0f), (float)(sub - 1));
+  return (uint32_t)c * (uint32_t)sub + (uint32_t)f;
+}
+
+// Morton (Z-order) code of fine coordinates with bx, by, bz significant bits
+// per axis: bit b of each axis that has one, x first, low bits first.
+__device__ __forceinline__ uint32_t morton3(uint32_t fx, uint32_t fy, uint32_t fz, int bx, int by, int bz) {
+  uint32_t key = 0u;
+  int pos = 0;
+  const int bmax = max(bx, max(by, bz));
+  for (int b = 0; b < bmax; ++b) {
+    if (b < bx) key |= ((fx >> b) & 1u) << pos++;
+    if (b < by) key |= ((fy >> b) & 1u) << pos++;
+    if (b < bz) key |= ((fz >> b) & 1u) << pos++;
+  }
+  return key;
+}
+
+__device__ __forceinline__ uint32_t morton_sub(uint32_t a, uint32_t b, uint32_t c) {
   return (a & 1u) | ((b & 1u) << 1) | ((c & 1u) << 2) | ((a & 2u) << 2) | ((b & 2u) << 3) | ((c & 2u) << 4);
 }
 
-__device__ __forceinline__ uint32_t sub_index(float x, float lo, float inv_cs, int G, int sub) {
-  const float t = (x - lo) * inv_cs;
-  const float c = fminf(fmaxf(floorf(t), 0.0f), (float)(G - 1));
-  const float f = floorf((t - c) * (float)sub);
-  return (uint32_t)fminf(fmaxf(f, 0.0f), (float)(sub - 1));
-}
-
 __global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const float* __restrict__ x,
-                                                          int64_t n, int sub,
+                                                          int64_t n, int sub, int mode, int bx, int by, int bz,
                                                           uint32_t* __restrict__ keys,
                                                           uint32_t* __restrict__ slot,
                                                           uint32_t* __restrict__ counts) {
@@ -251,11 +266,17 @@ __global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const fl
   const bool valid = i < n;
   const int64_t ii = valid ? i : 0;
   const float px = x[ii], py = x[n + ii], pz = x[2 * n + ii];
-  const uint32_t cell = cell_key(gc, px, py, pz);
-  const uint32_t sx = sub_index(px, gc.lo[0], gc.inv_cs, gc.dims[0], sub);
-  const uint32_t sy = sub_index(py, gc.lo[1], gc.inv_cs, gc.dims[1], sub);
-  const uint32_t sz = sub_index(pz, gc.lo[2], gc.inv_cs, gc.dims[2], sub);
-  const uint32_t k = cell * (uint32_t)(sub * sub * sub) + morton2(sx, sy, sz);
+  const uint32_t fx = fine_coord(px, gc.lo[0], gc.inv_cs, gc.dims[0], sub);
+  const uint32_t fy = fine_coord(py, gc.lo[1], gc.inv_cs, gc.dims[1], sub);
+  const uint32_t fz = fine_coord(pz, gc.lo[2], gc.inv_cs, gc.dims[2], sub);
+  uint32_t k;
+  if (mode == 1) {
+    k = morton3(fx, fy, fz, bx, by, bz);
+  } else {
+    const uint32_t us = (uint32_t)sub;
+    const uint32_t cell = (fx / us) + (uint32_t)gc.dims[0] * ((fy / us) + (uint32_t)gc.dims[1] * (fz / us));
+    k = cell * us * us * us + morton_sub(fx % us, fy % us, fz % us);
+  }
   const uint32_t sl = claim_slot(k, valid, counts);
   if (valid) {
     keys[i] = k;
@@ -294,12 +315,14 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
 }
 
 hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
-                          float* out_v, int64_t n_hr, int sub, const HRSortScratch& s,
+                          float* out_v, int64_t n_hr, int sub, int mode, const HRSortScratch& s,
                           int32_t* perm_out, hipStream_t st) {
   if (n_hr == 0) return hipSuccess;
-  const int64_t n_bins = s.n_cells * sub * sub * sub;
+  int bits[3];
+  for (int a = 0; a < 3; ++a) bits[a] = sort_bits((int64_t)gc.dims[a] * sub);
+  const int64_t n_bins = sort_bins(gc.dims, sub, mode);
   hipLaunchKernelGGL(k_hr_keys_count, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, gc, hr_x, n_hr,
-                     sub, s.keys, s.slot, s.counts);
+                     sub, mode, bits[0], bits[1], bits[2], s.keys, s.slot, s.counts);
   hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, s.ticket, st);
   if (e != hipSuccess) return e;
   const bool in_place = out_x == hr_x || out_v == hr_v;
@@ -311,6 +334,37 @@ hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* h
     hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.x, s.v, s.perm,
                        n_hr, out_x, out_v, perm_out);
   }
+  return hipGetLastError();
+}
+
+// Permute up to two [3][n] arrays: gather (dst[:, i] = src[:, perm[i]]) or
+// scatter (dst[:, perm[i]] = src[:, i]); indices outside [0, n) are skipped
+// and raise *bad.
+template <bool SCATTER>
+__global__ __launch_bounds__(kBlock) void k_permute(const float* __restrict__ a, const float* __restrict__ b,
+                                                    float* __restrict__ ao, float* __restrict__ bo, int64_t n,
+                                                    const int32_t* __restrict__ perm, uint32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t p = perm[i];
+  if (p < 0 || (int64_t)p >= n) {
+    atomicOr(bad, 1u);
+    return;
+  }
+  const int64_t src = SCATTER ? i : (int64_t)p;
+  const int64_t dst = SCATTER ? (int64_t)p : i;
+  for (int c = 0; c < 3; ++c) ao[c * n + dst] = a[c * n + src];
+  if (b != nullptr)
+    for (int c = 0; c < 3; ++c) bo[c * n + dst] = b[c * n + src];
+}
+
+hipError_t launch_permute(const float* a, const float* b, float* ao, float* bo, int64_t n, const int32_t* perm,
+                          int scatter, uint32_t* bad, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (scatter)
+    hipLaunchKernelGGL(k_permute<true>, dim3(blocks_for(n)), dim3(kBlock), 0, st, a, b, ao, bo, n, perm, bad);
+  else
+    hipLaunchKernelGGL(k_permute<false>, dim3(blocks_for(n)), dim3(kBlock), 0, st, a, b, ao, bo, n, perm, bad);
   return hipGetLastError();
 }
 

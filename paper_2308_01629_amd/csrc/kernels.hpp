@@ -24,8 +24,9 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
                              const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
                              const GridScratch& s, hipStream_t st);
 
-// HR reorder by (cell, Morton order of sub x sub x sub sub-cells), so that a
-// wave's 64 consecutive particles sit in a compact box.
+// HR reorder by the Morton (Z-order) code of fine cells (grid cells split into
+// sub^3 sub-cells), so that a wave's 64 consecutive particles sit in a compact
+// box and neighbouring waves are neighbours in space.
 struct HRSortScratch {
   uint32_t* keys;       // [max_hr]
   uint32_t* slot;       // [max_hr]
@@ -39,9 +40,25 @@ struct HRSortScratch {
   int64_t n_cells;      // grid cells
   int max_sub;          // largest sub-cell count per axis the bins are sized for (4, 2 or 1)
 };
+
+// Significant bits of a fine coordinate in [0, n).
+inline int sort_bits(int64_t n) {
+  int b = 0;
+  while (((int64_t)1 << b) < n) ++b;
+  return b;
+}
+// Bins of the HR reorder for a sub-cell count: mode 1 (global Morton code of
+// fine cells) 2^(bx + by + bz); mode 0 (grid cell, then Morton order of its
+// sub-cells) n_cells * sub^3.
+inline int64_t sort_bins(const int dims[3], int sub, int mode) {
+  if (mode == 0) return (int64_t)dims[0] * dims[1] * dims[2] * sub * sub * sub;
+  int b = 0;
+  for (int a = 0; a < 3; ++a) b += sort_bits((int64_t)dims[a] * sub);
+  return (int64_t)1 << b;
+}
 // out_x / out_v may alias hr_x / hr_v (then the permuted copy goes through scratch).
 hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
-                          float* out_v, int64_t n_hr, int sub, const HRSortScratch& s,
+                          float* out_v, int64_t n_hr, int sub, int mode, const HRSortScratch& s,
                           int32_t* perm_out, hipStream_t st);
 
 // a6: fused gather + blend + integrate + walls.
@@ -60,7 +77,8 @@ struct AdvanceArgs {
   uint32_t* dbg_ids;
   int64_t dbg_max_k;
   uint8_t* dbg_branch;
-  int groups;  // lane groups per wave in the tiled gather: 1, 2 or 4 (a tuning knob)
+  int groups;    // lane groups per wave in the tiled gather: 1, 2 or 4 (a tuning knob)
+  int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
 };
 hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool debug, hipStream_t st);
 
@@ -80,10 +98,14 @@ struct AdjointArgs {
   float* g_lr_v;
   int64_t n;
   int64_t n_lr;
+  int tiled;     // 1: wave-tiled kernel (non-rigid scenes), 0: one particle per lane
+  int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
 };
 hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st);
 
 // VALIDATE flag: sets *flag to 1 if any of the n floats is NaN or Inf.
 hipError_t launch_check_finite(const float* p, int64_t n, uint32_t* flag, hipStream_t st);
+hipError_t launch_permute(const float* a, const float* b, float* ao, float* bo, int64_t n, const int32_t* perm,
+                          int scatter, uint32_t* bad, hipStream_t st);
 
 }  // namespace ups

@@ -263,6 +263,9 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   h->p.walls = nullptr;
   compute_grid(&h->p, &h->gi, &why);
   h->tune.gather_groups = 1;
+  h->tune.adjoint_tiled = 1;
+  h->tune.tile_max = 512;
+  h->tune.adjoint_tile_max = 256;
   h->n_cells = h->gi.n_cells;
   h->n_chunks = (int)((h->n_cells + kScanChunk - 1) / kScanChunk);
   if (hipGetDevice(&h->device) != hipSuccess) {
@@ -288,13 +291,20 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->hs.x, 3 * nh)
   ALLOC(h->hs.v, 3 * nh)
   ALLOC(h->hs.perm, nh)
-  // HR sort bins: sub^3 Morton sub-cells per grid cell, at most 2^24 bins
+  // HR reorder bins: Morton codes of fine cells, at most 2^24 bins
   h->hs.n_cells = h->n_cells;
+  // both key modes must fit the bins allocated for max_sub
+  auto bins_for = [&](int sub) {
+    const int64_t b0 = sort_bins(h->gi.dims, sub, 0), b1 = sort_bins(h->gi.dims, sub, 1);
+    return b0 > b1 ? b0 : b1;
+  };
   h->hs.max_sub = 4;
-  while (h->hs.max_sub > 1 && h->n_cells * h->hs.max_sub * h->hs.max_sub * h->hs.max_sub > ((int64_t)1 << 24))
-    h->hs.max_sub /= 2;
-  const int64_t n_bins = nh > 0 ? h->n_cells * h->hs.max_sub * h->hs.max_sub * h->hs.max_sub : 1;
+  while (h->hs.max_sub > 1 && bins_for(h->hs.max_sub) > ((int64_t)1 << 24)) h->hs.max_sub /= 2;
+  const bool can_sort = bins_for(h->hs.max_sub) <= ((int64_t)1 << 24);
+  if (!can_sort) h->hs.max_sub = 0;  // grid too fine for the reorder: sort_hr reports GRID_TOO_LARGE
+  const int64_t n_bins = (nh > 0 && can_sort) ? bins_for(h->hs.max_sub) : 1;
   h->tune.sort_sub = h->hs.max_sub >= 2 ? 2 : 1;
+  h->tune.sort_mode = 0;
   ALLOC(h->hs.counts, n_bins)
   ALLOC(h->hs.local, n_bins)
   ALLOC(h->hs.chunk_sum, n_bins / kScanChunk + 2)
@@ -409,6 +419,7 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
   a.dbg_max_k = max_k;
   a.dbg_branch = branch;
   a.groups = h->tune.gather_groups;
+  a.tile_max = h->tune.tile_max;
   const bool timed = h->timing && !debug && n_hr > 0;
   hipError_t e = hipSuccess;
   int slot = 0;
@@ -482,6 +493,8 @@ int upsample_step_backward(upsample_handle h, const float* lr_x, const float* lr
   a.g_lr_v = g_lr_v;
   a.n = n_hr;
   a.n_lr = n_lr;
+  a.tiled = h->tune.adjoint_tiled;
+  a.tile_max = h->tune.adjoint_tile_max;
   hipError_t e = launch_adjoint(a, wall_table(h), st);
   if (e != hipSuccess) return hip_fail(h, e, "step_backward");
   return UPSAMPLE_OK;
@@ -499,18 +512,50 @@ int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, fl
   int rc = check_device(h);
   if (rc != UPSAMPLE_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
+  if (h->hs.max_sub == 0)
+    return fail(h, UPSAMPLE_ERR_GRID_TOO_LARGE, "grid too fine for the HR reorder (more than 2^24 Morton bins)");
   if (h->hr_counts_dirty) {
-    const int64_t n_bins = h->n_cells * h->hs.max_sub * h->hs.max_sub * h->hs.max_sub;
-    hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)n_bins, st);
+    const int64_t b0 = sort_bins(h->gi.dims, h->hs.max_sub, 0), b1 = sort_bins(h->gi.dims, h->hs.max_sub, 1);
+    hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)(b0 > b1 ? b0 : b1), st);
     if (e == hipSuccess) e = hipMemsetAsync(h->hs.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "sort_hr");
     h->hr_counts_dirty = false;
   }
   hipError_t e = launch_sort_hr(grid_const(h), hr_x, hr_v, hr_x_out, hr_v_out, n_hr, h->tune.sort_sub,
-                                h->hs, perm_out, st);
+                                h->tune.sort_mode, h->hs, perm_out, st);
   if (e != hipSuccess) {
     h->hr_counts_dirty = true;
     return hip_fail(h, e, "sort_hr");
+  }
+  return UPSAMPLE_OK;
+}
+
+int upsample_permute(upsample_handle h, const float* a, const float* b, float* a_out, float* b_out,
+                     int64_t n, const int32_t* perm, int mode, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n < 0");
+  if (mode != UPSAMPLE_PERMUTE_GATHER && mode != UPSAMPLE_PERMUTE_SCATTER)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "mode must be UPSAMPLE_PERMUTE_GATHER or UPSAMPLE_PERMUTE_SCATTER");
+  if (n > 0 && (a == nullptr || a_out == nullptr || perm == nullptr))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "a, a_out or perm is NULL");
+  if ((b == nullptr) != (b_out == nullptr)) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "b and b_out: both or neither");
+  if (n > 0 && (a_out == a || (b != nullptr && (b_out == b || b_out == a || a_out == b))))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "outputs must not alias inputs");
+  int rc = check_device(h);
+  if (rc != UPSAMPLE_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const bool validate = (h->p.flags & UPSAMPLE_FLAG_VALIDATE) != 0u;
+  hipError_t e = hipSuccess;
+  if (validate) e = hipMemsetAsync(h->finite_flag, 0, sizeof(uint32_t), st);
+  if (e == hipSuccess)
+    e = launch_permute(a, b, a_out, b_out, n, perm, mode == UPSAMPLE_PERMUTE_SCATTER ? 1 : 0, h->finite_flag, st);
+  if (e != hipSuccess) return hip_fail(h, e, "permute");
+  if (validate) {
+    uint32_t bad = 0;
+    e = hipMemcpyAsync(&bad, h->finite_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(h, e, "permute");
+    if (bad != 0u) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "perm holds an index outside [0, n)");
   }
   return UPSAMPLE_OK;
 }
@@ -548,6 +593,12 @@ int upsample_set_tuning(upsample_handle h, const upsample_tuning* t) {
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "gather_groups must be 1, 2 or 4");
   if (t->sort_sub != 1 && t->sort_sub != 2 && t->sort_sub != 4)
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_sub must be 1, 2 or 4");
+  if (t->sort_mode != 0 && t->sort_mode != 1)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_mode must be 0 or 1");
+  if (t->tile_max < 0 || t->adjoint_tile_max < 0)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "tile_max must be >= 0");
+  if (t->adjoint_tiled != 0 && t->adjoint_tiled != 1)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "adjoint_tiled must be 0 or 1");
   if (t->sort_sub > h->hs.max_sub)
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_sub exceeds the bins allocated for this grid");
   h->tune = *t;

@@ -1,0 +1,236 @@
+// Wave tiling shared by the step kernel and its adjoint.
+//
+// A wave holds 64 consecutive HR particles, kept spatially compact by the HR
+// reorder, as G groups of 64/G lanes (G = 1, 2 or 4; a group is one or more
+// 16-lane DPP rows).  tile_setup() reduces the lanes' positions to per-group
+// bounding boxes and lists the (y, z) rows of the union of the lanes' cell
+// stencils; tile_visit() streams the LR particles of those rows through the
+// wave (one candidate per lane, a binary search over the row prefix sums) and
+// keeps a candidate in a group's LDS list when its distance to the group's box
+// is below the support (a conservative test: every LR particle within the
+// support of some lane of the group is kept).  Lists are handed to the caller's
+// visitor in chunks, padded to a common length with far-away dummies whose
+// weight is exactly 0, so every lane of the wave walks the same number of
+// entries with broadcast LDS reads.
+#pragma once
+
+#include "common.hpp"
+
+namespace ups {
+
+constexpr int kWaves = kBlock / 64;
+constexpr int kListBytes = 8192;  // LDS per wave for the candidate lists (32 B per entry)
+constexpr int kMaxRows = 256;     // stencil rows of one wave (four per lane); more: per-lane walk
+
+// Order-preserving map float -> int (non-NaN); an involution.
+__device__ __forceinline__ int ord(float f) {
+  const int i = __float_as_int(f);
+  return i ^ ((i >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float unord(int i) { return __int_as_float(i ^ ((i >> 31) & 0x7fffffff)); }
+
+// Min / max over each 16-lane row; lane 15 of the row holds the result.
+__device__ __forceinline__ int row_min(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x111, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x112, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x114, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x118, 0xf, 0xf, false));
+  return v;
+}
+__device__ __forceinline__ int row_max(int v) {
+  const int lo = (int)0x80000000;
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x118, 0xf, 0xf, false));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Box {
+  float lo[3], hi[3];
+};
+
+// Squared distance from point p to box b (0 inside).
+__device__ __forceinline__ float box_dist2(const Box& b, float px, float py, float pz) {
+  const float dx = fmaxf(fmaxf(b.lo[0] - px, px - b.hi[0]), 0.0f);
+  const float dy = fmaxf(fmaxf(b.lo[1] - py, py - b.hi[1]), 0.0f);
+  const float dz = fmaxf(fmaxf(b.lo[2] - pz, pz - b.hi[2]), 0.0f);
+  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+template <int G, int Cap = kListBytes / 32 / G>
+struct TileLDS {
+  static constexpr int kCap = Cap;  // entries per group list
+  float4 p[kWaves][G][kCap];  // (X_j, sorted index | rigid << 31)
+  float4 v[kWaves][G][kCap];  // (V_j, original index as bits)
+  uint32_t rb[kWaves][kMaxRows];      // first sorted index of each stencil row
+  uint32_t rp[kWaves][kMaxRows + 1];  // exclusive prefix of row lengths
+};
+
+template <int G>
+struct TileSetup {
+  Box gb[G];
+  int nrows;       // > kMaxRows: the wave is too spread out for a shared list
+  uint32_t total;  // candidates streamed (sum of row lengths)
+  int X0, Y0, Z0, ny;  // first cell of the rows; rows run y-fastest
+};
+
+// Group boxes, stencil rows and their prefix sums (rows only when nrows <= kMaxRows).
+template <int G, class L>
+__device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
+                                                   const uint32_t* __restrict__ cell_start, float x,
+                                                   float y, float z, int lane, int wid, L& lds) {
+  constexpr int kRowsPerGroup = 4 / G;
+  TileSetup<G> ts;
+  const int e0 = row_min(ord(x)), e1 = row_min(ord(y)), e2 = row_min(ord(z));
+  const int f0 = row_max(ord(x)), f1 = row_max(ord(y)), f2 = row_max(ord(z));
+  int w0x = 0x7fffffff, w0y = 0x7fffffff, w0z = 0x7fffffff;
+  int w1x = (int)0x80000000, w1y = (int)0x80000000, w1z = (int)0x80000000;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    int a0 = 0x7fffffff, a1 = 0x7fffffff, a2 = 0x7fffffff;
+    int b0 = (int)0x80000000, b1 = (int)0x80000000, b2 = (int)0x80000000;
+#pragma unroll
+    for (int r = 0; r < kRowsPerGroup; ++r) {
+      const int l = 16 * (g * kRowsPerGroup + r) + 15;
+      a0 = min(a0, __builtin_amdgcn_readlane(e0, l));
+      a1 = min(a1, __builtin_amdgcn_readlane(e1, l));
+      a2 = min(a2, __builtin_amdgcn_readlane(e2, l));
+      b0 = max(b0, __builtin_amdgcn_readlane(f0, l));
+      b1 = max(b1, __builtin_amdgcn_readlane(f1, l));
+      b2 = max(b2, __builtin_amdgcn_readlane(f2, l));
+    }
+    ts.gb[g].lo[0] = unord(a0); ts.gb[g].lo[1] = unord(a1); ts.gb[g].lo[2] = unord(a2);
+    ts.gb[g].hi[0] = unord(b0); ts.gb[g].hi[1] = unord(b1); ts.gb[g].hi[2] = unord(b2);
+    w0x = min(w0x, a0); w0y = min(w0y, a1); w0z = min(w0z, a2);
+    w1x = max(w1x, b0); w1y = max(w1y, b1); w1z = max(w1z, b2);
+  }
+  // Cell coordinates are monotone in position: the cells of the wave box
+  // corners bound every lane's cell, so these rows hold every lane's stencil.
+  const int R = gc.reach;
+  const int X0 = max(cell_coord(unord(w0x), gc.lo[0], gc.inv_cs, gc.dims[0]) - R, 0);
+  const int X1 = min(cell_coord(unord(w1x), gc.lo[0], gc.inv_cs, gc.dims[0]) + R, gc.dims[0] - 1);
+  const int Y0 = max(cell_coord(unord(w0y), gc.lo[1], gc.inv_cs, gc.dims[1]) - R, 0);
+  const int Y1 = min(cell_coord(unord(w1y), gc.lo[1], gc.inv_cs, gc.dims[1]) + R, gc.dims[1] - 1);
+  const int Z0 = max(cell_coord(unord(w0z), gc.lo[2], gc.inv_cs, gc.dims[2]) - R, 0);
+  const int Z1 = min(cell_coord(unord(w1z), gc.lo[2], gc.inv_cs, gc.dims[2]) + R, gc.dims[2] - 1);
+  const int ny = Y1 - Y0 + 1;
+  ts.nrows = ny * (Z1 - Z0 + 1);
+  ts.total = 0u;
+  ts.X0 = X0;
+  ts.Y0 = Y0;
+  ts.Z0 = Z0;
+  ts.ny = ny;
+  if (ts.nrows > kMaxRows) return ts;
+  // rows r = lane + 64 q, q = 0..3: four wave scans in row order
+  uint32_t carry = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxRows / 64; ++q) {
+    if (64 * q >= ts.nrows) break;
+    const int r = lane + 64 * q;
+    uint32_t rb = 0, rl = 0;
+    if (r < ts.nrows) {
+      const int yy = Y0 + r % ny, zz = Z0 + r / ny;
+      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
+      rb = cell_start[row + (uint32_t)X0];
+      rl = cell_start[row + (uint32_t)X1 + 1u] - rb;
+    }
+    const uint32_t incl = wave_incl_scan(rl, lane) + carry;
+    lds.rb[wid][r] = rb;
+    lds.rp[wid][r + 1] = incl;
+    carry = __builtin_amdgcn_readlane(incl, 63);
+  }
+  ts.total = carry;
+  if (lane == 0) lds.rp[wid][0] = 0u;
+  wave_lds_sync();
+  return ts;
+}
+
+// Default tag stored with a candidate: sorted index | rigid << 31.
+struct SortedTag {
+  __device__ __forceinline__ uint32_t operator()(int /*row*/, uint32_t /*k*/, uint32_t j, float flag) const {
+    return j | (flag != 0.0f ? 0x80000000u : 0u);
+  }
+};
+
+// Stream the candidates and hand the LDS lists to visit(nc, p_list, v_list)
+// in chunks; p_list / v_list point at this lane's group list.  tag(row, k, j,
+// flag) gives the 32 bits stored in the .w of the position entry.
+template <int G, class L, class Visit, class Tag = SortedTag>
+__device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridConst& gc,
+                                           const LRPoint* __restrict__ lr, int lane, int wid,
+                                           L& lds, Visit&& visit, Tag tag = Tag()) {
+  constexpr int kCap = L::kCap;
+  const int grp = lane / (64 / G);
+  const float cull2 = gc.h2 * 1.001f;
+  const float4 far_p = make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f);
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint32_t cnt[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) cnt[g] = 0u;
+  for (uint32_t k0 = 0; k0 < ts.total; k0 += 64u) {
+    const uint32_t k = k0 + (uint32_t)lane;
+    bool keep[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) keep[g] = false;
+    float4 P = zero4, V = zero4;
+    uint32_t bits = 0;
+    if (k < ts.total) {
+      int lo = 0, hi = ts.nrows;  // largest row r with rp[r] <= k
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (lds.rp[wid][mid] <= k) lo = mid; else hi = mid;
+      }
+      const uint32_t j = lds.rb[wid][lo] + (k - lds.rp[wid][lo]);
+      P = lr[j].p;
+      V = lr[j].v;
+      bits = tag(lo, k, j, P.w);
+#pragma unroll
+      for (int g = 0; g < G; ++g) keep[g] = box_dist2(ts.gb[g], P.x, P.y, P.z) <= cull2;
+    }
+    const float4 pj = make_float4(P.x, P.y, P.z, __uint_as_float(bits));
+    uint32_t nmax = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint64_t m = __ballot(keep[g]);
+      if (keep[g]) {
+        const uint32_t pos = cnt[g] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        lds.p[wid][g][pos] = pj;
+        lds.v[wid][g][pos] = V;
+      }
+      cnt[g] += (uint32_t)__popcll(m);
+      nmax = max(nmax, cnt[g]);
+    }
+    if (nmax + 64u <= (uint32_t)kCap && k0 + 64u < ts.total) continue;  // room for another pass
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      for (uint32_t q = cnt[g] + (uint32_t)lane; q < nmax; q += 64u) {
+        lds.p[wid][g][q] = far_p;
+        lds.v[wid][g][q] = zero4;
+      }
+    }
+    wave_lds_sync();
+    visit(__builtin_amdgcn_readfirstlane(nmax), &lds.p[wid][grp][0], &lds.v[wid][grp][0]);
+#pragma unroll
+    for (int g = 0; g < G; ++g) cnt[g] = 0u;
+    wave_lds_sync();
+  }
+}
+
+}  // namespace ups

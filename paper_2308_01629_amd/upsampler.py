@@ -179,6 +179,20 @@ class Upsampler:
                                              _ptr(perm), _stream()))
         return perm
 
+    def permute(self, a, perm, b=None, scatter: bool = False, out_a=None, out_b=None):
+        """Gather (a[:, perm]) or scatter (out[:, perm] = a) the columns of
+        [3, N] arrays a and, if given, b; returns (out_a, out_b)."""
+        n = _soa(a, "a").shape[1]
+        if b is not None:
+            _soa(b, "b")
+        if perm.dtype != torch.int32 or perm.shape != (n,) or not perm.is_contiguous():
+            raise ValueError("perm must be a contiguous int32 tensor of length N")
+        oa = torch.empty_like(a) if out_a is None else _soa(out_a, "out_a")
+        ob = None if b is None else (torch.empty_like(b) if out_b is None else _soa(out_b, "out_b"))
+        self._check(self._L.upsample_permute(self._h, _ptr(a), _ptr(b), _ptr(oa), _ptr(ob), n, _ptr(perm),
+                                             1 if scatter else 0, _stream()))
+        return oa, ob
+
     # -- debug exports
     def debug_grid(self, n_lr: int, device="cuda"):
         info = self.grid_info()
@@ -199,19 +213,23 @@ class Upsampler:
         return count, ids, branch
 
     # -- launch-shape knobs
-    def set_tuning(self, gather_groups: Optional[int] = None, sort_sub: Optional[int] = None) -> None:
+    TUNING_KEYS = ("gather_groups", "sort_sub", "adjoint_tiled", "sort_mode", "tile_max", "adjoint_tile_max")
+
+    def set_tuning(self, **kw) -> None:
+        """Set launch-shape knobs (upsample_tuning); unnamed knobs keep their value."""
         t = _lib.Tuning()
         self._check(self._L.upsample_get_tuning(self._h, ctypes.byref(t)))
-        if gather_groups is not None:
-            t.gather_groups = int(gather_groups)
-        if sort_sub is not None:
-            t.sort_sub = int(sort_sub)
+        for k, v in kw.items():
+            if k not in self.TUNING_KEYS:
+                raise KeyError(k)
+            if v is not None:
+                setattr(t, k, int(v))
         self._check(self._L.upsample_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = _lib.Tuning()
         self._check(self._L.upsample_get_tuning(self._h, ctypes.byref(t)))
-        return {"gather_groups": int(t.gather_groups), "sort_sub": int(t.sort_sub)}
+        return {k: int(getattr(t, k)) for k in self.TUNING_KEYS}
 
     # -- kernel timing probe
     def timing_enable(self, enable: bool = True) -> None:

@@ -70,3 +70,34 @@ def compare_step(gx, gv, lr_x, lr_v, rigid, hr_x, hr_v, prm, L, n_steps=1, idx=N
     assert band_hits <= max(2, max_band_frac * idx.size), band_hits
     return {"n": int(idx.size), "max_dx": float(ex.max(initial=0)), "max_rel_dv": float(ev.max(initial=0)),
             "band": band_hits, "alpha_band": int(o["band"].sum())}
+
+
+def morton_sort_keys(x, spec, sub, mode=1):
+    """The HR reorder key of positions x [3, N] for a grid spec (float32
+    arithmetic): mode 1 the Z-order code of fine cells, mode 0 the grid cell
+    then the Z-order of its sub-cells.  Used to check the reorder's output."""
+    x = np.asarray(x, dtype=np.float32)
+    bits, fine = [], []
+    for a in range(3):
+        t = (x[a] - spec.lo[a]) * spec.inv_cs
+        c = np.clip(np.floor(t), 0, spec.dims[a] - 1).astype(np.float32)
+        f = np.clip(np.floor((t - c) * np.float32(sub)), 0, sub - 1)
+        fine.append(c.astype(np.int64) * sub + f.astype(np.int64))
+        bits.append(int(np.ceil(np.log2(spec.dims[a] * sub))) if spec.dims[a] * sub > 1 else 0)
+    if mode == 0:
+        c = [f // sub for f in fine]
+        sb = [f % sub for f in fine]
+        cell = c[0] + spec.dims[0] * (c[1] + spec.dims[1] * c[2])
+        m = np.zeros_like(cell)
+        for b in range(2):
+            for a in range(3):
+                m |= ((sb[a] >> b) & 1) << (3 * b + a)
+        return cell * sub ** 3 + m
+    key = np.zeros(x.shape[1], dtype=np.int64)
+    pos = 0
+    for b in range(max(bits)):
+        for a in range(3):
+            if b < bits[a]:
+                key |= ((fine[a] >> b) & 1) << pos
+                pos += 1
+    return key

@@ -13,7 +13,7 @@ from oracle import upsample_oracle as O
 from workloads import configs
 from workloads.generators import build_scene
 
-from gpu_util import compare_step, dev, host, log
+from gpu_util import compare_step, dev, host, log, morton_sort_keys
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -213,8 +213,8 @@ def test_deterministic_and_order_independent(U):
     assert torch.equal(torch.sort(perm).values, torch.arange(sc.n_hr, device="cuda"))
     assert torch.equal(sx, hx[:, perm]) and torch.equal(sv, hv[:, perm])
     spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
-    k = O.cell_keys(host(sx), spec)
-    assert np.all(np.diff(k.astype(np.int64)) >= 0)
+    k = morton_sort_keys(host(sx), spec, up.get_tuning()["sort_sub"], up.get_tuning()["sort_mode"])
+    assert np.all(np.diff(k) >= 0)
     c = up.step(Xd, Vd, None, sx, sv)
     torch.cuda.synchronize()
     assert torch.equal(c[0], a[0][:, perm]) and torch.equal(c[1], a[1][:, perm])
@@ -238,12 +238,43 @@ def test_gather_group_variants_match_oracle(U, groups):
     log(f"groups={groups}: {s}")
 
 
+@pytest.mark.parametrize("rigid", [False, True])
+def test_wave_paths_bit_identical(U, rigid):
+    # each wave either tiles its candidates through LDS or walks per lane,
+    # chosen by how many candidates it would stream; the choice must not
+    # change any particle's result
+    if rigid:
+        sc = build_scene("heap", 1500, 30001, seed=[21, 3], rigid_floor=True)
+        X, V = sc.lr_frame(1)
+        up = U.from_scene(sc, max_lr=X.shape[1])
+        rig = dev(sc.lr_rigid, torch)
+    else:
+        sc = configs.drain(scale=1 / 16)
+        X, V = sc.lr_frame(3)
+        up = U.from_scene(sc)
+        rig = None
+    hx, hv = dev(sc.hr_x0, torch), dev(np.random.default_rng(6).normal(size=sc.hr_x0.shape).astype(np.float32), torch)
+    up.sort_hr(hx, hv, with_perm=False)
+    out = []
+    for tmax in (0, up.get_tuning()["tile_max"], 1 << 30):
+        up.set_tuning(tile_max=tmax)
+        out.append(up.step(dev(X, torch), dev(V, torch), rig, hx, hv))
+    torch.cuda.synchronize()
+    for o in out[1:]:
+        assert torch.equal(o[0], out[0][0]) and torch.equal(o[1], out[0][1])
+    s = compare_step(host(out[0][0]), host(out[0][1]), X, V, sc.lr_rigid if rigid else None, host(hx), host(hv),
+                     sc.params(), sc.box_length, idx=_sample(sc.n_hr, 16384, 10))
+    log(f"wave paths rigid={rigid}: {s}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("sub", [1, 2, 4])
-def test_sort_hr_out_of_place_and_sub_cells(U, sub):
+def test_sort_hr_out_of_place_and_sub_cells(U, sub, mode):
     sc = configs.drain(scale=1 / 32)
     up = U.from_scene(sc)
-    up.set_tuning(sort_sub=sub)
-    hx = dev(sc.hr_x0[:, ::-1].copy(), torch)        # reversed: far from sorted
+    up.set_tuning(sort_sub=sub, sort_mode=mode)
+    shuffle = np.random.default_rng(8).permutation(sc.n_hr)
+    hx = dev(sc.hr_x0[:, shuffle].copy(), torch)       # shuffled: no spatial order
     hv = dev(np.random.default_rng(4).normal(size=sc.hr_x0.shape).astype(np.float32), torch)
     ox, ov = torch.empty_like(hx), torch.empty_like(hv)
     perm = up.sort_hr(hx, hv, out_x=ox, out_v=ov).long()
@@ -251,5 +282,41 @@ def test_sort_hr_out_of_place_and_sub_cells(U, sub):
     assert torch.equal(torch.sort(perm).values, torch.arange(sc.n_hr, device="cuda"))
     assert torch.equal(ox, hx[:, perm]) and torch.equal(ov, hv[:, perm])
     spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
-    k = O.cell_keys(host(ox), spec)
-    assert np.all(np.diff(k.astype(np.int64)) >= 0)
+    k = morton_sort_keys(host(ox), spec, sub, mode)
+    assert np.all(np.diff(k) >= 0)
+    # consecutive 64-particle groups are compact: far smaller boxes than unsorted
+    def mean_box(p):
+        m = p.shape[1] // 64
+        w = p[:, :m * 64].reshape(3, m, 64)
+        return float(np.prod(w.max(axis=2) - w.min(axis=2), axis=0).mean())
+    assert mean_box(host(ox)) < 0.05 * mean_box(host(hx))
+
+
+def test_permute_gather_scatter(U):
+    from paper_2308_01629_amd import UpsampleError
+    sc = configs.plain()
+    up = U.from_scene(sc)
+    rng = np.random.default_rng(12)
+    n = 70001                                           # ragged against the 256-thread blocks
+    a = dev(rng.normal(size=(3, n)).astype(np.float32), torch)
+    b = dev(rng.normal(size=(3, n)).astype(np.float32), torch)
+    perm = dev(rng.permutation(n).astype(np.int32), torch)
+    ga, gb = up.permute(a, perm, b)
+    only_a, none_b = up.permute(a, perm)
+    sa, sb = up.permute(ga, perm, gb, scatter=True)
+    torch.cuda.synchronize()
+    assert none_b is None and torch.equal(only_a, ga)
+    assert torch.equal(ga, a[:, perm.long()]) and torch.equal(gb, b[:, perm.long()])
+    assert torch.equal(sa, a) and torch.equal(sb, b)
+    e0, _ = up.permute(a[:, :0].contiguous(), perm[:0].contiguous())
+    assert e0.shape == (3, 0)
+    with pytest.raises(UpsampleError, match="INVALID_ARG"):
+        up.permute(a, perm, out_a=a)
+    v = U(sc.r_lr, sc.r_hr, sc.dt, sc.g, sc.domain_lo, sc.domain_hi, max_lr=10, max_hr=10, validate=True)
+    small = dev(rng.normal(size=(3, 10)).astype(np.float32), torch)
+    bad = dev(np.array([0, 1, 2, 3, 4, 5, 6, 7, 8, 10], np.int32), torch)
+    with pytest.raises(UpsampleError, match="INVALID_ARG"):
+        v.permute(small, bad)
+    ok, _ = v.permute(small, dev(np.arange(10, dtype=np.int32)[::-1].copy(), torch))
+    torch.cuda.synchronize()
+    assert torch.equal(ok, small.flip(1))
