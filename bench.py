@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched legs")
     ap.add_argument("--only", choices=["drain", "diff", "batched"], default=None,
                     help="run one leg only (profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB elementwise copy kernel 4 times (scale for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -258,8 +261,8 @@ def cpu_baseline(sc, frames, budget_s=12.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (the upsampling path has no multi-GPU leg in this "
-              f"build); got --gpus {args.gpus}", file=sys.stderr)
+        print(f"bench.py runs on one GPU only: the upsampling path has no multi-GPU leg "
+              f"(got --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -271,13 +274,24 @@ def main():
     out = {"metric": METRIC, "unit": "HR particle-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic"}
-    d = drain_leg(args, torch, Upsampler)
-    out.update({k: d[k] for k in ("value", "ms_per_step", "config", "roofline", "step_hbm_frac")})
-    if not args.no_extras:
+    if args.only in (None, "drain"):
+        d = drain_leg(args, torch, Upsampler)
+        out.update({k: d[k] for k in ("value", "ms_per_step", "config", "roofline", "step_hbm_frac")})
+    if args.only == "diff" or (args.only is None and not args.no_extras):
         out["backward_forward"] = diff_leg(args, torch, Upsampler)
-    if not args.no_cpu_baseline:
+    if args.only == "batched" or (args.only is None and not args.no_extras):
+        out["batched"] = batched_leg(args, torch, Upsampler)
+    if args.only is None and not args.no_cpu_baseline:
         log("cpu baseline: timing the oracle")
         out["cpu_baseline"] = cpu_baseline(d["scene"], d["frames"])
+    if args.calibrate_copy:
+        # negation: reads and writes exactly 256 MiB per launch
+        a = torch.ones(64 << 20, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log("copy calibration: 4 launches of 268435456 bytes read + written")
     print(json.dumps(out), flush=True)
 
 

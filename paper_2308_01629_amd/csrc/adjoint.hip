@@ -305,7 +305,8 @@ __device__ __forceinline__ Six pair_contrib(float4 Q, float4 W, float x, float y
 // block adds the non-zero slots to global memory once at the end.
 constexpr int kAccCap = 768;        // accumulator slots per block
 constexpr int kBlockRows = 256;     // at most one row per thread
-constexpr int kAdjListCap = 128;    // LDS candidate entries per wave and flush
+constexpr int kAdjListCap = 64;     // LDS candidate entries per wave and flush
+constexpr int kAdjRows = 64;        // stencil rows of one wave
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* wsum) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -325,11 +326,11 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 }
 
 __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTable wt) {
-  __shared__ TileLDS<1, kAdjListCap> lds;
+  __shared__ TileLDS<1, kAdjListCap, kAdjRows> lds;
   __shared__ float acc[6][kAccCap];
   __shared__ uint32_t brb[kBlockRows];       // first sorted index of each block row
   __shared__ uint32_t brp[kBlockRows + 1];   // exclusive prefix of block row lengths
-  __shared__ uint32_t sbase[kWaves][kMaxRows];  // block slot of each wave row's first entry
+  __shared__ uint32_t sbase[kWaves][kAdjRows];  // block slot of each wave row's first entry
   __shared__ int wbox[kWaves][6];
   __shared__ int bmeta[8];
   __shared__ uint32_t wsum[kWaves];
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
   const int64_t nl = a.n_lr;
 
   const TileSetup<1> ts = tile_setup<1>(gc, a.cell_start, x, y, z, lane, wid, lds);
-  const bool wave_tiled = ts.nrows <= kMaxRows && ts.total <= (uint32_t)a.tile_max;
+  const bool wave_tiled = ts.nrows <= kAdjRows && ts.total <= (uint32_t)a.tile_max;
 
   // ---- block box and block rows
   if (lane == 0) {

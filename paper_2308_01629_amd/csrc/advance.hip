@@ -168,9 +168,12 @@ __global__ __launch_bounds__(kBlock) void k_advance(AdvanceArgs a, WallTable wt)
 // Wave-tiled gather (tile.hpp): every lane walks its group's LDS candidate
 // list,   d = X_j - x_i,  t = 1 - |d|^2 / h^2,  w = max(t, 0)^3,
 // accumulating S, U, M; the per-lane stencil walk covers spread-out waves.
+constexpr int kGatherListEntries = 128;  // per wave, split over the G group lists
+constexpr int kGatherRows = 64;
+
 template <bool RIGID, int G>
 __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
-  __shared__ TileLDS<G> lds;
+  __shared__ TileLDS<G, kGatherListEntries / G, kGatherRows> lds;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t n = a.n;
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTab
 
   float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
   const TileSetup<G> ts = tile_setup<G>(gc, a.cell_start, x, y, z, lane, wid, lds);
-  if (ts.nrows > kMaxRows || ts.total > (uint32_t)a.tile_max) {
+  if (ts.nrows > lds.kRows || ts.total > (uint32_t)a.tile_max) {
     // spread-out wave: every lane walks its own stencil
     const Sums s = gather<false, RIGID>(gc, a.lr, a.cell_start, x, y, z, nullptr, 0);
     S = s.S; Ux = s.Ux; Uy = s.Uy; Uz = s.Uz; M = s.M;

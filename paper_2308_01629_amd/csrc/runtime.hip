@@ -265,7 +265,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   h->tune.gather_groups = 1;
   h->tune.adjoint_tiled = 1;
   h->tune.tile_max = 512;
-  h->tune.adjoint_tile_max = 256;
+  h->tune.adjoint_tile_max = 384;
   h->n_cells = h->gi.n_cells;
   h->n_chunks = (int)((h->n_cells + kScanChunk - 1) / kScanChunk);
   if (hipGetDevice(&h->device) != hipSuccess) {

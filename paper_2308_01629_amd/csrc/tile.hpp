@@ -19,8 +19,6 @@
 namespace ups {
 
 constexpr int kWaves = kBlock / 64;
-constexpr int kListBytes = 8192;  // LDS per wave for the candidate lists (32 B per entry)
-constexpr int kMaxRows = 256;     // stencil rows of one wave (four per lane); more: per-lane walk
 
 // Order-preserving map float -> int (non-NaN); an involution.
 __device__ __forceinline__ int ord(float f) {
@@ -73,24 +71,29 @@ __device__ __forceinline__ float box_dist2(const Box& b, float px, float py, flo
   return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
-template <int G, int Cap = kListBytes / 32 / G>
+// LDS of the wave tiles of one block: Cap list entries per group (32 B each)
+// and up to Rows stencil rows per wave (a multiple of 64; a wave with more
+// rows takes the per-lane walk).
+template <int G, int Cap, int Rows>
 struct TileLDS {
-  static constexpr int kCap = Cap;  // entries per group list
+  static constexpr int kCap = Cap;
+  static constexpr int kRows = Rows;
+  static_assert(Rows % 64 == 0 && Rows <= 256, "rows are scanned 64 at a time");
   float4 p[kWaves][G][kCap];  // (X_j, sorted index | rigid << 31)
   float4 v[kWaves][G][kCap];  // (V_j, original index as bits)
-  uint32_t rb[kWaves][kMaxRows];      // first sorted index of each stencil row
-  uint32_t rp[kWaves][kMaxRows + 1];  // exclusive prefix of row lengths
+  uint32_t rb[kWaves][kRows];      // first sorted index of each stencil row
+  uint32_t rp[kWaves][kRows + 1];  // exclusive prefix of row lengths
 };
 
 template <int G>
 struct TileSetup {
   Box gb[G];
-  int nrows;       // > kMaxRows: the wave is too spread out for a shared list
+  int nrows;       // > the LDS row capacity: the wave is too spread out for a shared list
   uint32_t total;  // candidates streamed (sum of row lengths)
   int X0, Y0, Z0, ny;  // first cell of the rows; rows run y-fastest
 };
 
-// Group boxes, stencil rows and their prefix sums (rows only when nrows <= kMaxRows).
+// Group boxes, stencil rows and their prefix sums (rows only when nrows fits the LDS).
 template <int G, class L>
 __device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
                                                    const uint32_t* __restrict__ cell_start, float x,
@@ -136,11 +139,11 @@ __device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
   ts.Y0 = Y0;
   ts.Z0 = Z0;
   ts.ny = ny;
-  if (ts.nrows > kMaxRows) return ts;
-  // rows r = lane + 64 q, q = 0..3: four wave scans in row order
+  if (ts.nrows > L::kRows) return ts;
+  // rows r = lane + 64 q: one wave scan per 64 rows, in row order
   uint32_t carry = 0;
 #pragma unroll
-  for (int q = 0; q < kMaxRows / 64; ++q) {
+  for (int q = 0; q < L::kRows / 64; ++q) {
     if (64 * q >= ts.nrows) break;
     const int r = lane + 64 * q;
     uint32_t rb = 0, rl = 0;
