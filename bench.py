@@ -237,6 +237,74 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8):
             "rollout_forward_backward_ms": t_rfb, "rollout_backward_over_forward": (t_rfb - t_rf) / t_rf}
 
 
+def batched_leg(args, torch, Upsampler, steps=10, warmup=2):
+    """64 scenes (heap / column / drain, N_H log-uniform in [50k, 1M], N_L =
+    N_H / 32): one graph replay of the batched step per step vs 64 plain
+    upsample_step calls from Python, same inputs; the final states of both
+    runs must be bit-identical.  The batched timing includes the copy of each
+    step's LR frame into the graph's fixed input buffers."""
+    from workloads import configs
+    from paper_2308_01629_amd.batch import Batch
+    t0 = time.time()
+    scenes = configs.batched(64)
+    b = Batch.from_scenes(scenes)
+    plain = [Upsampler.from_scene(s) for s in scenes]
+    n_frames = warmup + steps
+    log(f"batched: {len(scenes)} scenes, {b.total_lr} LR, {b.total_hr} HR, generating {n_frames} frames")
+    frames = [[s.lr_frame(t) for s in scenes] for t in range(1, n_frames + 1)]
+    LXs = [[torch.from_numpy(f[0]).cuda() for f in fr] for fr in frames]
+    LVs = [[torch.from_numpy(f[1]).cuda() for f in fr] for fr in frames]
+    LXb = [torch.from_numpy(b.pack_lr([f[0] for f in fr])).cuda() for fr in frames]
+    LVb = [torch.from_numpy(b.pack_lr([f[1] for f in fr])).cuda() for fr in frames]
+    xs = [torch.from_numpy(s.hr_x0).cuda() for s in scenes]
+    vs = [torch.from_numpy(s.hr_v0).cuda() for s in scenes]
+    for s, up in enumerate(plain):
+        up.sort_hr(xs[s], vs[s], with_perm=False)
+    hx, hv = torch.cat(xs, dim=1).contiguous(), torch.cat(vs, dim=1).contiguous()
+    lx, lv = torch.empty_like(LXb[0]), torch.empty_like(LVb[0])
+    log(f"batched: setup {time.time() - t0:.1f}s, info {b.info()}")
+
+    def run_batched(first, count):
+        for t in range(first, first + count):
+            lx.copy_(LXb[t])
+            lv.copy_(LVb[t])
+            b.step(lx, lv, hx, hv, out_x=hx, out_v=hv)
+
+    def run_plain(first, count):
+        for t in range(first, first + count):
+            for s, up in enumerate(plain):
+                up.step(LXs[t][s], LVs[t][s], None, xs[s], vs[s], out_x=xs[s], out_v=vs[s])
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    run_batched(0, warmup)
+    run_plain(0, warmup)
+    t_b = timed(lambda: run_batched(warmup, steps))
+    t_p = timed(lambda: run_plain(warmup, steps))
+    same = all(torch.equal(gx, x) and torch.equal(gv, v)
+               for gx, gv, x, v in zip(b.split_hr(hx), b.split_hr(hv), xs, vs))
+    info = b.info()
+    b.close()
+    for up in plain:
+        up.close()
+    log(f"batched: {t_b:.3f} ms/step batched vs {t_p:.3f} ms/step plain, speedup {t_p / t_b:.2f}, "
+        f"bit-identical {same}")
+    return {"workload": "batched", "n_scenes": len(scenes), "n_lr_total": b.total_lr,
+            "n_hr_total": b.total_hr, "steps": steps, "batched_ms_per_step": t_b, "plain_ms_per_step": t_p,
+            "speedup": t_p / t_b, "batched_hr_updates_per_s": b.total_hr / (t_b / 1e3),
+            "plain_hr_updates_per_s": b.total_hr / (t_p / 1e3), "bit_identical": bool(same),
+            "tiles": info["tiles"], "persistent_blocks": info["persistent_blocks"],
+            "graphs_captured": info["graphs_captured"]}
+
+
 def cpu_baseline(sc, frames, budget_s=12.0):
     """The oracle as it stands on a bounded sample of the drain workload: the
     full LR frame, a seeded sample of HR particles, one step."""

@@ -264,6 +264,57 @@ int upsample_get_tuning(upsample_handle h, upsample_tuning* t);
 int upsample_timing_enable(upsample_handle h, int enable);
 int upsample_timing_read(upsample_handle h, double* advance_ms, int64_t* launches);
 
+/*
+ * Batched step: many independent scenes (each the problem of Section 4 with
+ * its own parameters) advanced together.
+ *
+ * Particles of all scenes sit column-wise in shared device arrays: LR arrays
+ * are [3][total_lr] with scene s in columns lr_offset .. lr_offset + n_lr - 1,
+ * HR arrays [3][total_hr] likewise, where total_lr / total_hr are the largest
+ * offset + count over the scenes; the column ranges of two scenes must not
+ * overlap.  lr_rigid, when given, is uint8 [total_lr].  Each scene keeps its
+ * own upsample_params (grid, dt, gravity, blend constants, walls; max_lr,
+ * max_hr and flags are ignored); its counts are fixed at init.
+ *
+ * One step rebuilds the grids of all scenes with one counting sort over the
+ * cells of every scene and advances all HR particles with one persistent
+ * kernel over a table of (scene, 256-particle tile) entries, laid out so that
+ * each of the chip's XCDs works through a contiguous range of tiles.  The
+ * launches are captured into a HIP graph (on an internal stream) once per
+ * distinct set of buffer pointers -- the last four sets are kept -- and the
+ * graph is replayed on the caller's stream; with UPSAMPLE_BATCH_EAGER they
+ * are launched directly.  A captured step allocates nothing and holds no
+ * memset node.  Per scene, results are bit-identical to upsample_step on a
+ * handle with the same parameters.  The HR outputs may alias the inputs.
+ *
+ * Errors: UPSAMPLE_ERR_INVALID_ARG (bad scene table, overlapping ranges,
+ * NULL buffers), UPSAMPLE_ERR_GRID_TOO_LARGE (all scenes' cells or LR
+ * particles reach 2^31), UPSAMPLE_ERR_NO_DEVICE, UPSAMPLE_ERR_OOM,
+ * UPSAMPLE_ERR_HIP.  A batch, like a handle, is not thread-safe; calls on one
+ * batch must be ordered on one stream.
+ */
+typedef struct upsample_batch_s* upsample_batch;
+
+typedef struct {
+  upsample_params params;
+  int64_t lr_offset, n_lr;
+  int64_t hr_offset, n_hr;
+} upsample_scene;
+
+#define UPSAMPLE_BATCH_EAGER 1u
+#define UPSAMPLE_MAX_SCENES 65535
+
+int upsample_batch_init(const upsample_scene* scenes, int32_t n_scenes, uint32_t flags,
+                        upsample_batch* out);
+int upsample_batch_step(upsample_batch b, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                        const float* hr_x, const float* hr_v, float* hr_x_out, float* hr_v_out,
+                        void* stream);
+int upsample_batch_destroy(upsample_batch b);  /* waits for the device; NULL is a no-op */
+const char* upsample_batch_last_error(upsample_batch b);
+/* out[0] total_lr, out[1] total_hr, out[2] HR tiles, out[3] persistent blocks,
+ * out[4] graphs captured so far */
+int upsample_batch_info(upsample_batch b, int64_t* out);
+
 #ifdef __cplusplus
 }
 #endif

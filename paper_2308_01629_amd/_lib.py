@@ -25,6 +25,7 @@ MAX_WALLS = 32
 WALL_FLOATS = 12
 DEFAULT_CELL_FACTOR = 1.0001
 FLAG_VALIDATE = 1
+BATCH_EAGER = 1
 
 
 class UpsampleError(RuntimeError):

@@ -81,11 +81,11 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
   return r;
 }
 
-__device__ __forceinline__ void apply_walls(const WallTable& wt, int n_walls, float r_hr, float ox,
-                                            float oy, float oz, float& x, float& y, float& z,
+__device__ __forceinline__ void apply_walls(const float* __restrict__ walls, int n_walls, float r_hr,
+                                            float ox, float oy, float oz, float& x, float& y, float& z,
                                             float& vx, float& vy, float& vz) {
   for (int k = 0; k < n_walls; ++k) {
-    const float* w = &wt.w[k * UPSAMPLE_WALL_FLOATS];
+    const float* w = &walls[k * UPSAMPLE_WALL_FLOATS];
     const float nx = w[0], ny = w[1], nz = w[2], d = w[3];
     const float pen = fmaf(nz, z, fmaf(ny, y, nx * x)) - d;
     if (pen < r_hr) {  // rare: most particles are clear of most walls
@@ -117,7 +117,7 @@ __device__ __forceinline__ void apply_walls(const WallTable& wt, int n_walls, fl
 }
 
 // Shepard average, blend, symplectic Euler and walls for one HR particle.
-__device__ __forceinline__ void finish(const AdvanceArgs& a, const WallTable& wt, int64_t i, float x,
+__device__ __forceinline__ void finish(const AdvanceArgs& a, const float* __restrict__ walls, int64_t i, float x,
                                       float y, float z, float vx, float vy, float vz, float S,
                                       float Ux, float Uy, float Uz, float M, bool* A_out) {
   // Shepard average and blend parameter (Section 4); empty support -> v~ = 0, alpha = 1.
@@ -134,8 +134,8 @@ __device__ __forceinline__ void finish(const AdvanceArgs& a, const WallTable& wt
   const float fx = fmaf(dt, a.sc.g[0], vx), fy = fmaf(dt, a.sc.g[1], vy), fz = fmaf(dt, a.sc.g[2], vz);
   float nvx = fmaf(alpha, fx - tx, tx), nvy = fmaf(alpha, fy - ty, ty), nvz = fmaf(alpha, fz - tz, tz);
   float nx = fmaf(dt, nvx, x), ny = fmaf(dt, nvy, y), nz = fmaf(dt, nvz, z);
-  apply_walls(wt, a.sc.n_walls, a.sc.r_hr, x, y, z, nx, ny, nz, nvx, nvy, nvz);
-  const int64_t n = a.n;
+  apply_walls(walls, a.sc.n_walls, a.sc.r_hr, x, y, z, nx, ny, nz, nvx, nvy, nvz);
+  const int64_t n = a.ld;
   a.hx_out[i] = nx;
   a.hx_out[n + i] = ny;
   a.hx_out[2 * n + i] = nz;
@@ -151,13 +151,13 @@ template <bool DEBUG>
 __global__ __launch_bounds__(kBlock) void k_advance(AdvanceArgs a, WallTable wt) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
-  const int64_t n = a.n;
+  const int64_t n = a.ld;
   const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
   const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
   uint32_t* ids = (DEBUG && a.dbg_ids != nullptr) ? a.dbg_ids + i * a.dbg_max_k : nullptr;
   const Sums s = gather<DEBUG, true>(a.gc, a.lr, a.cell_start, x, y, z, ids, a.dbg_max_k);
   bool A;
-  finish(a, wt, i, x, y, z, vx, vy, vz, s.S, s.Ux, s.Uy, s.Uz, s.M, &A);
+  finish(a, wt.w, i, x, y, z, vx, vy, vz, s.S, s.Ux, s.Uy, s.Uz, s.M, &A);
   if (DEBUG) {
     if (a.dbg_count != nullptr) a.dbg_count[i] = s.count;
     if (a.dbg_branch != nullptr)
@@ -171,15 +171,20 @@ __global__ __launch_bounds__(kBlock) void k_advance(AdvanceArgs a, WallTable wt)
 constexpr int kGatherListEntries = 128;  // per wave, split over the G group lists
 constexpr int kGatherRows = 64;
 
+template <int G>
+using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries / G : 64), kGatherRows>;
+
+// One block-sized tile of HR particles first .. first + kBlock - 1 (those
+// below a.n are live; the rest shadow the last particle and write nothing).
 template <bool RIGID, int G>
-__global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
-  __shared__ TileLDS<G, kGatherListEntries / G, kGatherRows> lds;
+__device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* __restrict__ walls,
+                                             GatherLDS<G>& lds, int64_t first) {
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t n = a.n;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool live = i0 < n;
-  const int64_t i = live ? i0 : n - 1;  // idle lanes shadow the last particle
+  const int64_t n = a.ld;
+  const int64_t i0 = first + threadIdx.x;
+  const bool live = i0 < a.n;
+  const int64_t i = live ? i0 : a.n - 1;  // idle lanes shadow the last particle
   const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
   const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
   const GridConst& gc = a.gc;
@@ -217,7 +222,42 @@ __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTab
   }
   if (live) {
     bool A;
-    finish(a, wt, i, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, &A);
+    finish(a, walls, i, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, &A);
+  }
+}
+
+template <bool RIGID, int G>
+__global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
+  __shared__ GatherLDS<G> lds;
+  advance_tile<RIGID, G>(a, wt.w, lds, (int64_t)blockIdx.x * kBlock);
+}
+
+// Batched step: a persistent grid strides over the (scene, first particle)
+// tile table; each tile reads its scene's constants from the scene table.
+template <bool RIGID>
+__global__ __launch_bounds__(kBlock) void k_advance_batched(BatchAdvanceArgs b) {
+  __shared__ GatherLDS<1> lds;
+  for (int64_t t = blockIdx.x; t < b.n_tiles; t += gridDim.x) {
+    const BatchTile tile = b.tiles[t];
+    const BatchScene& sc = b.scenes[tile.scene];
+    AdvanceArgs a;
+    a.gc = sc.gc;
+    a.sc = sc.sc;
+    a.lr = b.lr;
+    a.cell_start = b.cell_start + sc.cell_base;
+    a.hx = b.hx + sc.hr_off;
+    a.hv = b.hv + sc.hr_off;
+    a.hx_out = b.hx_out + sc.hr_off;
+    a.hv_out = b.hv_out + sc.hr_off;
+    a.n = sc.n_hr;
+    a.ld = b.ld;
+    a.dbg_count = nullptr;
+    a.dbg_ids = nullptr;
+    a.dbg_max_k = 0;
+    a.dbg_branch = nullptr;
+    a.groups = 1;
+    a.tile_max = b.tile_max;
+    advance_tile<RIGID, 1>(a, b.walls + sc.wall_off, lds, (int64_t)tile.first);
   }
 }
 
@@ -236,6 +276,22 @@ hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool deb
     hipLaunchKernelGGL((k_advance_tiled<false, 2>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
   else
     hipLaunchKernelGGL((k_advance_tiled<false, 1>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  return hipGetLastError();
+}
+
+int advance_batched_blocks_per_cu(bool rigid) {
+  int nb = 0;
+  hipError_t e = rigid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advance_batched<true>, kBlock, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advance_batched<false>, kBlock, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t launch_advance_batched(const BatchAdvanceArgs& b, int grid, hipStream_t st) {
+  if (b.n_tiles == 0) return hipSuccess;
+  if (b.rigid)
+    hipLaunchKernelGGL(k_advance_batched<true>, dim3(grid), dim3(kBlock), 0, st, b);
+  else
+    hipLaunchKernelGGL(k_advance_batched<false>, dim3(grid), dim3(kBlock), 0, st, b);
   return hipGetLastError();
 }
 

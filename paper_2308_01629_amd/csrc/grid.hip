@@ -284,6 +284,60 @@ __global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const fl
   }
 }
 
+// Batched grid: keys of every scene's LR particles, offset by the scene's
+// first global cell; the internal index of a particle is its scene's first
+// internal index plus its index inside the scene.
+__global__ __launch_bounds__(kBlock) void k_keys_count_batched(BatchGridArgs b, uint32_t* __restrict__ keys,
+                                                               uint32_t* __restrict__ slot,
+                                                               uint32_t* __restrict__ counts) {
+  const BatchTile blk = b.lr_blocks[blockIdx.x];
+  const BatchScene& sc = b.scenes[blk.scene];
+  const int64_t e = (int64_t)blk.first + threadIdx.x;
+  const bool valid = e < sc.n_lr;
+  uint32_t k = 0u;
+  if (valid) {
+    const int64_t src = sc.lr_off + e;
+    k = sc.cell_base + cell_key(sc.gc, b.lr_x[src], b.lr_x[b.ld + src], b.lr_x[2 * b.ld + src]);
+  }
+  const uint32_t sl = claim_slot(k, valid, counts);
+  if (valid) {
+    const int64_t q = sc.lr_int + e;
+    keys[q] = k;
+    slot[q] = sl;
+    b.scene_of[q] = (uint16_t)blk.scene;
+  }
+}
+
+// Stable rank inside the cell and the sorted LR copy, as k_stable; the id
+// bits hold the particle's index inside its scene.
+__global__ __launch_bounds__(kBlock) void k_stable_batched(const uint32_t* __restrict__ tmp,
+                                                           const uint32_t* __restrict__ keys,
+                                                           const uint32_t* __restrict__ cell_start,
+                                                           BatchGridArgs b, uint32_t* __restrict__ perm,
+                                                           LRPoint* __restrict__ out) {
+  const int64_t n = b.n_int;
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t i = tmp[p];
+  if (i >= (uint64_t)n) return;  // defensive: tmp is a permutation of [0, n)
+  const uint32_t k = keys[i];
+  const uint32_t c0 = cell_start[k], c1 = cell_start[k + 1];
+  if (c1 > (uint64_t)n || c0 > c1) return;
+  uint32_t rank = 0;
+  for (uint32_t q = c0; q < c1; ++q) rank += (tmp[q] < i) ? 1u : 0u;
+  const uint32_t dst = c0 + rank;
+  if (dst >= c1) return;
+  perm[dst] = i;
+  const BatchScene& sc = b.scenes[b.scene_of[i]];
+  const int64_t local = (int64_t)i - sc.lr_int;
+  const int64_t src = sc.lr_off + local;
+  const float flag = (b.lr_rigid != nullptr && b.lr_rigid[src] != 0) ? 1.0f : 0.0f;
+  LRPoint o;
+  o.p = make_float4(b.lr_x[src], b.lr_x[b.ld + src], b.lr_x[2 * b.ld + src], flag);
+  o.v = make_float4(b.lr_v[src], b.lr_v[b.ld + src], b.lr_v[2 * b.ld + src], __uint_as_float((uint32_t)local));
+  out[dst] = o;
+}
+
 hipError_t scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t* chunk_sum,
                      uint32_t* ticket, hipStream_t st) {
   int n_chunks = (int)((n_bins + kScanChunk - 1) / kScanChunk);
@@ -310,6 +364,24 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
   if (n_lr > 0) {
     hipLaunchKernelGGL(k_stable, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, s.tmp, s.keys,
                        s.cell_start, n_lr, lr_x, lr_v, lr_rigid, s.perm, s.lr_sorted);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& s, hipStream_t st) {
+  if (b.n_lr_blocks > 0) {
+    hipLaunchKernelGGL(k_keys_count_batched, dim3((unsigned)b.n_lr_blocks), dim3(kBlock), 0, st, b, s.keys,
+                       s.slot, s.counts);
+  }
+  hipError_t e = scan_bins(s.counts, b.n_cells, s.local, s.chunk_sum, s.ticket, st);
+  if (e != hipSuccess) return e;
+  const int n_chunks = (int)((b.n_cells + kScanChunk - 1) / kScanChunk);
+  const int64_t span = b.n_int > b.n_cells + 1 ? b.n_int : b.n_cells + 1;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, b.n_int, s.local,
+                     s.chunk_sum, b.n_cells, n_chunks, s.tmp, s.cell_start);
+  if (b.n_int > 0) {
+    hipLaunchKernelGGL(k_stable_batched, dim3(blocks_for(b.n_int)), dim3(kBlock), 0, st, s.tmp, s.keys,
+                       s.cell_start, b, s.perm, s.lr_sorted);
   }
   return hipGetLastError();
 }

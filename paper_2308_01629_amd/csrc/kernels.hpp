@@ -1,6 +1,8 @@
 // Host-side launchers of the library's kernels (one translation unit each).
 #pragma once
 
+#include <string>
+
 #include "common.hpp"
 
 namespace ups {
@@ -72,6 +74,7 @@ struct AdvanceArgs {
   float* hx_out;
   float* hv_out;
   int64_t n;
+  int64_t ld;  // component stride of the HR arrays ([3][ld]; n for one scene)
   // debug outputs (all may be null)
   uint32_t* dbg_count;
   uint32_t* dbg_ids;
@@ -81,6 +84,59 @@ struct AdvanceArgs {
   int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
 };
 hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool debug, hipStream_t st);
+
+// a9: batched step over many scenes in concatenated buffers.
+struct BatchScene {
+  GridConst gc;
+  StepConst sc;
+  int64_t hr_off, n_hr;   // caller's HR columns
+  int64_t lr_off, n_lr;   // caller's LR columns
+  int64_t lr_int;         // first internal (concatenated) LR index of the scene
+  uint32_t cell_base;     // first global cell of the scene
+  uint32_t n_cells;
+  int32_t wall_off;       // first float of the scene's walls in the wall table
+  int32_t pad;
+};
+struct BatchTile {
+  uint32_t scene;
+  uint32_t first;  // first particle of the tile inside its scene
+};
+struct BatchAdvanceArgs {
+  const BatchScene* scenes;
+  const BatchTile* tiles;  // one per kBlock HR particles of each scene
+  int64_t n_tiles;
+  const float* walls;
+  const LRPoint* lr;           // every scene's sorted LR copy, scene after scene
+  const uint32_t* cell_start;  // global cells
+  const float* hx;
+  const float* hv;
+  float* hx_out;
+  float* hv_out;
+  int64_t ld;  // component stride of the caller's HR arrays
+  int tile_max;
+  int rigid;
+};
+int advance_batched_blocks_per_cu(bool rigid);
+hipError_t launch_advance_batched(const BatchAdvanceArgs& b, int grid, hipStream_t st);
+
+// Batched grid rebuild: one key / count / scan / scatter / stable pass over
+// the LR particles of every scene (keys offset by the scene's cell base).
+struct BatchGridArgs {
+  const BatchScene* scenes;
+  const BatchTile* lr_blocks;  // one per kBlock LR particles of each scene
+  int64_t n_lr_blocks;
+  const float* lr_x;
+  const float* lr_v;
+  const uint8_t* lr_rigid;
+  int64_t ld;          // component stride of the caller's LR arrays
+  int64_t n_int;       // LR particles of all scenes
+  int64_t n_cells;     // cells of all scenes
+  uint16_t* scene_of;  // [n_int] scene of each internal LR index
+};
+hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& s, hipStream_t st);
+
+// Host: validate one scene's parameters and compute its grid (runtime.hip).
+int check_scene_params(const upsample_params* p, upsample_grid_info* gi, std::string* why);
 
 // a7: adjoint step.
 struct AdjointArgs {

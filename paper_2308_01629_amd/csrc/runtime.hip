@@ -201,6 +201,16 @@ int validate_finite(upsample_handle h, hipStream_t st, const float* const* array
 
 }  // namespace
 
+namespace ups {
+
+int check_scene_params(const upsample_params* p, upsample_grid_info* gi, std::string* why) {
+  const int rc = validate_params(p, why);
+  if (rc != UPSAMPLE_OK) return rc;
+  return compute_grid(p, gi, why);
+}
+
+}  // namespace ups
+
 extern "C" {
 
 int upsample_default_params(upsample_params* p) {
@@ -414,6 +424,7 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
   a.hx_out = hr_x_out;
   a.hv_out = hr_v_out;
   a.n = n_hr;
+  a.ld = n_hr;
   a.dbg_count = count;
   a.dbg_ids = ids;
   a.dbg_max_k = max_k;

@@ -79,6 +79,8 @@ struct TileLDS {
   static constexpr int kCap = Cap;
   static constexpr int kRows = Rows;
   static_assert(Rows % 64 == 0 && Rows <= 256, "rows are scanned 64 at a time");
+  // one streaming pass appends up to 64 candidates to every group list
+  static_assert(Cap >= 64, "a group list must hold one full pass");
   float4 p[kWaves][G][kCap];  // (X_j, sorted index | rigid << 31)
   float4 v[kWaves][G][kCap];  // (V_j, original index as bits)
   uint32_t rb[kWaves][kRows];      // first sorted index of each stencil row

@@ -101,6 +101,45 @@ def test_null_handle_calls_rejected():
     assert L.upsample_strerror(2).decode().startswith("particle count")
 
 
+def _scene(p, lr_off, n_lr, hr_off, n_hr):
+    d = _lib.SceneDesc()
+    d.params = p
+    d.lr_offset, d.n_lr, d.hr_offset, d.n_hr = lr_off, n_lr, hr_off, n_hr
+    return d
+
+
+def test_batch_table_validated_before_device():
+    L = _lib.lib()
+    inv = _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+    b = ctypes.c_void_p()
+    p, _w = _params()
+    bad, _w2 = _params(r_lr=0.0)
+
+    def init(scenes, flags=0):
+        arr = (_lib.SceneDesc * len(scenes))(*scenes)
+        return L.upsample_batch_init(arr, len(scenes), flags, ctypes.byref(b))
+
+    assert L.upsample_batch_init(None, 1, 0, ctypes.byref(b)) == inv
+    assert init([_scene(p, 0, 10, 0, 10)], flags=0x10) == inv
+    assert init([_scene(p, 0, 10, 0, 10), _scene(p, 5, 10, 10, 10)]) == inv      # LR ranges overlap
+    assert init([_scene(p, 0, 10, 0, 10), _scene(p, 10, 10, 9, 10)]) == inv      # HR ranges overlap
+    assert init([_scene(p, -1, 10, 0, 10)]) == inv
+    assert init([_scene(p, 0, 10, 0, 10), _scene(bad, 10, 10, 10, 10)]) == inv   # bad scene params
+    small, _w3 = _params(r_lr=1e-4, domain_hi=(100, 100, 100))
+    assert init([_scene(small, 0, 10, 0, 10)]) == _lib.ERR_CODES["UPSAMPLE_ERR_GRID_TOO_LARGE"]
+    arr = (_lib.SceneDesc * 1)(_scene(p, 0, 10, 0, 10))
+    assert L.upsample_batch_init(arr, 0, 0, ctypes.byref(b)) == inv
+    assert L.upsample_batch_init(arr, 1, 0, None) == inv
+    if _no_gpu():
+        # unordered but disjoint ranges and empty scenes are a valid table
+        ok = [_scene(p, 20, 10, 30, 10), _scene(p, 0, 20, 0, 30), _scene(p, 0, 0, 0, 0)]
+        assert init(ok) == _lib.ERR_CODES["UPSAMPLE_ERR_NO_DEVICE"]
+    assert L.upsample_batch_step(None, None, None, None, None, None, None, None, None) == inv
+    assert L.upsample_batch_info(None, None) == inv
+    assert L.upsample_batch_destroy(None) == 0
+    assert L.upsample_batch_last_error(None).decode() == "null batch"
+
+
 @pytest.mark.skipif(not _no_gpu(), reason="host without a GPU only")
 def test_valid_init_without_device_reports_no_device():
     p, _w = _params()

@@ -362,9 +362,17 @@ def build_scene(geometry: str, n_lr: int, n_hr: int, seed, r_lr: Optional[float]
     of the geometry's nominal volume holds about ``n_lr`` sites."""
     geom = make_geometry(geometry, with_walls)
     sj, sf, sn, sh, st = (np.random.default_rng(s) for s in _seeds(seed))
-    if r_lr is None:
+    auto = r_lr is None
+    if auto:
         r_lr = auto_radius(geometry, n_lr)
-    X = fill_lattice(geom, r_lr, n_lr, sj)
+    while True:
+        try:
+            X = fill_lattice(geom, r_lr, n_lr, sj)   # draws nothing when it fails
+            break
+        except ValueError:
+            if not auto:
+                raise
+            r_lr *= 0.97   # small counts: the lattice quantises below the nominal fill
     rigid = np.zeros(n_lr, dtype=np.uint8)
     if rigid_floor:
         # boundary sampling of the floor as static rigid LR particles (Section 3)
