@@ -265,6 +265,42 @@ int upsample_timing_enable(upsample_handle h, int enable);
 int upsample_timing_read(upsample_handle h, double* advance_ms, int64_t* launches);
 
 /*
+ * Autotuner.  Times the step kernel (upsample_advance) for candidate cell
+ * factors kappa in {0.51, 0.6, 0.75, 1.0001, 1.25} (cs = kappa * 3 r_lr;
+ * below 1 the stencil reaches two cells) and for the launch knobs sort_sub,
+ * gather_groups and tile_max, by replaying a short stretch of the caller's
+ * run: lr_x, lr_v hold n_frames consecutive LR frames ([n_frames][3][n_lr],
+ * device); a copy of the HR state is reordered at the first frame, as a run
+ * reorders at the start of each interval, and carried along the frames; each
+ * setting is scored by its mean kernel time over the frames (waves spread as
+ * particles drift between reorders, so the fresh state alone favours the
+ * wrong knobs; n_frames of about the reorder interval is a good choice).
+ * The fastest setting is returned.  It does not change what a step computes:
+ * it depends on the grid and launch shape only (the membership predicate is
+ * exact at any kappa).  Inputs are not modified.  The call allocates
+ * temporary device memory and synchronises the stream; it is meant for
+ * set-up, not for the timed path.
+ *
+ * cache_path (may be NULL) names a JSON-lines file: a result is looked up
+ * there by a key made of the device architecture and a hash of the counts,
+ * n_frames, the parameters and the wall table (from_cache = 1, nothing is
+ * measured), and a new measurement is appended.  Errors: as upsample_init,
+ * plus UPSAMPLE_ERR_INVALID_ARG for n_frames outside [1, 1024] and
+ * UPSAMPLE_ERR_GRID_TOO_LARGE if no candidate grid fits.
+ */
+typedef struct {
+  float cell_factor;       /* kappa for upsample_params.cell_factor */
+  upsample_tuning tuning;  /* knobs for upsample_set_tuning */
+  float advance_ms;        /* its mean step-kernel time per launch over the frames */
+  int32_t from_cache;      /* 1: read from cache_path */
+} upsample_autotune_result;
+
+int upsample_autotune(const upsample_params* p, const float* lr_x, const float* lr_v,
+                      const uint8_t* lr_rigid, int64_t n_lr, int32_t n_frames, const float* hr_x,
+                      const float* hr_v, int64_t n_hr, const char* cache_path, void* stream,
+                      upsample_autotune_result* out);
+
+/*
  * Batched step: many independent scenes (each the problem of Section 4 with
  * its own parameters) advanced together.
  *

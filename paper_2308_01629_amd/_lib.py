@@ -64,6 +64,11 @@ class Tuning(ctypes.Structure):
                 ("tile_max", ctypes.c_int32), ("adjoint_tile_max", ctypes.c_int32)]
 
 
+class AutotuneResult(ctypes.Structure):
+    _fields_ = [("cell_factor", ctypes.c_float), ("tuning", Tuning), ("advance_ms", ctypes.c_float),
+                ("from_cache", ctypes.c_int32)]
+
+
 class SceneDesc(ctypes.Structure):
     """upsample_scene: one scene of a batch."""
     _fields_ = [("params", Params), ("lr_offset", ctypes.c_int64), ("n_lr", ctypes.c_int64),
@@ -101,8 +106,8 @@ SIGNATURES = {
     "upsample_batch_destroy": (_INT, [_P]),
     "upsample_batch_last_error": (ctypes.c_char_p, [_P]),
     "upsample_batch_info": (_INT, [_P, ctypes.POINTER(_I64)]),
-    "upsample_autotune": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _I64, ctypes.c_char_p, _P,
-                                 ctypes.POINTER(ctypes.c_float)]),
+    "upsample_autotune": (_INT, [ctypes.POINTER(Params), _P, _P, _P, _I64, _I32, _P, _P, _I64, ctypes.c_char_p,
+                                 _P, ctypes.POINTER(AutotuneResult)]),
 }
 
 _lib: Optional[ctypes.CDLL] = None

@@ -46,10 +46,12 @@ class Batch:
         del keep
 
     @classmethod
-    def from_scenes(cls, scenes, cell_factor: float = 0.0, eager: bool = False) -> "Batch":
+    def from_scenes(cls, scenes, cell_factor=0.0, eager: bool = False) -> "Batch":
+        """``cell_factor``: one kappa for every scene or one per scene."""
+        kap = list(cell_factor) if np.ndim(cell_factor) else [float(cell_factor)] * len(scenes)
         params = [dict(r_lr=sc.r_lr, r_hr=sc.r_hr, dt=sc.dt, g=tuple(sc.g), domain_lo=tuple(sc.domain_lo),
                        domain_hi=tuple(sc.domain_hi), walls=sc.walls, c1=sc.c1, c2=sc.c2,
-                       cell_factor=cell_factor) for sc in scenes]
+                       cell_factor=k) for sc, k in zip(scenes, kap)]
         return cls(params, [sc.n_lr for sc in scenes], [sc.n_hr for sc in scenes], eager=eager)
 
     def _check(self, rc: int) -> None:

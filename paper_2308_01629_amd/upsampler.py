@@ -70,6 +70,31 @@ def grid_info_for(**kw) -> dict:
     return gi.as_dict()
 
 
+def autotune(params: dict, lr_x, lr_v, hr_x, hr_v, lr_rigid=None, cache_path: Optional[str] = None) -> dict:
+    """Fastest cell factor and launch knobs (upsample_autotune).  ``params``:
+    the keyword arguments of :func:`make_params`; ``lr_x``, ``lr_v``: one
+    frame [3, N_L] or consecutive frames [T, 3, N_L] of the run to replay."""
+    p, _wbuf = make_params(**params)
+    if lr_x.dim() == 2:
+        lr_x, lr_v = lr_x.unsqueeze(0), lr_v.unsqueeze(0)
+    if not (lr_x.is_cuda and lr_x.dtype == torch.float32 and lr_x.dim() == 3 and lr_x.shape[1] == 3
+            and lr_x.is_contiguous() and lr_v.shape == lr_x.shape and lr_v.is_contiguous()
+            and lr_v.dtype == torch.float32):
+        raise ValueError("lr_x, lr_v must be contiguous float32 device tensors [T, 3, N_L]")
+    n_frames, n_lr = lr_x.shape[0], lr_x.shape[2]
+    n_hr = _soa(hr_x, "hr_x").shape[1]
+    _soa(hr_v, "hr_v")
+    _u8(lr_rigid, n_lr, "lr_rigid")
+    r = _lib.AutotuneResult()
+    check(lib().upsample_autotune(ctypes.byref(p), _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), n_lr, n_frames,
+                                  _ptr(hr_x), _ptr(hr_v), n_hr, cache_path.encode() if cache_path else None,
+                                  _stream(), ctypes.byref(r)))
+    t = r.tuning
+    return {"cell_factor": float(r.cell_factor), "advance_ms": float(r.advance_ms),
+            "from_cache": bool(r.from_cache),
+            "tuning": {k: int(getattr(t, k)) for k in Upsampler.TUNING_KEYS}}
+
+
 class Upsampler:
     """One handle of the library: a scene's parameters plus scratch for up to
     ``max_lr`` LR and ``max_hr`` HR particles."""
@@ -92,6 +117,19 @@ class Upsampler:
         return cls(scene.r_lr, scene.r_hr, scene.dt, scene.g, scene.domain_lo, scene.domain_hi,
                    walls=scene.walls, max_lr=max_lr if max_lr is not None else scene.n_lr,
                    max_hr=max_hr if max_hr is not None else scene.n_hr, c1=scene.c1, c2=scene.c2, **kw)
+
+    @classmethod
+    def tuned(cls, scene, lr_x, lr_v, hr_x, hr_v, lr_rigid=None, cache_path: Optional[str] = None, **kw):
+        """A handle for ``scene`` with the autotuned cell factor and knobs
+        (measured on the given particles); the result dict is kept in .autotune."""
+        params = dict(r_lr=scene.r_lr, r_hr=scene.r_hr, dt=scene.dt, g=tuple(scene.g),
+                      domain_lo=tuple(scene.domain_lo), domain_hi=tuple(scene.domain_hi), walls=scene.walls,
+                      c1=scene.c1, c2=scene.c2)
+        res = autotune(params, lr_x, lr_v, hr_x, hr_v, lr_rigid=lr_rigid, cache_path=cache_path)
+        up = cls.from_scene(scene, cell_factor=res["cell_factor"], **kw)
+        up.set_tuning(**res["tuning"])
+        up.autotune = res
+        return up
 
     # -- plumbing
     def _check(self, rc: int) -> None:

@@ -97,6 +97,7 @@ def test_null_handle_calls_rejected():
                                     None, None, None) == inv
     assert L.upsample_sort_hr(None, None, None, None, None, 0, None, None) == inv
     assert L.upsample_permute(None, None, None, None, None, 0, None, 0, None) == inv
+    assert L.upsample_autotune(None, None, None, None, 0, 1, None, None, 0, None, None, None) == inv
     assert L.upsample_destroy(None) == 0
     assert L.upsample_strerror(2).decode().startswith("particle count")
 
