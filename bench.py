@@ -66,17 +66,28 @@ def source_hash(*names):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_src: str, n_launch_units: dict):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, only when
-    it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "advance_drain_traffic.json")
+GATHER_SOURCES = ("advance.hip", "tile.hpp", "common.hpp")
+
+
+def traffic_from_profiles():
+    """HBM bytes per gather launch from the committed rocprofv3 PMC summary,
+    only while the kernel's sources are the ones it was measured on."""
+    path = os.path.join(ROOT, "profiles", "advance_drain_traffic.md")
     try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
+        lines = open(path).read().splitlines()
+    except OSError:
         return None
-    if rec.get("source_hash") != source_hash(kernel_src):
+    rec = {}
+    for ln in lines:
+        if ":" in ln and ln.split(":", 1)[0] in ("source_hash", "hbm_bytes_per_launch"):
+            k, v = ln.split(":", 1)
+            rec[k] = v.strip()
+    if rec.get("source_hash") != source_hash(*GATHER_SOURCES):
         return None
-    return rec.get("hbm_bytes_per_launch")
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def drain_leg(args, torch, Upsampler):
@@ -148,8 +159,8 @@ def drain_leg(args, torch, Upsampler):
     adv_bytes = 48 * sc.n_hr + 32 * sc.n_lr + 4 * (n_cells + 1)
     step_bytes = 48 * sc.n_hr + 89 * sc.n_lr + 8 * n_cells
     adv_s = adv_ms / 1e3 / max(launches, 1)
-    traffic = traffic_from_profiles("advance.hip", {})
-    rf = {"bound": "hbm", "kernel": "k_advance (fused gather/blend/integrate/walls)",
+    traffic = traffic_from_profiles()
+    rf = {"bound": "hbm", "kernel": "k_advance_tiled (fused gather/blend/integrate/walls)",
           "achieved": adv_bytes / adv_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
           "frac": adv_bytes / adv_s / HBM_PEAK, "traffic": traffic,
           "algorithmic_bytes_per_launch": adv_bytes, "avg_launch_us": adv_s * 1e6}
