@@ -184,6 +184,29 @@ int upsample_step_backward(upsample_handle h,
                            void* stream);
 
 /*
+ * Taped step and adjoint.  upsample_step_taped is upsample_step that also
+ * records, per HR particle, the forward sums the adjoint needs: tape is a
+ * device float array [6][n_hr] receiving S, U_x, U_y, U_z, M and the argmax
+ * of the weights (original LR index as float bits; ties: smallest index;
+ * 0xffffffff when the support is empty), with the rigid rule applied (a
+ * rigid-only support is recorded as zero sums).  upsample_step_backward_taped
+ * is upsample_step_backward reading these sums from tape instead of
+ * recomputing them; it must get the same LR frame and HR state as the taped
+ * step.  The results agree with the untaped adjoint to float32 rounding.
+ * The tape is caller-owned and must not alias any other argument.
+ */
+int upsample_step_taped(upsample_handle h,
+                        const float* lr_x, const float* lr_v, const uint8_t* lr_rigid, int64_t n_lr,
+                        const float* hr_x, const float* hr_v, float* hr_x_out, float* hr_v_out,
+                        int64_t n_hr, float* tape, void* stream);
+int upsample_step_backward_taped(upsample_handle h,
+                                 const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                                 int64_t n_lr, const float* hr_x, const float* hr_v, int64_t n_hr,
+                                 const float* tape, const float* gx_out, const float* gv_out,
+                                 float* gx_in, float* gv_in, float* g_lr_x, float* g_lr_v,
+                                 void* stream);
+
+/*
  * Reorder HR particles by grid cell and, inside a cell, by the Morton order of
  * sort_sub^3 sub-cells (upsample_tuning), so that consecutive particles -- the
  * lanes of one wave of the step kernel -- occupy a compact box.  Reads hr_x,

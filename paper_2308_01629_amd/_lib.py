@@ -93,6 +93,9 @@ SIGNATURES = {
     "upsample_advance": (_INT, [_P, _P, _P, _P, _P, _I64, _P]),
     "upsample_step": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P]),
     "upsample_step_backward": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "upsample_step_taped": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P, _P]),
+    "upsample_step_backward_taped": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
+                                            _P]),
     "upsample_sort_hr": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _P]),
     "upsample_permute": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _INT, _P]),
     "upsample_debug_grid": (_INT, [_P, _P, _P, _P, _P]),

@@ -142,31 +142,42 @@ __device__ __forceinline__ void adjoint_lane(const AdjointArgs& a, const WallTab
   float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
   uint32_t arg = 0xffffffffu;
   bool gran = false;
-  for (int zz = lo[2]; zz <= hi[2]; ++zz)
-    for (int yy = lo[1]; yy <= hi[1]; ++yy) {
-      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
-      const uint32_t b = a.cell_start[row + (uint32_t)lo[0]], e = a.cell_start[row + (uint32_t)hi[0] + 1u];
-      for (uint32_t j = b; j < e; ++j) {
-        const float4 P = a.lr[j].p;
-        const float s = sq_dist(P.x, P.y, P.z, x, y, z);
-        if (s < gc.h2) {
-          const float4 V = a.lr[j].v;
-          const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
-          const float w = t * t * t;
-          const uint32_t id = __float_as_uint(V.w);
-          S += w;
-          Ux = fmaf(w, V.x, Ux);
-          Uy = fmaf(w, V.y, Uy);
-          Uz = fmaf(w, V.z, Uz);
-          if (w > M || (w == M && id < arg)) {
-            M = w;
-            arg = id;
+  if (a.tape != nullptr) {
+    // the forward's record; a rigid-only support was recorded as zero sums
+    S = a.tape[i];
+    Ux = a.tape[n + i];
+    Uy = a.tape[2 * n + i];
+    Uz = a.tape[3 * n + i];
+    M = a.tape[4 * n + i];
+    arg = __float_as_uint(a.tape[5 * n + i]);
+    gran = S > 0.0f;
+  } else {
+    for (int zz = lo[2]; zz <= hi[2]; ++zz)
+      for (int yy = lo[1]; yy <= hi[1]; ++yy) {
+        const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
+        const uint32_t b = a.cell_start[row + (uint32_t)lo[0]], e = a.cell_start[row + (uint32_t)hi[0] + 1u];
+        for (uint32_t j = b; j < e; ++j) {
+          const float4 P = a.lr[j].p;
+          const float s = sq_dist(P.x, P.y, P.z, x, y, z);
+          if (s < gc.h2) {
+            const float4 V = a.lr[j].v;
+            const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
+            const float w = t * t * t;
+            const uint32_t id = __float_as_uint(V.w);
+            S += w;
+            Ux = fmaf(w, V.x, Ux);
+            Uy = fmaf(w, V.y, Uy);
+            Uz = fmaf(w, V.z, Uz);
+            if (w > M || (w == M && id < arg)) {
+              M = w;
+              arg = id;
+            }
+            gran |= (P.w == 0.0f);
           }
-          gran |= (P.w == 0.0f);
         }
       }
-    }
-  if (!gran) S = Ux = Uy = Uz = M = 0.f;  // rigid LR count only next to a granular one
+    if (!gran) S = Ux = Uy = Uz = M = 0.f;  // rigid LR count only next to a granular one
+  }
   Back bk = backprop(a.sc, wt, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, a.gx_out[i], a.gx_out[n + i],
                      a.gx_out[2 * n + i], a.gv_out[i], a.gv_out[n + i], a.gv_out[2 * n + i]);
   if (gran) {
@@ -413,24 +424,35 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
     // ---- pass 1: sums and argmax (ties: smallest original index)
     float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
     uint32_t arg = 0xffffffffu;
-    tile_visit<1>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
-      for (uint32_t c = 0; c < nc; ++c) {
-        const float4 Q = lp[c];
-        const float4 W = lv[c];
-        const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
-        const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
-        const float w = u * u * u;
-        const uint32_t id = __float_as_uint(W.w);
-        S += w;
-        Ux = fmaf(w, W.x, Ux);
-        Uy = fmaf(w, W.y, Uy);
-        Uz = fmaf(w, W.z, Uz);
-        const bool better = (w > M) || (w == M && id < arg);
-        M = better ? w : M;
-        arg = better ? id : arg;
-      }
-    });
+    if (a.tape != nullptr) {
+      S = a.tape[i];
+      Ux = a.tape[n + i];
+      Uy = a.tape[2 * n + i];
+      Uz = a.tape[3 * n + i];
+      M = a.tape[4 * n + i];
+      arg = __float_as_uint(a.tape[5 * n + i]);
+    } else {
+      uint64_t key = 0ull;  // (weight bits << 32 | ~index): unsigned maximum = argmax
+      tile_visit<1>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
+        for (uint32_t c = 0; c < nc; ++c) {
+          const float4 Q = lp[c];
+          const float4 W = lv[c];
+          const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
+          const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
+          const float w = u * u * u;
+          const uint32_t id = __float_as_uint(W.w);
+          S += w;
+          Ux = fmaf(w, W.x, Ux);
+          Uy = fmaf(w, W.y, Uy);
+          Uz = fmaf(w, W.z, Uz);
+          const uint64_t kk = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~id);
+          key = kk > key ? kk : key;
+        }
+      });
+      M = __uint_as_float((uint32_t)(key >> 32));
+      arg = ~(uint32_t)key;  // largest weight, ties to the smallest index; meaningful when M > 0
+    }
     // ---- replay and pull-back; idle lanes carry a zero upstream gradient
     const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
     const float z0 = 0.0f;

@@ -17,6 +17,7 @@ struct Sums {
   float S, Ux, Uy, Uz, M;
   bool gran;
   uint32_t count;
+  uint32_t arg;  // TAPE: original index of the largest weight (ties: smallest index)
 };
 
 // Walk the stencil of HR position (x, y, z) and accumulate the weighted sums
@@ -24,11 +25,11 @@ struct Sums {
 // s < h2 decides the rigid rule; DEBUG also records the member ids.
 // RIGID: the scene has rigid LR particles, so their contributions are dropped
 // when no granular LR particle is in the support.
-template <bool DEBUG, bool RIGID>
+template <bool DEBUG, bool RIGID, bool TAPE = false>
 __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __restrict__ lr,
                                        const uint32_t* __restrict__ cell_start, float x, float y,
                                        float z, uint32_t* ids, int64_t max_k) {
-  Sums r{0.f, 0.f, 0.f, 0.f, 0.f, false, 0u};
+  Sums r{0.f, 0.f, 0.f, 0.f, 0.f, false, 0u, 0xffffffffu};
   const int R = gc.reach;
   const int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
   const int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
@@ -56,6 +57,10 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
           r.Ux = fmaf(w, V.x, r.Ux);
           r.Uy = fmaf(w, V.y, r.Uy);
           r.Uz = fmaf(w, V.z, r.Uz);
+          if (TAPE) {
+            const uint32_t id = __float_as_uint(V.w);
+            if (w > r.M || (w == r.M && id < r.arg)) r.arg = id;
+          }
           r.M = fmaxf(r.M, w);
         }
         // support membership (the exact predicate) decides the rigid rule
@@ -77,6 +82,7 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
     r.S = 0.f;
     r.Ux = r.Uy = r.Uz = 0.f;
     r.M = 0.f;
+    r.arg = 0xffffffffu;
   }
   return r;
 }
@@ -176,7 +182,8 @@ using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries /
 
 // One block-sized tile of HR particles first .. first + kBlock - 1 (those
 // below a.n are live; the rest shadow the last particle and write nothing).
-template <bool RIGID, int G>
+// TAPE: also record (S, Ux, Uy, Uz, M, argmax) per particle for the adjoint.
+template <bool RIGID, int G, bool TAPE = false>
 __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* __restrict__ walls,
                                              GatherLDS<G>& lds, int64_t first) {
   const int lane = threadIdx.x & 63;
@@ -190,11 +197,15 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
   const GridConst& gc = a.gc;
 
   float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
+  uint32_t arg = 0xffffffffu;
+  // TAPE: (weight bits << 32 | ~index) -- its unsigned maximum is the largest
+  // weight and, among equal weights, the smallest index
+  uint64_t key = 0ull;
   const TileSetup<G> ts = tile_setup<G>(gc, a.cell_start, x, y, z, lane, wid, lds);
   if (ts.nrows > lds.kRows || ts.total > (uint32_t)a.tile_max) {
     // spread-out wave: every lane walks its own stencil
-    const Sums s = gather<false, RIGID>(gc, a.lr, a.cell_start, x, y, z, nullptr, 0);
-    S = s.S; Ux = s.Ux; Uy = s.Uy; Uz = s.Uz; M = s.M;
+    const Sums s = gather<false, RIGID, TAPE>(gc, a.lr, a.cell_start, x, y, z, nullptr, 0);
+    S = s.S; Ux = s.Ux; Uy = s.Uy; Uz = s.Uz; M = s.M; arg = s.arg;
   } else {
     const float inv_h2 = gc.inv_h2;
     bool gran = !RIGID;
@@ -210,7 +221,12 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
         Ux = fmaf(w, W.x, Ux);
         Uy = fmaf(w, W.y, Uy);
         Uz = fmaf(w, W.z, Uz);
-        M = fmaxf(M, w);
+        if (TAPE) {
+          const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~__float_as_uint(W.w));
+          key = k > key ? k : key;
+        } else {
+          M = fmaxf(M, w);
+        }
         if (RIGID) {
           const uint32_t bits = __float_as_uint(Q.w);
           // exact membership of a granular LR particle decides the rigid rule
@@ -218,18 +234,34 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
         }
       }
     });
-    if (RIGID && !gran) S = Ux = Uy = Uz = M = 0.f;
+    if (TAPE) {
+      M = __uint_as_float((uint32_t)(key >> 32));
+      arg = ~(uint32_t)key;  // meaningful only when M > 0
+    }
+    if (RIGID && !gran) {
+      S = Ux = Uy = Uz = M = 0.f;
+      arg = 0xffffffffu;
+    }
   }
   if (live) {
     bool A;
     finish(a, walls, i, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, &A);
+    if (TAPE) {
+      const int64_t m = a.n;
+      a.tape[i] = S;
+      a.tape[m + i] = Ux;
+      a.tape[2 * m + i] = Uy;
+      a.tape[3 * m + i] = Uz;
+      a.tape[4 * m + i] = M;
+      a.tape[5 * m + i] = __uint_as_float(arg);
+    }
   }
 }
 
-template <bool RIGID, int G>
+template <bool RIGID, int G, bool TAPE = false>
 __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
   __shared__ GatherLDS<G> lds;
-  advance_tile<RIGID, G>(a, wt.w, lds, (int64_t)blockIdx.x * kBlock);
+  advance_tile<RIGID, G, TAPE>(a, wt.w, lds, (int64_t)blockIdx.x * kBlock);
 }
 
 // Batched step: a persistent grid strides over the (scene, first particle)
@@ -257,6 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_advance_batched(BatchAdvanceArgs b) 
     a.dbg_branch = nullptr;
     a.groups = 1;
     a.tile_max = b.tile_max;
+    a.tape = nullptr;
     advance_tile<RIGID, 1>(a, b.walls + sc.wall_off, lds, (int64_t)tile.first);
   }
 }
@@ -268,6 +301,10 @@ hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool deb
   const unsigned blocks = (unsigned)((a.n + kBlock - 1) / kBlock);
   if (debug)
     hipLaunchKernelGGL(k_advance<true>, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  else if (a.tape != nullptr && a.sc.has_rigid)
+    hipLaunchKernelGGL((k_advance_tiled<true, 1, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  else if (a.tape != nullptr)
+    hipLaunchKernelGGL((k_advance_tiled<false, 1, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
   else if (a.sc.has_rigid)
     hipLaunchKernelGGL((k_advance_tiled<true, 1>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
   else if (a.groups == 4)

@@ -82,6 +82,7 @@ struct AdvanceArgs {
   uint8_t* dbg_branch;
   int groups;    // lane groups per wave in the tiled gather: 1, 2 or 4 (a tuning knob)
   int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
+  float* tape;   // [6][n] (S, Ux, Uy, Uz, M, argmax bits) or null
 };
 hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool debug, hipStream_t st);
 
@@ -156,6 +157,7 @@ struct AdjointArgs {
   int64_t n_lr;
   int tiled;     // 1: wave-tiled kernel (non-rigid scenes), 0: one particle per lane
   int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
+  const float* tape;  // forward record [6][n] (skips the recomputation of the sums) or null
 };
 hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st);
 

@@ -400,7 +400,7 @@ static hipError_t fold_timing(upsample_handle h, int64_t upto) {
 
 static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
                         float* hr_v_out, int64_t n_hr, void* stream, bool debug, uint32_t* count,
-                        uint32_t* ids, int64_t max_k, uint8_t* branch) {
+                        uint32_t* ids, int64_t max_k, uint8_t* branch, float* tape = nullptr) {
   if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
   if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
   if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr || hr_x_out == nullptr || hr_v_out == nullptr))
@@ -431,6 +431,7 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
   a.dbg_branch = branch;
   a.groups = h->tune.gather_groups;
   a.tile_max = h->tune.tile_max;
+  a.tape = tape;
   const bool timed = h->timing && !debug && n_hr > 0;
   hipError_t e = hipSuccess;
   int slot = 0;
@@ -469,11 +470,25 @@ int upsample_step(upsample_handle h, const float* lr_x, const float* lr_v, const
   return upsample_advance(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream);
 }
 
-int upsample_step_backward(upsample_handle h, const float* lr_x, const float* lr_v,
-                           const uint8_t* lr_rigid, int64_t n_lr, const float* hr_x,
-                           const float* hr_v, int64_t n_hr, const float* gx_out,
-                           const float* gv_out, float* gx_in, float* gv_in, float* g_lr_x,
-                           float* g_lr_v, void* stream) {
+int upsample_step_taped(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                        int64_t n_lr, const float* hr_x, const float* hr_v, float* hr_x_out, float* hr_v_out,
+                        int64_t n_hr, float* tape, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
+  if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
+  if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr || hr_x_out == nullptr || hr_v_out == nullptr ||
+                   tape == nullptr))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR or tape pointer is NULL");
+  int rc = upsample_build_grid(h, lr_x, lr_v, lr_rigid, n_lr, stream);
+  if (rc != UPSAMPLE_OK) return rc;
+  return advance_impl(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream, false, nullptr, nullptr, 0, nullptr,
+                      tape);
+}
+
+static int backward_impl(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                         int64_t n_lr, const float* hr_x, const float* hr_v, int64_t n_hr, const float* tape,
+                         const float* gx_out, const float* gv_out, float* gx_in, float* gv_in, float* g_lr_x,
+                         float* g_lr_v, void* stream) {
   if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
   if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
   if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
@@ -506,9 +521,30 @@ int upsample_step_backward(upsample_handle h, const float* lr_x, const float* lr
   a.n_lr = n_lr;
   a.tiled = h->tune.adjoint_tiled;
   a.tile_max = h->tune.adjoint_tile_max;
+  a.tape = tape;
   hipError_t e = launch_adjoint(a, wall_table(h), st);
   if (e != hipSuccess) return hip_fail(h, e, "step_backward");
   return UPSAMPLE_OK;
+}
+
+int upsample_step_backward(upsample_handle h, const float* lr_x, const float* lr_v,
+                           const uint8_t* lr_rigid, int64_t n_lr, const float* hr_x,
+                           const float* hr_v, int64_t n_hr, const float* gx_out,
+                           const float* gv_out, float* gx_in, float* gv_in, float* g_lr_x,
+                           float* g_lr_v, void* stream) {
+  return backward_impl(h, lr_x, lr_v, lr_rigid, n_lr, hr_x, hr_v, n_hr, nullptr, gx_out, gv_out, gx_in, gv_in,
+                       g_lr_x, g_lr_v, stream);
+}
+
+int upsample_step_backward_taped(upsample_handle h, const float* lr_x, const float* lr_v,
+                                 const uint8_t* lr_rigid, int64_t n_lr, const float* hr_x,
+                                 const float* hr_v, int64_t n_hr, const float* tape, const float* gx_out,
+                                 const float* gv_out, float* gx_in, float* gv_in, float* g_lr_x,
+                                 float* g_lr_v, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_hr > 0 && tape == nullptr) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "tape is NULL");
+  return backward_impl(h, lr_x, lr_v, lr_rigid, n_lr, hr_x, hr_v, n_hr, tape, gx_out, gv_out, gx_in, gv_in,
+                       g_lr_x, g_lr_v, stream);
 }
 
 int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,

@@ -39,6 +39,12 @@ def _u8(t: Optional[torch.Tensor], n: int, name: str) -> Optional[torch.Tensor]:
     return t
 
 
+def _tape(t: torch.Tensor, n: int) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.shape == (6, n) and t.is_contiguous()):
+        raise ValueError(f"tape must be a contiguous float32 device tensor of shape [6, {n}]")
+    return t
+
+
 def make_params(r_lr: float, r_hr: float, dt: float, g: Sequence[float], domain_lo, domain_hi,
                 walls=None, max_lr: int = 0, max_hr: int = 0, c1: float = 512.0 / 729.0,
                 c2: float = 0.6, cell_factor: float = 0.0, validate: bool = False):
@@ -172,7 +178,9 @@ class Upsampler:
                                              n, _stream()))
         return out_x, out_v
 
-    def step(self, lr_x, lr_v, lr_rigid, hr_x, hr_v, out_x=None, out_v=None):
+    def step(self, lr_x, lr_v, lr_rigid, hr_x, hr_v, out_x=None, out_v=None, tape=None):
+        """One step; with ``tape`` ([6, N] float32, see upsample_step_taped)
+        the forward sums are recorded for step_backward."""
         nl = _soa(lr_x, "lr_x").shape[1]
         _soa(lr_v, "lr_v")
         _u8(lr_rigid, nl, "lr_rigid")
@@ -180,15 +188,22 @@ class Upsampler:
         _soa(hr_v, "hr_v")
         out_x = torch.empty_like(hr_x) if out_x is None else _soa(out_x, "out_x")
         out_v = torch.empty_like(hr_v) if out_v is None else _soa(out_v, "out_v")
-        self._check(self._L.upsample_step(self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl,
-                                          _ptr(hr_x), _ptr(hr_v), _ptr(out_x), _ptr(out_v), n,
-                                          _stream()))
+        if tape is None:
+            self._check(self._L.upsample_step(self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl,
+                                              _ptr(hr_x), _ptr(hr_v), _ptr(out_x), _ptr(out_v), n,
+                                              _stream()))
+        else:
+            _tape(tape, n)
+            self._check(self._L.upsample_step_taped(self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl,
+                                                    _ptr(hr_x), _ptr(hr_v), _ptr(out_x), _ptr(out_v), n,
+                                                    _ptr(tape), _stream()))
         return out_x, out_v
 
     def step_backward(self, lr_x, lr_v, lr_rigid, hr_x, hr_v, gx_out, gv_out,
-                      g_lr_x=None, g_lr_v=None, gx_in=None, gv_in=None):
+                      g_lr_x=None, g_lr_v=None, gx_in=None, gv_in=None, tape=None):
         """Returns (gx_in, gv_in, g_lr_x, g_lr_v); LR gradients are ADDED into
-        g_lr_x / g_lr_v when given (zeros otherwise)."""
+        g_lr_x / g_lr_v when given (zeros otherwise).  ``tape``: the record of
+        the taped forward step on the same inputs (skips the recomputation)."""
         nl = _soa(lr_x, "lr_x").shape[1]
         _soa(lr_v, "lr_v")
         _u8(lr_rigid, nl, "lr_rigid")
@@ -199,9 +214,15 @@ class Upsampler:
         g_lr_v = torch.zeros_like(lr_v) if g_lr_v is None else _soa(g_lr_v, "g_lr_v")
         gx_in = torch.empty_like(hr_x) if gx_in is None else _soa(gx_in, "gx_in")
         gv_in = torch.empty_like(hr_v) if gv_in is None else _soa(gv_in, "gv_in")
-        self._check(self._L.upsample_step_backward(
-            self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl, _ptr(hr_x), _ptr(hr_v), n,
-            _ptr(gx_out), _ptr(gv_out), _ptr(gx_in), _ptr(gv_in), _ptr(g_lr_x), _ptr(g_lr_v), _stream()))
+        if tape is None:
+            self._check(self._L.upsample_step_backward(
+                self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl, _ptr(hr_x), _ptr(hr_v), n,
+                _ptr(gx_out), _ptr(gv_out), _ptr(gx_in), _ptr(gv_in), _ptr(g_lr_x), _ptr(g_lr_v), _stream()))
+        else:
+            _tape(tape, n)
+            self._check(self._L.upsample_step_backward_taped(
+                self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl, _ptr(hr_x), _ptr(hr_v), n, _ptr(tape),
+                _ptr(gx_out), _ptr(gv_out), _ptr(gx_in), _ptr(gv_in), _ptr(g_lr_x), _ptr(g_lr_v), _stream()))
         return gx_in, gv_in, g_lr_x, g_lr_v
 
     def sort_hr(self, hr_x, hr_v, with_perm: bool = True, out_x=None, out_v=None):

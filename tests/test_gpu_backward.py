@@ -153,15 +153,59 @@ def test_rollout_reorder_is_transparent(U):
     v0 = dev(sc.hr_v0[:, shuffle].copy(), torch)
     w = torch.randn_like(x0)
     res = {}
-    for reorder in (False, True):
+    for reorder, re in ((False, 0), (True, 0), (True, 2)):
         LVg = LV.clone().requires_grad_(True)
         x0g = x0.clone().requires_grad_(True)
-        xT, vT = rollout(up, x0g, v0, LX, LVg, checkpoint_every=every, reorder=reorder)
+        xT, vT = rollout(up, x0g, v0, LX, LVg, checkpoint_every=every, reorder=reorder, reorder_every=re)
         (xT * w).sum().backward()
         torch.cuda.synchronize()
-        res[reorder] = (xT.detach(), vT.detach(), host(LVg.grad), host(x0g.grad))
-    assert torch.equal(res[False][0], res[True][0]) and torch.equal(res[False][1], res[True][1])
-    e_v = rel(res[True][2], res[False][2].astype(np.float64))
-    e_0 = rel(res[True][3], res[False][3].astype(np.float64))
-    log(f"reorder rollout: rel dV {e_v:.2e} dx0 {e_0:.2e}")
-    assert e_v < 1e-5 and e_0 < 1e-5
+        res[(reorder, re)] = (xT.detach(), vT.detach(), host(LVg.grad), host(x0g.grad))
+    base = res[(False, 0)]
+    for key in ((True, 0), (True, 2)):
+        r = res[key]
+        assert torch.equal(base[0], r[0]) and torch.equal(base[1], r[1]), key
+        e_v = rel(r[2], base[2].astype(np.float64))
+        e_0 = rel(r[3], base[3].astype(np.float64))
+        log(f"reorder rollout {key}: rel dV {e_v:.2e} dx0 {e_0:.2e}")
+        assert e_v < 1e-5 and e_0 < 1e-5
+
+
+@pytest.mark.parametrize("case", ["plain", "rigid", "drain"])
+def test_taped_step_and_adjoint(U, case):
+    # the taped forward writes the same state as the plain step and records
+    # the sums; the taped adjoint matches the recomputing one and the oracle
+    if case == "rigid":
+        sc = build_scene("heap", 1500, 30001, seed=[21, 3], rigid_floor=True)
+        X, V = sc.lr_frame(1)
+        up = U.from_scene(sc, max_lr=X.shape[1])
+        rig = sc.lr_rigid
+    else:
+        sc = configs.plain() if case == "plain" else configs.drain(scale=1 / 16)
+        X, V = sc.lr_frame(2)
+        up = U.from_scene(sc)
+        rig = None
+    rng = np.random.default_rng(12)
+    hx, hv = dev(sc.hr_x0, torch), dev(rng.normal(0, 0.5, sc.hr_x0.shape).astype(np.float32), torch)
+    if case == "drain":
+        up.sort_hr(hx, hv, with_perm=False)
+    Xd, Vd = dev(X, torch), dev(V, torch)
+    rd = None if rig is None else dev(rig, torch)
+    tape = torch.empty((6, sc.n_hr), dtype=torch.float32, device="cuda")
+    x0, v0 = up.step(Xd, Vd, rd, hx, hv)
+    x1, v1 = up.step(Xd, Vd, rd, hx, hv, tape=tape)
+    torch.cuda.synchronize()
+    assert torch.equal(x0, x1) and torch.equal(v0, v1)
+    # the record against the oracle's sums (membership of the float32 predicate)
+    o = O.step(X, V, rig, host(hx), host(hv), sc.params())
+    t = host(tape).astype(np.float64)
+    np.testing.assert_allclose(t[0], o["S"], rtol=2e-5, atol=1e-6)
+    np.testing.assert_allclose(t[4], o["M"], rtol=2e-5, atol=1e-6)
+    gxo = torch.randn_like(hx)
+    gvo = torch.randn_like(hv)
+    a = up.step_backward(Xd, Vd, rd, hx, hv, gxo, gvo)
+    b = up.step_backward(Xd, Vd, rd, hx, hv, gxo, gvo, tape=tape)
+    torch.cuda.synchronize()
+    for p_, q_ in zip(a, b):
+        assert rel(host(q_), host(p_).astype(np.float64)) < 1e-5
+    errs = _check_step(up, sc, X, V, rig, host(hx), host(hv), host(gxo), host(gvo))
+    log(f"taped adjoint {case}: {errs}")
