@@ -468,14 +468,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
     const int ca1 = (row == 0) ? 2 : (row == 1) ? 0 : (row == 2) ? 5 : 3;  // r1: a2 b0 a5 b3
     const bool cb1 = (row == 1) || (row == 3);             //     (b entries in rows 1, 3)
     const int ca2 = (row == 0) ? 1 : (row == 1) ? 2 : (row == 2) ? 4 : 5;  // r2: b1 b2 b4 b5
-    auto add_out = [&](int comp, uint32_t slot, uint32_t id, float v) {
-      if (block_acc) {
-        atomicAdd(&acc[comp][slot], v);
-      } else {
-        float* dst = comp < 3 ? a.g_lr_v + (int64_t)comp * nl : a.g_lr_x + (int64_t)(comp - 3) * nl;
-        unsafeAtomicAdd(dst + id, v);
-      }
+    // destinations of this lane's three reduced values (per row, fixed for the loop)
+    auto lr_grad = [&](int comp) {
+      return comp < 3 ? a.g_lr_v + (int64_t)comp * nl : a.g_lr_x + (int64_t)(comp - 3) * nl;
     };
+    float* const dst0 = lr_grad(ca0);
+    float* const dst1 = lr_grad(ca1);
+    float* const dst2 = lr_grad(ca2);
     auto pair_pass = [&](uint32_t nc, const float4* lp, const float4* lv) {
       // two candidates per iteration; the next pair is read ahead
       float4 QA = lp[0], WA = lv[0];
@@ -496,13 +495,20 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
         }
         float r0, r1, r2;
         reduce12(va, vb, &r0, &r1, &r2);
+        // Without a second candidate, QB / WB repeat the first one and its
+        // components are zero: the adds below stay branch-free.
         if (row_tail) {
           const uint32_t sa = __float_as_uint(QA.w), sbb = __float_as_uint(QB.w);
           const uint32_t ia = __float_as_uint(WA.w), ib = __float_as_uint(WB.w);
-          add_out(ca0, sa, ia, r0);
-          if (!cb1) add_out(ca1, sa, ia, r1);
-          else if (has_b) add_out(ca1, sbb, ib, r1);
-          if (has_b) add_out(ca2, sbb, ib, r2);
+          if (block_acc) {
+            atomicAdd(&acc[ca0][sa], r0);
+            atomicAdd(&acc[ca1][cb1 ? sbb : sa], r1);
+            atomicAdd(&acc[ca2][sbb], r2);
+          } else {
+            unsafeAtomicAdd(dst0 + ia, r0);
+            unsafeAtomicAdd(dst1 + (cb1 ? ib : ia), r1);
+            unsafeAtomicAdd(dst2 + ib, r2);
+          }
         }
         QA = QA2; WA = WA2; QB = QB2; WB = WB2;
       }
