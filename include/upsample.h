@@ -214,7 +214,9 @@ int upsample_step_backward_taped(upsample_handle h,
  * alias their inputs for an in-place reorder through scratch, or neither).
  * perm_out (device int32 [n_hr], may be NULL) receives, for each new position,
  * the particle's old index.  The order inside a sub-cell is unspecified.
- * Per-particle results of later steps do not depend on the order.
+ * Later steps compute the same per-particle results in any order, up to
+ * float32 rounding (the weights of a compact wave are taken relative to its
+ * box centre).
  */
 int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
                      float* hr_v_out, int64_t n_hr, int32_t* perm_out, void* stream);

@@ -44,9 +44,10 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
       const uint32_t e = cell_start[row + (uint32_t)x1 + 1u];
       for (uint32_t j = b; j < e; ++j) {
         const float4 P = lr[j].p;
-        // the same weight arithmetic, candidate order and zero test as the
-        // wave-tiled path, so a particle's sums do not depend on which path
-        // its wave takes
+        // the candidate order and zero test of the wave-tiled path and its
+        // direct-form weight arithmetic (bit-identical to the tiled path for
+        // waves wider than 2h and for rigid scenes; the dot-product form of
+        // compact waves differs by rounding)
         const float dx = P.x - x, dy = P.y - y, dz = P.z - z;
         const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const float t = fmaxf(fmaf(-sq, gc.inv_h2, 1.0f), 0.0f);
@@ -180,6 +181,20 @@ constexpr int kGatherRows = 64;
 template <int G>
 using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries / G : 64), kGatherRows>;
 
+// Staging of the dot-product form: q = X - c relative to the wave's box
+// centre c and B = -|q|^2 / h^2, so that for a lane at p = x - c
+//   u = 1 - |q - p|^2 / h^2 = (1 - |p|^2 / h^2) + B + (2 / h^2) p . q
+// takes one add and three fmas per candidate.  Used only for waves whose box
+// is at most 2h wide, where the cancellation stays far below the tolerance.
+struct DotStage {
+  float cx, cy, cz, inv_h2;
+  __device__ __forceinline__ float4 operator()(float4 P, uint32_t) const {
+    const float qx = P.x - cx, qy = P.y - cy, qz = P.z - cz;
+    return make_float4(qx, qy, qz, -(fmaf(qz, qz, fmaf(qy, qy, qx * qx)) * inv_h2));
+  }
+  __device__ __forceinline__ float4 pad() const { return make_float4(0.0f, 0.0f, 0.0f, -3.0e38f); }
+};
+
 // One block-sized tile of HR particles first .. first + kBlock - 1 (those
 // below a.n are live; the rest shadow the last particle and write nothing).
 // TAPE: also record (S, Ux, Uy, Uz, M, argmax) per particle for the adjoint.
@@ -209,6 +224,40 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
   } else {
     const float inv_h2 = gc.inv_h2;
     bool gran = !RIGID;
+    // the wave's box (union of its groups)
+    float lo0 = ts.gb[0].lo[0], lo1 = ts.gb[0].lo[1], lo2 = ts.gb[0].lo[2];
+    float hi0 = ts.gb[0].hi[0], hi1 = ts.gb[0].hi[1], hi2 = ts.gb[0].hi[2];
+#pragma unroll
+    for (int g = 1; g < G; ++g) {
+      lo0 = fminf(lo0, ts.gb[g].lo[0]); lo1 = fminf(lo1, ts.gb[g].lo[1]); lo2 = fminf(lo2, ts.gb[g].lo[2]);
+      hi0 = fmaxf(hi0, ts.gb[g].hi[0]); hi1 = fmaxf(hi1, ts.gb[g].hi[1]); hi2 = fmaxf(hi2, ts.gb[g].hi[2]);
+    }
+    const float ext = fmaxf(hi0 - lo0, fmaxf(hi1 - lo1, hi2 - lo2));
+    if (!RIGID && ext * ext <= 4.0f * gc.h2) {
+      const DotStage ds{0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2), inv_h2};
+      const float px = x - ds.cx, py = y - ds.cy, pz = z - ds.cz;
+      const float A = fmaf(-fmaf(pz, pz, fmaf(py, py, px * px)), inv_h2, 1.0f);
+      const float k2 = 2.0f * inv_h2;
+      const float Px = k2 * px, Py = k2 * py, Pz = k2 * pz;
+      tile_visit<G>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
+        for (uint32_t c = 0; c < nc; ++c) {
+          const float4 Q = lp[c];
+          const float4 W = lv[c];
+          const float u = fmaxf(fmaf(Q.x, Px, fmaf(Q.y, Py, fmaf(Q.z, Pz, A + Q.w))), 0.0f);
+          const float w = u * u * u;
+          S += w;
+          Ux = fmaf(w, W.x, Ux);
+          Uy = fmaf(w, W.y, Uy);
+          Uz = fmaf(w, W.z, Uz);
+          if (TAPE) {
+            const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~__float_as_uint(W.w));
+            key = k > key ? k : key;
+          } else {
+            M = fmaxf(M, w);
+          }
+        }
+      }, SortedTag(), ds);
+    } else {
     tile_visit<G>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
       for (uint32_t c = 0; c < nc; ++c) {
         const float4 Q = lp[c];
@@ -234,6 +283,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
         }
       }
     });
+    }
     if (TAPE) {
       M = __uint_as_float((uint32_t)(key >> 32));
       arg = ~(uint32_t)key;  // meaningful only when M > 0

@@ -173,17 +173,28 @@ struct SortedTag {
   }
 };
 
+// Default staging: the candidate's position with its tag; padding entries sit
+// far away (weight exactly 0 for every lane).
+struct PlainStage {
+  __device__ __forceinline__ float4 operator()(float4 P, uint32_t bits) const {
+    return make_float4(P.x, P.y, P.z, __uint_as_float(bits));
+  }
+  __device__ __forceinline__ float4 pad() const { return make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f); }
+};
+
 // Stream the candidates and hand the LDS lists to visit(nc, p_list, v_list)
 // in chunks; p_list / v_list point at this lane's group list.  tag(row, k, j,
 // flag) gives the 32 bits stored in the .w of the position entry.
-template <int G, class L, class Visit, class Tag = SortedTag>
+// stage(P, tag) gives the 16 bytes stored for a kept candidate (culling
+// always uses its absolute position); stage.pad() the padding entry.
+template <int G, class L, class Visit, class Tag = SortedTag, class Stage = PlainStage>
 __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridConst& gc,
                                            const LRPoint* __restrict__ lr, int lane, int wid,
-                                           L& lds, Visit&& visit, Tag tag = Tag()) {
+                                           L& lds, Visit&& visit, Tag tag = Tag(), Stage stage = Stage()) {
   constexpr int kCap = L::kCap;
   const int grp = lane / (64 / G);
   const float cull2 = gc.h2 * 1.001f;
-  const float4 far_p = make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f);
+  const float4 far_p = stage.pad();
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
   uint32_t cnt[G];
 #pragma unroll
@@ -208,7 +219,7 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
 #pragma unroll
       for (int g = 0; g < G; ++g) keep[g] = box_dist2(ts.gb[g], P.x, P.y, P.z) <= cull2;
     }
-    const float4 pj = make_float4(P.x, P.y, P.z, __uint_as_float(bits));
+    const float4 pj = stage(P, bits);
     uint32_t nmax = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {

@@ -13,7 +13,7 @@ from oracle import upsample_oracle as O
 from workloads import configs
 from workloads.generators import build_scene
 
-from gpu_util import compare_step, dev, host, log, morton_sort_keys
+from gpu_util import assert_same_step, compare_step, dev, host, log, morton_sort_keys
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -207,7 +207,7 @@ def test_deterministic_and_order_independent(U):
     b = up.step(Xd, Vd, None, hx, hv)
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
-    # reorder HR by cell: per-particle results are unchanged, bit for bit
+    # reorder HR by cell: per-particle results agree to rounding (the waves change)
     sx, sv = hx.clone(), hv.clone()
     perm = up.sort_hr(sx, sv).long()
     assert torch.equal(torch.sort(perm).values, torch.arange(sc.n_hr, device="cuda"))
@@ -217,7 +217,7 @@ def test_deterministic_and_order_independent(U):
     assert np.all(np.diff(k) >= 0)
     c = up.step(Xd, Vd, None, sx, sv)
     torch.cuda.synchronize()
-    assert torch.equal(c[0], a[0][:, perm]) and torch.equal(c[1], a[1][:, perm])
+    assert_same_step(c[0], c[1], a[0][:, perm], a[1][:, perm], sc.box_length)
 
 
 @pytest.mark.parametrize("groups", [1, 2, 4])
@@ -239,10 +239,11 @@ def test_gather_group_variants_match_oracle(U, groups):
 
 
 @pytest.mark.parametrize("rigid", [False, True])
-def test_wave_paths_bit_identical(U, rigid):
+def test_wave_paths_agree(U, rigid):
     # each wave either tiles its candidates through LDS or walks per lane,
-    # chosen by how many candidates it would stream; the choice must not
-    # change any particle's result
+    # chosen by how many candidates it would stream; the choice changes a
+    # particle's result by rounding only (bit for bit with rigid particles,
+    # whose tiled weights use absolute coordinates like the per-lane walk)
     if rigid:
         sc = build_scene("heap", 1500, 30001, seed=[21, 3], rigid_floor=True)
         X, V = sc.lr_frame(1)
@@ -261,7 +262,10 @@ def test_wave_paths_bit_identical(U, rigid):
         out.append(up.step(dev(X, torch), dev(V, torch), rig, hx, hv))
     torch.cuda.synchronize()
     for o in out[1:]:
-        assert torch.equal(o[0], out[0][0]) and torch.equal(o[1], out[0][1])
+        if rigid:
+            assert torch.equal(o[0], out[0][0]) and torch.equal(o[1], out[0][1])
+        else:
+            assert_same_step(o[0], o[1], out[0][0], out[0][1], sc.box_length)
     s = compare_step(host(out[0][0]), host(out[0][1]), X, V, sc.lr_rigid if rigid else None, host(hx), host(hv),
                      sc.params(), sc.box_length, idx=_sample(sc.n_hr, 16384, 10))
     log(f"wave paths rigid={rigid}: {s}")
