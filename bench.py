@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--groups", type=int, default=0, help="gather lane groups per wave (0: library default)")
     ap.add_argument("--cell-factor", type=float, default=0.0, help="fixed kappa (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the autotuner")
+    ap.add_argument("--step-loop", action="store_true",
+                    help="drain: one upsample_step call per step instead of upsample_run")
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched legs")
@@ -118,11 +120,18 @@ def drain_leg(args, torch, Upsampler):
     gi = up.grid_info()
     log(f"drain: setup {time.time() - t0:.1f}s, grid {gi['dims']} reach {gi['reach']} tuning {up.get_tuning()}")
     up.sort_hr(hx, hv, with_perm=False)
-    # HR state ping-pongs between two buffer pairs: the reorder writes the other pair
+    # HR state ping-pongs between two buffer pairs in the step loop: the
+    # reorder writes the other pair; upsample_run works in place
     state = [hx, hv, torch.empty_like(hx), torch.empty_like(hv)]
 
     def run(first, count, timed_kernel=False):
         up.timing_enable(timed_kernel)
+        if not args.step_loop:
+            # every step's grid is built on a second stream while the previous
+            # step's gather runs; reorders every sort_every steps
+            up.run(LX[first:first + count], LV[first:first + count], state[0], state[1],
+                   sort_every=args.sort_every)
+            return
         for k in range(count):
             t = first + k
             if args.sort_every and t % args.sort_every == 0:
@@ -169,6 +178,7 @@ def drain_leg(args, torch, Upsampler):
            "config": {"workload": "drain", "n_lr": sc.n_lr, "n_hr": sc.n_hr, "r_lr": sc.r_lr,
                       "r_hr": sc.r_hr, "dt": sc.dt, "walls": int(sc.walls.shape[0]),
                       "grid": list(gi["dims"]), "reach": gi["reach"], "sort_every": args.sort_every,
+                      "entry": "upsample_step loop" if args.step_loop else "upsample_run",
                       "cell_size": gi["cell_size"], "tuning": up.get_tuning(),
                       "autotuned": tune is not None},
            "roofline": rf, "scene": sc, "frames": frames}

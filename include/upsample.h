@@ -207,6 +207,26 @@ int upsample_step_backward_taped(upsample_handle h,
                                  void* stream);
 
 /*
+ * Multi-step run: advances the HR state in place through n_frames
+ * consecutive LR frames (lr_x, lr_v: device [n_frames][3][n_lr]; lr_rigid, if
+ * given, applies to every frame), i.e. n_frames upsample_step calls.  Before
+ * step t the state is reordered as by upsample_sort_hr when sort_every > 0
+ * and t % sort_every == 0.  Each frame's grid is built on an internal stream
+ * into one of two buffers while the previous frame's step kernel runs; HIP
+ * events order the two streams, and everything is done when the caller's
+ * stream reaches the call's end.  perm_io (device int32 [n_hr], may be NULL)
+ * maps positions to particles: on entry the particle at each position (for
+ * instance 0, 1, 2, ...), on return the same after the reorders.  The
+ * handle's grid afterwards is the last frame's.  The first call allocates a
+ * second grid buffer and the internal stream.  Results per particle equal
+ * those of the step-by-step loop up to float32 rounding (reorders change the
+ * waves).
+ */
+int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                 int64_t n_lr, int32_t n_frames, float* hr_x, float* hr_v, int64_t n_hr,
+                 int32_t sort_every, int32_t* perm_io, void* stream);
+
+/*
  * Reorder HR particles by grid cell and, inside a cell, by the Morton order of
  * sort_sub^3 sub-cells (upsample_tuning), so that consecutive particles -- the
  * lanes of one wave of the step kernel -- occupy a compact box.  Reads hr_x,

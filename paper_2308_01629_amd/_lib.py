@@ -96,6 +96,7 @@ SIGNATURES = {
     "upsample_step_taped": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P, _P]),
     "upsample_step_backward_taped": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
                                             _P]),
+    "upsample_run": (_INT, [_P, _P, _P, _P, _I64, _I32, _P, _P, _I64, _I32, _P, _P]),
     "upsample_sort_hr": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _P]),
     "upsample_permute": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _INT, _P]),
     "upsample_debug_grid": (_INT, [_P, _P, _P, _P, _P]),

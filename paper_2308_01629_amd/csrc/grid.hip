@@ -440,6 +440,27 @@ hipError_t launch_permute(const float* a, const float* b, float* ao, float* bo, 
   return hipGetLastError();
 }
 
+// tmp[i] = perm_io[p[i]]: the original index of each position after a reorder
+// whose permutation is p, given perm_io before it.
+__global__ __launch_bounds__(kBlock) void k_compose_perm(const int32_t* __restrict__ perm_io,
+                                                         const int32_t* __restrict__ p, int64_t n,
+                                                         int32_t* __restrict__ tmp) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t q = p[i];
+  if (q < 0 || (int64_t)q >= n) return;  // defensive: p is a permutation of [0, n)
+  tmp[i] = perm_io[q];
+}
+
+hipError_t launch_compose_perm(int32_t* perm_io, const int32_t* p, int64_t n, uint32_t* tmp, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int32_t* t = reinterpret_cast<int32_t*>(tmp);
+  hipLaunchKernelGGL(k_compose_perm, dim3(blocks_for(n)), dim3(kBlock), 0, st, perm_io, p, n, t);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(perm_io, t, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+  return e;
+}
+
 hipError_t launch_check_finite(const float* p, int64_t n, uint32_t* flag, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n)), dim3(kBlock), 0, st, p, n, flag);

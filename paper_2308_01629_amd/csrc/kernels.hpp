@@ -163,6 +163,8 @@ hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStrea
 
 // VALIDATE flag: sets *flag to 1 if any of the n floats is NaN or Inf.
 hipError_t launch_check_finite(const float* p, int64_t n, uint32_t* flag, hipStream_t st);
+// perm_io[i] <- perm_io[p[i]] through tmp (n entries of scratch).
+hipError_t launch_compose_perm(int32_t* perm_io, const int32_t* p, int64_t n, uint32_t* tmp, hipStream_t st);
 hipError_t launch_permute(const float* a, const float* b, float* ao, float* bo, int64_t n, const int32_t* perm,
                           int scatter, uint32_t* bad, hipStream_t st);
 

@@ -22,6 +22,14 @@ struct upsample_handle_s {
   int n_chunks;
   GridScratch g;
   HRSortScratch hs;
+  // upsample_run: second grid buffer, its build stream and events, the
+  // permutation scratch (allocated at the first call)
+  GridScratch g2;
+  bool run_ready;
+  bool g2_dirty;
+  hipStream_t side;
+  hipEvent_t built[2], consumed[2], entry;
+  int32_t* run_perm;
   uint32_t* finite_flag;
   bool grid_valid;
   bool counts_dirty;     // an interrupted build may have left counts non-zero
@@ -138,9 +146,19 @@ void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
                   h->g.ticket, h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.x,
                   h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum, h->hs.ticket,
-                  h->finite_flag};
+                  h->finite_flag, h->g2.keys, h->g2.slot, h->g2.tmp, h->g2.perm, h->g2.counts,
+                  h->g2.local, h->g2.chunk_sum, h->g2.ticket, h->g2.cell_start, h->g2.lr_sorted,
+                  h->run_perm};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
+  if (h->run_ready) {
+    (void)hipStreamDestroy(h->side);
+    for (int k = 0; k < 2; ++k) {
+      (void)hipEventDestroy(h->built[k]);
+      (void)hipEventDestroy(h->consumed[k]);
+    }
+    (void)hipEventDestroy(h->entry);
+  }
 }
 
 GridConst grid_const(const upsample_handle h) {
@@ -400,7 +418,8 @@ static hipError_t fold_timing(upsample_handle h, int64_t upto) {
 
 static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
                         float* hr_v_out, int64_t n_hr, void* stream, bool debug, uint32_t* count,
-                        uint32_t* ids, int64_t max_k, uint8_t* branch, float* tape = nullptr) {
+                        uint32_t* ids, int64_t max_k, uint8_t* branch, float* tape = nullptr,
+                        const GridScratch* grid = nullptr) {
   if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
   if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
   if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr || hr_x_out == nullptr || hr_v_out == nullptr))
@@ -417,8 +436,9 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
   AdvanceArgs a;
   a.gc = grid_const(h);
   a.sc = step_const(h);
-  a.lr = h->g.lr_sorted;
-  a.cell_start = h->g.cell_start;
+  const GridScratch& gs = grid != nullptr ? *grid : h->g;
+  a.lr = gs.lr_sorted;
+  a.cell_start = gs.cell_start;
   a.hx = hr_x;
   a.hv = hr_v;
   a.hx_out = hr_x_out;
@@ -545,6 +565,146 @@ int upsample_step_backward_taped(upsample_handle h, const float* lr_x, const flo
   if (n_hr > 0 && tape == nullptr) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "tape is NULL");
   return backward_impl(h, lr_x, lr_v, lr_rigid, n_lr, hr_x, hr_v, n_hr, tape, gx_out, gv_out, gx_in, gv_in,
                        g_lr_x, g_lr_v, stream);
+}
+
+static int run_prepare(upsample_handle h, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (!h->run_ready) {
+    const int64_t nl = h->p.max_lr, nh = h->p.max_hr;
+#define ALLOC(ptr, n) \
+  if (e == hipSuccess) e = dmalloc(&(ptr), (n));
+    ALLOC(h->g2.keys, nl)
+    ALLOC(h->g2.slot, nl)
+    ALLOC(h->g2.tmp, nl)
+    ALLOC(h->g2.perm, nl)
+    ALLOC(h->g2.counts, h->n_cells)
+    ALLOC(h->g2.local, h->n_cells)
+    ALLOC(h->g2.chunk_sum, h->n_chunks + 1)
+    ALLOC(h->g2.ticket, 1)
+    ALLOC(h->g2.cell_start, h->n_cells + 1)
+    ALLOC(h->g2.lr_sorted, nl)
+    ALLOC(h->run_perm, nh)
+#undef ALLOC
+    hipEvent_t* evs[5] = {&h->built[0], &h->built[1], &h->consumed[0], &h->consumed[1], &h->entry};
+    for (hipEvent_t* ev : evs) *ev = nullptr;
+    h->side = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    for (hipEvent_t* ev : evs)
+      if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      // the handle stays usable without upsample_run; buffers are freed with it
+      for (hipEvent_t* ev : evs)
+        if (*ev != nullptr) (void)hipEventDestroy(*ev);
+      if (h->side != nullptr) (void)hipStreamDestroy(h->side);
+      return hip_fail(h, e, "run: allocation");
+    }
+    h->run_ready = true;
+    h->g2_dirty = true;
+  }
+  if (h->g2_dirty) {
+    e = hipMemsetAsync(h->g2.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->g2.ticket, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return hip_fail(h, e, "run");
+    h->g2_dirty = false;
+  }
+  if (h->counts_dirty) {
+    e = hipMemsetAsync(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->g.ticket, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return hip_fail(h, e, "run");
+    h->counts_dirty = false;
+  }
+  return UPSAMPLE_OK;
+}
+
+int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid, int64_t n_lr,
+                 int32_t n_frames, float* hr_x, float* hr_v, int64_t n_hr, int32_t sort_every, int32_t* perm_io,
+                 void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_frames < 1) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_frames < 1");
+  if (sort_every < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_every < 0");
+  if (n_lr < 0 || n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "negative count");
+  if (n_lr > h->p.max_lr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_lr exceeds max_lr");
+  if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
+  if (n_lr > 0 && (lr_x == nullptr || lr_v == nullptr)) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "LR pointer is NULL");
+  if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr)) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
+  if (sort_every > 0 && n_hr > 0 && h->hs.max_sub == 0)
+    return fail(h, UPSAMPLE_ERR_GRID_TOO_LARGE, "grid too fine for the HR reorder (more than 2^24 Morton bins)");
+  int rc = check_device(h);
+  if (rc != UPSAMPLE_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const float* arrs[4] = {lr_x, lr_v, hr_x, hr_v};
+  const int64_t sizes[4] = {3 * n_lr * (int64_t)n_frames, 3 * n_lr * (int64_t)n_frames, 3 * n_hr, 3 * n_hr};
+  rc = validate_finite(h, st, arrs, sizes, 4);
+  if (rc != UPSAMPLE_OK) return rc;
+  rc = run_prepare(h, st);
+  if (rc != UPSAMPLE_OK) return rc;
+  if (h->hr_counts_dirty && sort_every > 0) {
+    const int64_t b0 = sort_bins(h->gi.dims, h->hs.max_sub, 0), b1 = sort_bins(h->gi.dims, h->hs.max_sub, 1);
+    hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)(b0 > b1 ? b0 : b1), st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->hs.ticket, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return hip_fail(h, e, "run");
+    h->hr_counts_dirty = false;
+  }
+  h->has_rigid = lr_rigid != nullptr;
+  const GridConst gc = grid_const(h);
+  GridScratch* buf[2] = {&h->g, &h->g2};
+  const size_t frame = 3 * (size_t)n_lr;
+  // the side stream starts after the caller's earlier work on the stream
+  hipError_t e = hipEventRecord(h->entry, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->entry, 0);
+  auto build = [&](int f) -> hipError_t {
+    const int b = f & 1;
+    hipError_t r = hipStreamWaitEvent(h->side, h->consumed[b], 0);  // gather f - 2 is done with buffer b
+    if (r == hipSuccess)
+      r = launch_build_grid(gc, lr_x + frame * (size_t)f, lr_v + frame * (size_t)f, lr_rigid, n_lr, h->n_cells,
+                            *buf[b], h->side);
+    if (r == hipSuccess) r = hipEventRecord(h->built[b], h->side);
+    return r;
+  };
+  if (e == hipSuccess) e = build(0);
+  for (int f = 0; f < n_frames && e == hipSuccess; ++f) {
+    const int b = f & 1;
+    if (f + 1 < n_frames) e = build(f + 1);  // overlaps with the gather of frame f
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, h->built[b], 0);
+    if (e != hipSuccess) break;
+    h->grid_valid = true;
+    h->grid_n_lr = n_lr;
+    const float* in_x = hr_x;
+    const float* in_v = hr_v;
+    if (sort_every > 0 && f % sort_every == 0 && n_hr > 0) {
+      // reorder into scratch; the step writes the state back into hr_x / hr_v
+      int32_t* p = perm_io != nullptr ? h->run_perm : nullptr;
+      e = launch_sort_hr(gc, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, h->tune.sort_sub, h->tune.sort_mode, h->hs, p,
+                         st);
+      if (e == hipSuccess && p != nullptr) e = launch_compose_perm(perm_io, p, n_hr, h->hs.slot, st);
+      if (e != hipSuccess) {
+        h->hr_counts_dirty = true;
+        break;
+      }
+      in_x = h->hs.x;
+      in_v = h->hs.v;
+    }
+    rc = advance_impl(h, in_x, in_v, hr_x, hr_v, n_hr, stream, false, nullptr, nullptr, 0, nullptr, nullptr,
+                      buf[b]);
+    if (rc != UPSAMPLE_OK) {
+      h->counts_dirty = h->g2_dirty = true;
+      (void)hipStreamSynchronize(h->side);
+      return rc;
+    }
+    e = hipEventRecord(h->consumed[b], st);
+  }
+  if (e != hipSuccess) {
+    h->counts_dirty = h->g2_dirty = true;
+    (void)hipStreamSynchronize(h->side);
+    return hip_fail(h, e, "run");
+  }
+  // the handle's grid is the last frame's
+  if (((n_frames - 1) & 1) == 1) {
+    const GridScratch t = h->g;
+    h->g = h->g2;
+    h->g2 = t;
+  }
+  return UPSAMPLE_OK;
 }
 
 int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,

@@ -225,6 +225,24 @@ class Upsampler:
                 _ptr(gx_out), _ptr(gv_out), _ptr(gx_in), _ptr(gv_in), _ptr(g_lr_x), _ptr(g_lr_v), _stream()))
         return gx_in, gv_in, g_lr_x, g_lr_v
 
+    def run(self, lr_x, lr_v, hr_x, hr_v, sort_every: int = 0, lr_rigid=None, perm=None):
+        """Advance hr_x / hr_v in place through frames lr_x, lr_v [T, 3, N_L]
+        (upsample_run); ``perm`` (int32 [N], optional) is updated through the
+        reorders made every ``sort_every`` steps."""
+        if not (lr_x.is_cuda and lr_x.dtype == torch.float32 and lr_x.dim() == 3 and lr_x.shape[1] == 3
+                and lr_x.is_contiguous() and lr_v.shape == lr_x.shape and lr_v.is_contiguous()
+                and lr_v.dtype == torch.float32):
+            raise ValueError("lr_x, lr_v must be contiguous float32 device tensors [T, 3, N_L]")
+        T, nl = lr_x.shape[0], lr_x.shape[2]
+        _u8(lr_rigid, nl, "lr_rigid")
+        n = _soa(hr_x, "hr_x").shape[1]
+        _soa(hr_v, "hr_v")
+        if perm is not None and not (perm.dtype == torch.int32 and perm.shape == (n,) and perm.is_contiguous()):
+            raise ValueError("perm must be a contiguous int32 tensor of length N")
+        self._check(self._L.upsample_run(self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl, T, _ptr(hr_x),
+                                         _ptr(hr_v), n, int(sort_every), _ptr(perm), _stream()))
+        return hr_x, hr_v
+
     def sort_hr(self, hr_x, hr_v, with_perm: bool = True, out_x=None, out_v=None):
         """Reorders the HR state by grid cell / Morton sub-cell: in place by
         default, or into out_x / out_v.  Returns the old index of each new

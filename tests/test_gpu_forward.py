@@ -324,3 +324,66 @@ def test_permute_gather_scatter(U):
     ok, _ = v.permute(small, dev(np.arange(10, dtype=np.int32)[::-1].copy(), torch))
     torch.cuda.synchronize()
     assert torch.equal(ok, small.flip(1))
+
+
+@pytest.mark.parametrize("sort_every", [0, 3])
+def test_run_matches_step_loop_and_oracle(U, sort_every):
+    # upsample_run builds each frame's grid on a second stream while the
+    # previous frame's step runs; it must compute the step-by-step loop
+    sc = configs.drain(scale=1 / 16)
+    T = 7
+    frames = [sc.lr_frame(t) for t in range(1, T + 1)]
+    LX = dev(np.stack([f[0] for f in frames]), torch)
+    LV = dev(np.stack([f[1] for f in frames]), torch)
+    hv0 = np.random.default_rng(13).normal(0, 0.5, sc.hr_x0.shape).astype(np.float32)
+    hx, hv = dev(sc.hr_x0, torch), dev(hv0, torch)
+    n = sc.n_hr
+    ref = U.from_scene(sc)
+    rx, rv = hx.clone(), hv.clone()
+    rperm = torch.arange(n, device="cuda", dtype=torch.int64)
+    for t in range(T):
+        if sort_every and t % sort_every == 0:
+            p = ref.sort_hr(rx, rv).long()
+            rperm = rperm[p]
+        rx, rv = ref.step(LX[t], LV[t], None, rx, rv, out_x=rx, out_v=rv)
+    up = U.from_scene(sc)
+    x, v = hx.clone(), hv.clone()
+    perm = torch.arange(n, device="cuda", dtype=torch.int32)
+    up.run(LX, LV, x, v, sort_every=sort_every, perm=perm)
+    torch.cuda.synchronize()
+    if sort_every == 0:
+        assert torch.equal(x, rx) and torch.equal(v, rv)
+        assert torch.equal(perm.long(), rperm)
+    # both in the original particle order
+    ox, ov = torch.empty_like(x), torch.empty_like(v)
+    ox[:, perm.long()] = x
+    ov[:, perm.long()] = v
+    qx, qv = torch.empty_like(x), torch.empty_like(v)
+    qx[:, rperm] = rx
+    qv[:, rperm] = rv
+    assert torch.equal(torch.sort(perm.long()).values, torch.arange(n, device="cuda"))
+    ddx = (ox - qx).abs().amax(dim=0)
+    ddv = ((ov - qv).abs() / torch.clamp(qv.abs(), min=1.0)).amax(dim=0)
+    off = ((ddx > 2e-7 * sc.box_length * T) | (ddv > 3e-6 * T)).sum().item()
+    dx, dv = torch.median(ddx).item(), torch.median(ddv).item()
+    # the reorders group particles into other waves, whose rounding differs;
+    # a particle sitting on an alpha threshold may then take the other branch
+    assert off <= max(5, 1e-4 * n), off
+    # HR particles are independent given the frames: the oracle follows a sample
+    idx = np.sort(np.random.default_rng(14).choice(n, 2048, replace=False))
+    xo, vo = sc.hr_x0[:, idx], hv0[:, idx]
+    for t in range(T):
+        o = O.step(frames[t][0], frames[t][1], None, xo, vo, sc.params())
+        xo, vo = o["x"], o["v"]
+    ex = np.abs(host(ox)[:, idx] - xo).max(axis=0)
+    ev = (np.abs(host(ov)[:, idx] - vo) / np.maximum(np.abs(vo), 1.0)).max(axis=0)
+    bad = (ex > 1e-6 * sc.box_length * T) | (ev > 1e-5 * T)
+    log(f"run sort_every={sort_every}: vs loop median |dx| {dx:.2e} |dv| {dv:.2e}, {off} beyond; vs oracle median |dx| "
+        f"{np.median(ex):.2e} |dv| {np.median(ev):.2e}, {int(bad.sum())} of {idx.size} beyond")
+    # an alpha or wall decision inside its band may flip once in T steps (the
+    # step-wise tests accept either branch); such particles then follow
+    # another, equally valid, trajectory
+    assert bad.sum() <= max(3, 0.005 * idx.size)
+    # the handle's grid is the last frame's
+    spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
+    _grid_check(up, frames[-1][0], spec)
