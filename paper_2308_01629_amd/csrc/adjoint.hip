@@ -35,13 +35,14 @@ __device__ __forceinline__ Back backprop(const StepConst& sc, const WallTable& w
                                          float z, float vx, float vy, float vz, float S, float Ux,
                                          float Uy, float Uz, float M, float gxo, float gyo, float gzo,
                                          float hxo, float hyo, float hzo) {
-  float tx = 0.f, ty = 0.f, tz = 0.f;
+  float tx = 0.f, ty = 0.f, tz = 0.f, rS = 0.f;
   bool A = true;
   if (S > 0.0f) {
-    tx = Ux / S;
-    ty = Uy / S;
-    tz = Uz / S;
-    A = (M <= sc.c1) || (M / S >= sc.c2);
+    rS = __builtin_amdgcn_rcpf(S);  // as in the forward step
+    tx = Ux * rS;
+    ty = Uy * rS;
+    tz = Uz * rS;
+    A = (M <= sc.c1) || (M * rS >= sc.c2);
   }
   const float alpha = A ? 1.0f - M : 0.0f;
   const float dt = sc.dt;
@@ -103,7 +104,7 @@ __device__ __forceinline__ Back backprop(const StepConst& sc, const WallTable& w
   b.gM = A ? -g_alpha : 0.0f;
   b.gUx = b.gUy = b.gUz = b.gS = 0.f;
   if (S > 0.0f) {
-    const float om = (1.0f - alpha) / S;
+    const float om = (1.0f - alpha) * rS;
     b.gUx = om * qx;
     b.gUy = om * qy;
     b.gUz = om * qz;
@@ -314,7 +315,7 @@ __device__ __forceinline__ Six pair_contrib(float4 Q, float4 W, float x, float y
 // flattened rows is one LR particle (sorted order).  Waves add their
 // wave-summed contributions to an LDS accumulator acc[component][slot] and the
 // block adds the non-zero slots to global memory once at the end.
-constexpr int kAccCap = 768;        // accumulator slots per block
+constexpr int kAccCap = 736;        // accumulator slots per block (LDS <= 32 KB: 5 blocks per CU)
 constexpr int kBlockRows = 256;     // at most one row per thread
 constexpr int kAdjListCap = 64;     // LDS candidate entries per wave and flush
 constexpr int kAdjRows = 64;        // stencil rows of one wave

@@ -131,10 +131,11 @@ __device__ __forceinline__ void finish(const AdvanceArgs& a, const float* __rest
   float tx = 0.f, ty = 0.f, tz = 0.f;
   bool A = true;
   if (S > 0.0f) {
-    tx = Ux / S;
-    ty = Uy / S;
-    tz = Uz / S;
-    A = (M <= a.sc.c1) || (M / S >= a.sc.c2);
+    const float r = __builtin_amdgcn_rcpf(S);  // 1 ulp; the adjoint's replay uses the same
+    tx = Ux * r;
+    ty = Uy * r;
+    tz = Uz * r;
+    A = (M <= a.sc.c1) || (M * r >= a.sc.c2);
   }
   const float alpha = A ? 1.0f - M : 0.0f;
   const float dt = a.sc.dt;

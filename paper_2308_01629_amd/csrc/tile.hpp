@@ -44,6 +44,18 @@ __device__ __forceinline__ int row_max(int v) {
   return v;
 }
 
+// Inclusive prefix maximum over the wave (DPP row shifts, then the row
+// broadcasts of lanes 15 and 31).
+__device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+  return v;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -85,6 +97,7 @@ struct TileLDS {
   float4 v[kWaves][G][kCap];  // (V_j, original index as bits)
   uint32_t rb[kWaves][kRows];      // first sorted index of each stencil row
   uint32_t rp[kWaves][kRows + 1];  // exclusive prefix of row lengths
+  uint32_t mark[kWaves][64];       // streaming: row starting at each position of a round
 };
 
 template <int G>
@@ -93,6 +106,7 @@ struct TileSetup {
   int nrows;       // > the LDS row capacity: the wave is too spread out for a shared list
   uint32_t total;  // candidates streamed (sum of row lengths)
   int X0, Y0, Z0, ny;  // first cell of the rows; rows run y-fastest
+  uint32_t my_start, my_len;  // row `lane` (rows <= 64): first streamed index and length
 };
 
 // Group boxes, stencil rows and their prefix sums (rows only when nrows fits the LDS).
@@ -141,6 +155,8 @@ __device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
   ts.Y0 = Y0;
   ts.Z0 = Z0;
   ts.ny = ny;
+  ts.my_start = 0u;
+  ts.my_len = 0u;
   if (ts.nrows > L::kRows) return ts;
   // rows r = lane + 64 q: one wave scan per 64 rows, in row order
   uint32_t carry = 0;
@@ -158,6 +174,10 @@ __device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
     const uint32_t incl = wave_incl_scan(rl, lane) + carry;
     lds.rb[wid][r] = rb;
     lds.rp[wid][r + 1] = incl;
+    if (q == 0) {
+      ts.my_start = incl - rl;
+      ts.my_len = rl;
+    }
     carry = __builtin_amdgcn_readlane(incl, 63);
   }
   ts.total = carry;
@@ -192,26 +212,34 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
                                            const LRPoint* __restrict__ lr, int lane, int wid,
                                            L& lds, Visit&& visit, Tag tag = Tag(), Stage stage = Stage()) {
   constexpr int kCap = L::kCap;
+  static_assert(L::kRows == 64, "the streaming gives each lane one stencil row");
   const int grp = lane / (64 / G);
   const float cull2 = gc.h2 * 1.001f;
   const float4 far_p = stage.pad();
+  uint32_t carried = 0u;  // the row holding the round's first candidate
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
   uint32_t cnt[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) cnt[g] = 0u;
   for (uint32_t k0 = 0; k0 < ts.total; k0 += 64u) {
     const uint32_t k = k0 + (uint32_t)lane;
+    // The row of candidate k is the last non-empty row starting at or before
+    // it: each such row marks its start inside this round (non-empty rows
+    // start at distinct positions), and a prefix maximum over the lanes
+    // spreads the marks.
+    lds.mark[wid][lane] = lane == 0 ? carried : 0u;
+    wave_lds_sync();
+    if (lane < ts.nrows && ts.my_len > 0u && ts.my_start >= k0 && ts.my_start - k0 < 64u)
+      lds.mark[wid][ts.my_start - k0] = (uint32_t)lane;
+    wave_lds_sync();
+    const int lo = (int)wave_prefix_max(lds.mark[wid][lane]);
+    carried = __builtin_amdgcn_readlane(lo, 63);
     bool keep[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) keep[g] = false;
     float4 P = zero4, V = zero4;
     uint32_t bits = 0;
     if (k < ts.total) {
-      int lo = 0, hi = ts.nrows;  // largest row r with rp[r] <= k
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (lds.rp[wid][mid] <= k) lo = mid; else hi = mid;
-      }
       const uint32_t j = lds.rb[wid][lo] + (k - lds.rp[wid][lo]);
       P = lr[j].p;
       V = lr[j].v;
