@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTab
 // Batched step: a persistent grid strides over the (scene, first particle)
 // tile table; each tile reads its scene's constants from the scene table.
 template <bool RIGID>
-__global__ __launch_bounds__(kBlock) void k_advance_batched(BatchAdvanceArgs b) {
+__global__ __launch_bounds__(kBlock, 5) void k_advance_batched(BatchAdvanceArgs b) {
   __shared__ GatherLDS<1> lds;
   for (int64_t t = blockIdx.x; t < b.n_tiles; t += gridDim.x) {
     const BatchTile tile = b.tiles[t];

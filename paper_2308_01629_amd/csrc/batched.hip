@@ -213,8 +213,10 @@ int upsample_batch_init(const upsample_scene* scenes, int32_t n_scenes, uint32_t
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || cus <= 0)
     cus = 256;
-  const bool any_lr = n_int > 0;
-  int64_t grid = (int64_t)cus * advance_batched_blocks_per_cu(any_lr);
+  // every block of the persistent grid resident, whichever variant (rigid or
+  // not) a step launches
+  const int per_cu = std::min(advance_batched_blocks_per_cu(true), advance_batched_blocks_per_cu(false));
+  int64_t grid = (int64_t)cus * per_cu;
   grid = std::max<int64_t>(kXcds, grid / kXcds * kXcds);
   b->grid_blocks = (int)std::min<int64_t>(grid, std::max<int64_t>(b->n_tiles, 1));
 
