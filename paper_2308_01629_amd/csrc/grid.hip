@@ -187,23 +187,63 @@ __global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ 
 }
 
 // HR reorder: scatter (x, v) by cell into scratch, remember the old index.
+// One block per block of k_hr_keys_count: it stages that block's particles in
+// LDS with coalesced reads, then walks its (key, slot, source) entries in their
+// block-local order, so that consecutive threads write consecutive
+// destinations of one bin.
+constexpr int kHrItems = 4;
+constexpr int kHrSpan = kHrItems * kBlock;  // particles per block of the HR reorder
+
+// Blocks are dispatched to the 8 XCDs round robin (block p on XCD p mod 8).
+// Renumber them so that XCD x runs a contiguous range of logical blocks: the
+// bin segments that neighbouring blocks share at their edges then meet in one
+// L2 instead of being written back in part from two.  A bijection on
+// [0, gridDim.x) for any grid size.
+constexpr uint32_t kXcdCount = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous_block() {
+  const uint32_t p = blockIdx.x, nb = gridDim.x;
+  const uint32_t x = p % kXcdCount, base = nb / kXcdCount, rem = nb % kXcdCount;
+  return x * base + min(x, rem) + p / kXcdCount;
+}
 __global__ __launch_bounds__(kBlock) void k_hr_scatter(const uint32_t* __restrict__ keys,
-                                                       const uint32_t* __restrict__ slot, int64_t n,
+                                                       const uint32_t* __restrict__ slot,
+                                                       const uint32_t* __restrict__ src, int64_t n,
                                                        const uint32_t* __restrict__ local,
                                                        const uint32_t* __restrict__ chunk_sum,
                                                        const float* __restrict__ x,
                                                        const float* __restrict__ v,
                                                        float* __restrict__ xs, float* __restrict__ vs,
                                                        int32_t* __restrict__ perm) {
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t dst = cell_offset(local, chunk_sum, keys[i]) + slot[i];
-  if (dst >= (uint64_t)n) return;  // defensive: counts started at zero
-  perm[dst] = (int32_t)i;
+  __shared__ float stage[6][kHrSpan];
+  const int64_t block0 = (int64_t)xcd_contiguous_block() * kHrSpan;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    xs[a * n + dst] = x[a * n + i];
-    vs[a * n + dst] = v[a * n + i];
+  for (int j = 0; j < kHrItems; ++j) {
+    const int l = j * kBlock + threadIdx.x;
+    const int64_t i = block0 + l;
+    if (i < n) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        stage[a][l] = x[a * n + i];
+        stage[3 + a][l] = v[a * n + i];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kHrItems; ++j) {
+    const int64_t q = block0 + j * kBlock + threadIdx.x;
+    if (q >= n) continue;
+    const uint32_t i = src[q];
+    const uint32_t l = (uint32_t)((int64_t)i - block0);
+    const uint32_t dst = cell_offset(local, chunk_sum, keys[q]) + slot[q];
+    // defensive: counts started at zero, sources stay inside the block
+    if (dst >= (uint64_t)n || i >= (uint64_t)n || l >= (uint32_t)kHrSpan) continue;
+    perm[dst] = (int32_t)i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      xs[a * n + dst] = stage[a][l];
+      vs[a * n + dst] = stage[3 + a][l];
+    }
   }
 }
 
@@ -257,30 +297,126 @@ __device__ __forceinline__ uint32_t morton_sub(uint32_t a, uint32_t b, uint32_t 
   return (a & 1u) | ((b & 1u) << 1) | ((c & 1u) << 2) | ((a & 2u) << 2) | ((b & 2u) << 3) | ((c & 2u) << 4);
 }
 
+// HR reorder keys and slots, with the bin claims aggregated over blocks of
+// kHrItems * kBlock consecutive particles.  Each wave first joins runs of equal
+// keys (as claim_slot does); the first lane of each run then enters the key in
+// an LDS hash table of the block's distinct keys and adds the run length to
+// that entry.  One global atomic add per distinct key then claims the block's
+// slots of that bin, so a bin receives one atomic per block instead of one per
+// wave run.  The block writes (key, slot, source index) in block-local order:
+// the particles of one key together, in slot order, so that consecutive
+// threads of the scatter write consecutive destinations.  Keys are below 2^24,
+// so all-ones marks an empty entry.  The table holds twice the block's particle
+// count: a linear probe meets its key or an empty entry within one sweep, and
+// the global-atomic path for a run that finds neither is never taken.
+constexpr int kHrTableBits = 11;
+constexpr int kHrTable = 1 << kHrTableBits;
+constexpr int kHrPerThread = kHrTable / kBlock;
+static_assert(kHrTable >= 2 * kHrSpan, "HR key table must stay at most half full");
+static_assert(kHrTable % kBlock == 0, "HR key table entries per thread");
+constexpr uint32_t kNoKey = 0xffffffffu;
+
 __global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const float* __restrict__ x,
                                                           int64_t n, int sub, int mode, int bx, int by, int bz,
                                                           uint32_t* __restrict__ keys,
                                                           uint32_t* __restrict__ slot,
+                                                          uint32_t* __restrict__ src,
                                                           uint32_t* __restrict__ counts) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = i < n;
-  const int64_t ii = valid ? i : 0;
-  const float px = x[ii], py = x[n + ii], pz = x[2 * n + ii];
-  const uint32_t fx = fine_coord(px, gc.lo[0], gc.inv_cs, gc.dims[0], sub);
-  const uint32_t fy = fine_coord(py, gc.lo[1], gc.inv_cs, gc.dims[1], sub);
-  const uint32_t fz = fine_coord(pz, gc.lo[2], gc.inv_cs, gc.dims[2], sub);
-  uint32_t k;
-  if (mode == 1) {
-    k = morton3(fx, fy, fz, bx, by, bz);
-  } else {
-    const uint32_t us = (uint32_t)sub;
-    const uint32_t cell = (fx / us) + (uint32_t)gc.dims[0] * ((fy / us) + (uint32_t)gc.dims[1] * (fz / us));
-    k = cell * us * us * us + morton_sub(fx % us, fy % us, fz % us);
+  __shared__ uint32_t tkey[kHrTable];  // key of the entry, then its first block-local position
+  __shared__ uint32_t tval[kHrTable];  // particle count of the entry, then its first slot
+  __shared__ uint32_t n_direct;        // particles whose run claimed its slots directly
+  for (int t = threadIdx.x; t < kHrTable; t += kBlock) {
+    tkey[t] = kNoKey;
+    tval[t] = 0u;
   }
-  const uint32_t sl = claim_slot(k, valid, counts);
-  if (valid) {
-    keys[i] = k;
-    slot[i] = sl;
+  if (threadIdx.x == 0) n_direct = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t block0 = (int64_t)xcd_contiguous_block() * kHrSpan;
+  uint32_t key[kHrItems], rank[kHrItems], drank[kHrItems];
+  int ent[kHrItems];
+#pragma unroll
+  for (int j = 0; j < kHrItems; ++j) {
+    const int64_t i = block0 + (int64_t)j * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    const int64_t ii = valid ? i : 0;
+    const uint32_t fx = fine_coord(x[ii], gc.lo[0], gc.inv_cs, gc.dims[0], sub);
+    const uint32_t fy = fine_coord(x[n + ii], gc.lo[1], gc.inv_cs, gc.dims[1], sub);
+    const uint32_t fz = fine_coord(x[2 * n + ii], gc.lo[2], gc.inv_cs, gc.dims[2], sub);
+    uint32_t k;
+    if (mode == 1) {
+      k = morton3(fx, fy, fz, bx, by, bz);
+    } else {
+      // sub is 1, 2 or 4: divide and take remainders by shifts
+      const uint32_t sh = (uint32_t)(__ffs(sub) - 1), m = (uint32_t)sub - 1u;
+      const uint32_t cell = (fx >> sh) + (uint32_t)gc.dims[0] * ((fy >> sh) + (uint32_t)gc.dims[1] * (fz >> sh));
+      k = (cell << (3u * sh)) + morton_sub(fx & m, fy & m, fz & m);
+    }
+    const uint32_t kk = valid ? k : kNoKey;
+    const uint32_t prev = __shfl_up(kk, 1, 64);
+    const bool head = (lane == 0) || (prev != kk);
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int start = 63 - __clzll(heads & upto);
+    const uint64_t above = heads & ~upto;
+    const int next = above ? (__ffsll((long long)above) - 1) : 64;
+    int e = -1;
+    uint32_t r = 0u, dr = 0u;
+    if (head && valid) {
+      const uint32_t len = (uint32_t)(next - lane);
+      uint32_t h = (kk * 2654435761u) >> (32 - kHrTableBits);
+      for (int probe = 0; probe < kHrTable; ++probe) {
+        const uint32_t old = atomicCAS(&tkey[h], kNoKey, kk);
+        if (old == kNoKey || old == kk) {
+          e = (int)h;
+          break;
+        }
+        h = (h + 1u) & (uint32_t)(kHrTable - 1);
+      }
+      if (e >= 0) {
+        r = atomicAdd(&tval[e], len);
+      } else {
+        r = atomicAdd(&counts[kk], len);
+        dr = atomicAdd(&n_direct, len);
+      }
+    }
+    const uint32_t off = (uint32_t)(lane - start);
+    ent[j] = __shfl(e, start, 64);
+    rank[j] = __shfl(r, start, 64) + off;
+    drank[j] = __shfl(dr, start, 64) + off;
+    key[j] = kk;
+  }
+  __syncthreads();
+  // claim each key's slots, and lay the entries out one after another: thread
+  // t owns entries t, t + kBlock, ... and places them consecutively
+  uint32_t cnt[kHrPerThread], sum = 0u;
+#pragma unroll
+  for (int q = 0; q < kHrPerThread; ++q) {
+    const int t = q * kBlock + threadIdx.x;
+    const uint32_t k = tkey[t];
+    cnt[q] = tval[t];
+    if (k != kNoKey) tval[t] = atomicAdd(&counts[k], cnt[q]);
+    sum += cnt[q];
+  }
+  uint32_t in_table = 0u;
+  uint32_t pos = block_exclusive_scan(sum, &in_table);
+#pragma unroll
+  for (int q = 0; q < kHrPerThread; ++q) {
+    tkey[q * kBlock + threadIdx.x] = pos;
+    pos += cnt[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kHrItems; ++j) {
+    const int64_t i = block0 + (int64_t)j * kBlock + threadIdx.x;
+    if (i < n) {
+      const bool tab = ent[j] >= 0;
+      const int e = tab ? ent[j] : 0;
+      const int64_t dst = block0 + (tab ? (int64_t)tkey[e] + rank[j] : (int64_t)in_table + drank[j]);
+      keys[dst] = key[j];
+      slot[dst] = tab ? tval[e] + rank[j] : rank[j];
+      src[dst] = (uint32_t)i;
+    }
   }
 }
 
@@ -393,13 +529,15 @@ hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* h
   int bits[3];
   for (int a = 0; a < 3; ++a) bits[a] = sort_bits((int64_t)gc.dims[a] * sub);
   const int64_t n_bins = sort_bins(gc.dims, sub, mode);
-  hipLaunchKernelGGL(k_hr_keys_count, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, gc, hr_x, n_hr,
-                     sub, mode, bits[0], bits[1], bits[2], s.keys, s.slot, s.counts);
+  hipLaunchKernelGGL(k_hr_keys_count, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)),
+                     dim3(kBlock), 0, st, gc, hr_x, n_hr,
+                     sub, mode, bits[0], bits[1], bits[2], s.keys, s.slot, s.src, s.counts);
   hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, s.ticket, st);
   if (e != hipSuccess) return e;
   const bool in_place = out_x == hr_x || out_v == hr_v;
   int32_t* perm = (perm_out != nullptr && !in_place) ? perm_out : s.perm;
-  hipLaunchKernelGGL(k_hr_scatter, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.keys, s.slot, n_hr,
+  hipLaunchKernelGGL(k_hr_scatter, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)), dim3(kBlock), 0, st,
+                     s.keys, s.slot, s.src, n_hr,
                      s.local, s.chunk_sum, hr_x, hr_v, in_place ? s.x : out_x, in_place ? s.v : out_v,
                      perm);
   if (in_place) {

@@ -32,6 +32,7 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
 struct HRSortScratch {
   uint32_t* keys;       // [max_hr]
   uint32_t* slot;       // [max_hr]
+  uint32_t* src;        // [max_hr] source index of each (key, slot) entry
   float* x;             // [3][max_hr]
   float* v;             // [3][max_hr]
   int32_t* perm;        // [max_hr]

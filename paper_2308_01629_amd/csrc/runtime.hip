@@ -144,7 +144,7 @@ hipError_t dmalloc(T** p, int64_t count) {
 
 void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
-                  h->g.ticket, h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.x,
+                  h->g.ticket, h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.src, h->hs.x,
                   h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum, h->hs.ticket,
                   h->finite_flag, h->g2.keys, h->g2.slot, h->g2.tmp, h->g2.perm, h->g2.counts,
                   h->g2.local, h->g2.chunk_sum, h->g2.ticket, h->g2.cell_start, h->g2.lr_sorted,
@@ -316,6 +316,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->g.lr_sorted, nl)
   ALLOC(h->hs.keys, nh)
   ALLOC(h->hs.slot, nh)
+  ALLOC(h->hs.src, nh)
   ALLOC(h->hs.x, 3 * nh)
   ALLOC(h->hs.v, 3 * nh)
   ALLOC(h->hs.perm, nh)

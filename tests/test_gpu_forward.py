@@ -296,6 +296,32 @@ def test_sort_hr_out_of_place_and_sub_cells(U, sub, mode):
     assert mean_box(host(ox)) < 0.05 * mean_box(host(hx))
 
 
+@pytest.mark.parametrize("n", [1, 63, 1025, 70007])
+def test_sort_hr_ragged_and_nearly_sorted(U, n):
+    """Reorder at sizes that end inside a block of the counting kernel, on a
+    shuffled state, then on its own sorted output moved by a small jitter (the
+    nearly sorted input of a rollout), and with every particle in one cell."""
+    sc = configs.drain(scale=1 / 32)
+    up = U.from_scene(sc)
+    spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
+    rng = np.random.default_rng(n)
+    pick = rng.choice(sc.n_hr, n, replace=False)
+    x0 = sc.hr_x0[:, pick].copy()
+    jitter = rng.normal(0, 0.3 * sc.r_hr, x0.shape).astype(np.float32)
+    one_cell = np.broadcast_to(x0[:, :1], x0.shape) + rng.uniform(0, 1e-4, x0.shape).astype(np.float32)
+    for case, x in (("shuffled", x0), ("jittered", None), ("one cell", one_cell)):
+        if x is None:
+            x = host(ox) + jitter
+        hx = dev(np.ascontiguousarray(x, dtype=np.float32), torch)
+        hv = dev(rng.normal(size=x0.shape).astype(np.float32), torch)
+        ox, ov = torch.empty_like(hx), torch.empty_like(hv)
+        perm = up.sort_hr(hx, hv, out_x=ox, out_v=ov).long()
+        torch.cuda.synchronize()
+        assert torch.equal(torch.sort(perm).values, torch.arange(n, device="cuda")), case
+        assert torch.equal(ox, hx[:, perm]) and torch.equal(ov, hv[:, perm]), case
+        assert np.all(np.diff(morton_sort_keys(host(ox), spec, 2, 0)) >= 0), case
+
+
 def test_permute_gather_scatter(U):
     from paper_2308_01629_amd import UpsampleError
     sc = configs.plain()
