@@ -322,7 +322,7 @@ constexpr int kAdjRows = 64;        // stencil rows of one wave
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* wsum) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t inc = wave_incl_scan(v, lane);
+  const uint32_t inc = wave_incl_scan(v);
   if (lane == 63) wsum[wid] = inc;
   __syncthreads();
   uint32_t off = 0, tot = 0;

@@ -44,6 +44,24 @@ __device__ __forceinline__ int row_max(int v) {
   return v;
 }
 
+// Min / max over each group of 64 / G lanes (G = 1, 2, 4): the row reduction,
+// then the row broadcasts of lanes 15 and 31; the group's last lane holds it.
+template <int G>
+__device__ __forceinline__ int group_min(int v) {
+  v = row_min(v);
+  if (G <= 2) v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x142, 0xa, 0xf, false));
+  if (G == 1) v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x143, 0xc, 0xf, false));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int group_max(int v) {
+  const int lo = (int)0x80000000;
+  v = row_max(v);
+  if (G <= 2) v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x142, 0xa, 0xf, false));
+  if (G == 1) v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x143, 0xc, 0xf, false));
+  return v;
+}
+
 // Inclusive prefix maximum over the wave (DPP row shifts, then the row
 // broadcasts of lanes 15 and 31).
 __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v) {
@@ -56,12 +74,15 @@ __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
+// Inclusive prefix sum over the wave, in the same DPP pattern (lanes whose
+// source lies outside the row, and rows outside the mask, add 0).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
   return v;
 }
 
@@ -114,26 +135,21 @@ template <int G, class L>
 __device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
                                                    const uint32_t* __restrict__ cell_start, float x,
                                                    float y, float z, int lane, int wid, L& lds) {
-  constexpr int kRowsPerGroup = 4 / G;
+  static_assert(G == 1 || G == 2 || G == 4, "groups are 64, 32 or 16 lanes");
   TileSetup<G> ts;
-  const int e0 = row_min(ord(x)), e1 = row_min(ord(y)), e2 = row_min(ord(z));
-  const int f0 = row_max(ord(x)), f1 = row_max(ord(y)), f2 = row_max(ord(z));
+  const int e0 = group_min<G>(ord(x)), e1 = group_min<G>(ord(y)), e2 = group_min<G>(ord(z));
+  const int f0 = group_max<G>(ord(x)), f1 = group_max<G>(ord(y)), f2 = group_max<G>(ord(z));
   int w0x = 0x7fffffff, w0y = 0x7fffffff, w0z = 0x7fffffff;
   int w1x = (int)0x80000000, w1y = (int)0x80000000, w1z = (int)0x80000000;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    int a0 = 0x7fffffff, a1 = 0x7fffffff, a2 = 0x7fffffff;
-    int b0 = (int)0x80000000, b1 = (int)0x80000000, b2 = (int)0x80000000;
-#pragma unroll
-    for (int r = 0; r < kRowsPerGroup; ++r) {
-      const int l = 16 * (g * kRowsPerGroup + r) + 15;
-      a0 = min(a0, __builtin_amdgcn_readlane(e0, l));
-      a1 = min(a1, __builtin_amdgcn_readlane(e1, l));
-      a2 = min(a2, __builtin_amdgcn_readlane(e2, l));
-      b0 = max(b0, __builtin_amdgcn_readlane(f0, l));
-      b1 = max(b1, __builtin_amdgcn_readlane(f1, l));
-      b2 = max(b2, __builtin_amdgcn_readlane(f2, l));
-    }
+    const int l = (64 / G) * (g + 1) - 1;
+    const int a0 = __builtin_amdgcn_readlane(e0, l);
+    const int a1 = __builtin_amdgcn_readlane(e1, l);
+    const int a2 = __builtin_amdgcn_readlane(e2, l);
+    const int b0 = __builtin_amdgcn_readlane(f0, l);
+    const int b1 = __builtin_amdgcn_readlane(f1, l);
+    const int b2 = __builtin_amdgcn_readlane(f2, l);
     ts.gb[g].lo[0] = unord(a0); ts.gb[g].lo[1] = unord(a1); ts.gb[g].lo[2] = unord(a2);
     ts.gb[g].hi[0] = unord(b0); ts.gb[g].hi[1] = unord(b1); ts.gb[g].hi[2] = unord(b2);
     w0x = min(w0x, a0); w0y = min(w0y, a1); w0z = min(w0z, a2);
@@ -158,7 +174,10 @@ __device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
   ts.my_start = 0u;
   ts.my_len = 0u;
   if (ts.nrows > L::kRows) return ts;
-  // rows r = lane + 64 q: one wave scan per 64 rows, in row order
+  // rows r = lane + 64 q: one wave scan per 64 rows, in row order.  r / ny by
+  // a float reciprocal: with r < 256 and ny <= 256, (r + 1/2) / ny lies at
+  // least 1/512 from an integer, far beyond the reciprocal's error.
+  const float rny = __builtin_amdgcn_rcpf((float)ny);
   uint32_t carry = 0;
 #pragma unroll
   for (int q = 0; q < L::kRows / 64; ++q) {
@@ -166,12 +185,13 @@ __device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
     const int r = lane + 64 * q;
     uint32_t rb = 0, rl = 0;
     if (r < ts.nrows) {
-      const int yy = Y0 + r % ny, zz = Z0 + r / ny;
+      const int rz = (int)fmaf((float)r, rny, 0.5f * rny);
+      const int yy = Y0 + __mul24(-rz, ny) + r, zz = Z0 + rz;
       const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
       rb = cell_start[row + (uint32_t)X0];
       rl = cell_start[row + (uint32_t)X1 + 1u] - rb;
     }
-    const uint32_t incl = wave_incl_scan(rl, lane) + carry;
+    const uint32_t incl = wave_incl_scan(rl) + carry;
     lds.rb[wid][r] = rb;
     lds.rp[wid][r + 1] = incl;
     if (q == 0) {
