@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--sort-sub", type=int, default=0, help="HR reorder sub-cells per axis (0: library default)")
+    ap.add_argument("--sort-mode", type=int, default=-1,
+                    help="HR reorder key: 0 cell then Morton, 1 Morton, 2 Hilbert (-1: library default)")
     ap.add_argument("--groups", type=int, default=0, help="gather lane groups per wave (0: library default)")
     ap.add_argument("--cell-factor", type=float, default=0.0, help="fixed kappa (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the autotuner")
@@ -115,6 +117,8 @@ def drain_leg(args, torch, Upsampler):
         log(f"drain: autotune {tune}")
     if args.sort_sub:
         up.set_tuning(sort_sub=args.sort_sub)
+    if args.sort_mode >= 0:
+        up.set_tuning(sort_mode=args.sort_mode)
     if args.groups:
         up.set_tuning(gather_groups=args.groups)
     gi = up.grid_info()

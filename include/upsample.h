@@ -227,9 +227,10 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
                  int32_t sort_every, int32_t* perm_io, void* stream);
 
 /*
- * Reorder HR particles by grid cell and, inside a cell, by the Morton order of
- * sort_sub^3 sub-cells (upsample_tuning), so that consecutive particles -- the
- * lanes of one wave of the step kernel -- occupy a compact box.  Reads hr_x,
+ * Reorder HR particles by the key that upsample_tuning's sort_mode selects
+ * over cells split into sort_sub^3 sub-cells (by default the Hilbert index of
+ * the sub-cells), so that consecutive particles -- the lanes of one wave of
+ * the step kernel -- occupy a compact box.  Reads hr_x,
  * hr_v [3][n_hr]; writes the reordered arrays to hr_x_out, hr_v_out (both
  * alias their inputs for an in-place reorder through scratch, or neither).
  * perm_out (device int32 [n_hr], may be NULL) receives, for each new position,
@@ -283,7 +284,10 @@ int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* 
  * against the group's bounding box.  Default 1.  sort_sub: sub-cells per axis
  * of the HR reorder key (1, 2 or 4, at most what the grid's bins allow).
  * sort_mode: 0 orders HR by grid cell then by the Morton order of its
- * sub-cells, 1 by the global Morton (Z-order) code of the sub-cells.
+ * sub-cells, 1 by the global Morton (Z-order) code of the sub-cells, 2 by the
+ * global Hilbert index of the sub-cells (bins for it are allocated at the
+ * default sort_sub when they fit in 2^24).  A sort_sub / sort_mode pair whose
+ * bins exceed the handle's allocation is rejected with INVALID_ARG.
  * adjoint_tiled: 1 (default) runs the adjoint as wave tiles with block-summed
  * LR gradients, 0 one particle per lane with per-pair atomics (scenes with
  * rigid LR particles always use the latter).  tile_max / adjoint_tile_max: a
@@ -312,7 +316,8 @@ int upsample_timing_read(upsample_handle h, double* advance_ms, int64_t* launche
 /*
  * Autotuner.  Times the step kernel (upsample_advance) for candidate cell
  * factors kappa in {0.51, 0.6, 0.75, 1.0001, 1.25} (cs = kappa * 3 r_lr;
- * below 1 the stencil reaches two cells) and for the launch knobs sort_sub,
+ * below 1 the stencil reaches two cells) and for the launch knobs (sort_sub,
+ * sort_mode) in {(1, Hilbert), (2, Hilbert), (2, cell then Morton)},
  * gather_groups and tile_max, by replaying a short stretch of the caller's
  * run: lr_x, lr_v hold n_frames consecutive LR frames ([n_frames][3][n_lr],
  * device); a copy of the HR state is reordered at the first frame, as a run

@@ -15,7 +15,8 @@
 namespace {
 
 constexpr float kKappas[] = {0.51f, 0.6f, 0.75f, UPSAMPLE_DEFAULT_CELL_FACTOR, 1.25f};
-constexpr int kSubs[] = {1, 2};
+// HR reorder keys tried: (sub-cells per axis, key mode)
+constexpr int kSorts[][2] = {{1, 2}, {2, 2}, {2, 0}};
 constexpr int kGroups[] = {1, 2};
 constexpr int kTileMax[] = {384, 512, 768};
 constexpr int kReps = 2;
@@ -171,11 +172,12 @@ extern "C" int upsample_autotune(const upsample_params* p, const float* lr_x, co
     upsample_tuning t;
     upsample_get_tuning(h, &t);
     const upsample_tuning t0 = t;
-    for (int sub : kSubs) {
+    for (const auto& sort : kSorts) {
       if (rc != UPSAMPLE_OK) break;
       t = t0;
-      t.sort_sub = sub;
-      if (upsample_set_tuning(h, &t) != UPSAMPLE_OK) continue;  // more sub-cells than the bins allow
+      t.sort_sub = sort[0];
+      t.sort_mode = sort[1];
+      if (upsample_set_tuning(h, &t) != UPSAMPLE_OK) continue;  // more bins than this grid allows
       // (groups, tile_max) combos; times summed over the frames
       constexpr int kCombos = sizeof(kGroups) / sizeof(int) * (sizeof(kTileMax) / sizeof(int));
       float total[kCombos];

@@ -293,6 +293,45 @@ __device__ __forceinline__ uint32_t morton3(uint32_t fx, uint32_t fy, uint32_t f
   return key;
 }
 
+// Index of fine cell (x0, x1, x2) along a 3-D Hilbert curve over a cube of
+// 2^b cells per axis, by Skilling's transpose method ("Programming the Hilbert
+// curve", AIP Conf. Proc. 707, 2004): undo the excess work of each level from
+// the top bit down, Gray-encode, then interleave the bits with axis 0 most
+// significant.  Consecutive indices are face-neighbouring cells, so runs of
+// particles in this order fill compact boxes (no Z-order jumps).
+__device__ __forceinline__ uint32_t hilbert3(uint32_t x0, uint32_t x1, uint32_t x2, int b) {
+  for (int k = b - 1; k > 0; --k) {
+    const uint32_t q = 1u << k, p = q - 1u;
+    x0 = (x0 & q) ? (x0 ^ p) : x0;
+    {
+      const uint32_t t = (x0 ^ x1) & p;
+      const bool hit = (x1 & q) != 0u;
+      x0 = hit ? (x0 ^ p) : (x0 ^ t);
+      x1 = hit ? x1 : (x1 ^ t);
+    }
+    {
+      const uint32_t t = (x0 ^ x2) & p;
+      const bool hit = (x2 & q) != 0u;
+      x0 = hit ? (x0 ^ p) : (x0 ^ t);
+      x2 = hit ? x2 : (x2 ^ t);
+    }
+  }
+  x1 ^= x0;
+  x2 ^= x1;
+  uint32_t t = 0u;
+  for (int k = b - 1; k > 0; --k) {
+    const uint32_t q = 1u << k;
+    if (x2 & q) t ^= q - 1u;
+  }
+  x0 ^= t;
+  x1 ^= t;
+  x2 ^= t;
+  uint32_t key = 0u;
+  for (int k = b - 1; k >= 0; --k)
+    key = (key << 3) | (((x0 >> k) & 1u) << 2) | (((x1 >> k) & 1u) << 1) | ((x2 >> k) & 1u);
+  return key;
+}
+
 __device__ __forceinline__ uint32_t morton_sub(uint32_t a, uint32_t b, uint32_t c) {
   return (a & 1u) | ((b & 1u) << 1) | ((c & 1u) << 2) | ((a & 2u) << 2) | ((b & 2u) << 3) | ((c & 2u) << 4);
 }
@@ -344,7 +383,9 @@ __global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const fl
     const uint32_t fy = fine_coord(x[n + ii], gc.lo[1], gc.inv_cs, gc.dims[1], sub);
     const uint32_t fz = fine_coord(x[2 * n + ii], gc.lo[2], gc.inv_cs, gc.dims[2], sub);
     uint32_t k;
-    if (mode == 1) {
+    if (mode == 2) {
+      k = hilbert3(fx, fy, fz, max(bx, max(by, bz)));
+    } else if (mode == 1) {
       k = morton3(fx, fy, fz, bx, by, bz);
     } else {
       // sub is 1, 2 or 4: divide and take remainders by shifts

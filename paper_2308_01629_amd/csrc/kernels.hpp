@@ -41,6 +41,7 @@ struct HRSortScratch {
   uint32_t* chunk_sum;  // [n_bins / kScanChunk + 2]
   uint32_t* ticket;     // [1]
   int64_t n_cells;      // grid cells
+  int64_t n_bins;       // bins allocated in counts / local
   int max_sub;          // largest sub-cell count per axis the bins are sized for (4, 2 or 1)
 };
 
@@ -52,11 +53,17 @@ inline int sort_bits(int64_t n) {
 }
 // Bins of the HR reorder for a sub-cell count: mode 1 (global Morton code of
 // fine cells) 2^(bx + by + bz); mode 0 (grid cell, then Morton order of its
-// sub-cells) n_cells * sub^3.
+// sub-cells) n_cells * sub^3; mode 2 (global Hilbert index of fine cells, on
+// a cube of 2^max(bx, by, bz) cells per axis) 2^(3 max(bx, by, bz)).
 inline int64_t sort_bins(const int dims[3], int sub, int mode) {
   if (mode == 0) return (int64_t)dims[0] * dims[1] * dims[2] * sub * sub * sub;
-  int b = 0;
-  for (int a = 0; a < 3; ++a) b += sort_bits((int64_t)dims[a] * sub);
+  int b = 0, m = 0;
+  for (int a = 0; a < 3; ++a) {
+    const int ba = sort_bits((int64_t)dims[a] * sub);
+    b += ba;
+    m = ba > m ? ba : m;
+  }
+  if (mode == 2) return (int64_t)1 << (3 * m);
   return (int64_t)1 << b;
 }
 // out_x / out_v may alias hr_x / hr_v (then the permuted copy goes through scratch).

@@ -331,9 +331,18 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   while (h->hs.max_sub > 1 && bins_for(h->hs.max_sub) > ((int64_t)1 << 24)) h->hs.max_sub /= 2;
   const bool can_sort = bins_for(h->hs.max_sub) <= ((int64_t)1 << 24);
   if (!can_sort) h->hs.max_sub = 0;  // grid too fine for the reorder: sort_hr reports GRID_TOO_LARGE
-  const int64_t n_bins = (nh > 0 && can_sort) ? bins_for(h->hs.max_sub) : 1;
+  int64_t n_bins = (nh > 0 && can_sort) ? bins_for(h->hs.max_sub) : 1;
   h->tune.sort_sub = h->hs.max_sub >= 2 ? 2 : 1;
   h->tune.sort_mode = 0;
+  // Hilbert keys (mode 2) at the default sub-cell count are the default when
+  // their bins fit: runs of particles in Hilbert order fill more compact wave
+  // boxes than either Morton key
+  const int64_t b2 = sort_bins(h->gi.dims, h->tune.sort_sub, 2);
+  if (nh > 0 && can_sort && b2 <= ((int64_t)1 << 24)) {
+    if (b2 > n_bins) n_bins = b2;
+    h->tune.sort_mode = 2;
+  }
+  h->hs.n_bins = n_bins;
   ALLOC(h->hs.counts, n_bins)
   ALLOC(h->hs.local, n_bins)
   ALLOC(h->hs.chunk_sum, n_bins / kScanChunk + 2)
@@ -640,8 +649,7 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
   rc = run_prepare(h, st);
   if (rc != UPSAMPLE_OK) return rc;
   if (h->hr_counts_dirty && sort_every > 0) {
-    const int64_t b0 = sort_bins(h->gi.dims, h->hs.max_sub, 0), b1 = sort_bins(h->gi.dims, h->hs.max_sub, 1);
-    hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)(b0 > b1 ? b0 : b1), st);
+    hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)h->hs.n_bins, st);
     if (e == hipSuccess) e = hipMemsetAsync(h->hs.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "run");
     h->hr_counts_dirty = false;
@@ -723,8 +731,7 @@ int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, fl
   if (h->hs.max_sub == 0)
     return fail(h, UPSAMPLE_ERR_GRID_TOO_LARGE, "grid too fine for the HR reorder (more than 2^24 Morton bins)");
   if (h->hr_counts_dirty) {
-    const int64_t b0 = sort_bins(h->gi.dims, h->hs.max_sub, 0), b1 = sort_bins(h->gi.dims, h->hs.max_sub, 1);
-    hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)(b0 > b1 ? b0 : b1), st);
+    hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)h->hs.n_bins, st);
     if (e == hipSuccess) e = hipMemsetAsync(h->hs.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "sort_hr");
     h->hr_counts_dirty = false;
@@ -801,14 +808,15 @@ int upsample_set_tuning(upsample_handle h, const upsample_tuning* t) {
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "gather_groups must be 1, 2 or 4");
   if (t->sort_sub != 1 && t->sort_sub != 2 && t->sort_sub != 4)
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_sub must be 1, 2 or 4");
-  if (t->sort_mode != 0 && t->sort_mode != 1)
-    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_mode must be 0 or 1");
+  if (t->sort_mode != 0 && t->sort_mode != 1 && t->sort_mode != 2)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_mode must be 0, 1 or 2");
   if (t->tile_max < 0 || t->adjoint_tile_max < 0)
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "tile_max must be >= 0");
   if (t->adjoint_tiled != 0 && t->adjoint_tiled != 1)
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "adjoint_tiled must be 0 or 1");
-  if (t->sort_sub > h->hs.max_sub)
-    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_sub exceeds the bins allocated for this grid");
+  if (t->sort_sub > h->hs.max_sub ||
+      (h->p.max_hr > 0 && h->hs.max_sub > 0 && sort_bins(h->gi.dims, t->sort_sub, t->sort_mode) > h->hs.n_bins))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_sub / sort_mode exceed the bins allocated for this grid");
   h->tune = *t;
   return UPSAMPLE_OK;
 }

@@ -72,10 +72,42 @@ def compare_step(gx, gv, lr_x, lr_v, rigid, hr_x, hr_v, prm, L, n_steps=1, idx=N
             "band": band_hits, "alpha_band": int(o["band"].sum())}
 
 
+def hilbert_index(f, bits):
+    """Index along a 3-D Hilbert curve of integer cells f [3, N] in a cube of
+    2^bits cells per axis (Skilling 2004, transpose form), axis 0 the most
+    significant bit of each triple.  Pinned by tests/test_abi.py: a bijection
+    onto [0, 8^bits) whose consecutive indices are face neighbours."""
+    X = [np.asarray(f[a], dtype=np.int64).copy() for a in range(3)]
+    q = 1 << (bits - 1)
+    while q > 1:
+        p = q - 1
+        for i in range(3):
+            hit = (X[i] & q) != 0
+            t = (X[0] ^ X[i]) & p
+            x0 = np.where(hit, X[0] ^ p, X[0] ^ t)
+            if i:
+                X[i] = np.where(hit, X[i], X[i] ^ t)
+            X[0] = x0
+        q >>= 1
+    X[1] ^= X[0]
+    X[2] ^= X[1]
+    t = np.zeros_like(X[0])
+    q = 1 << (bits - 1)
+    while q > 1:
+        t = np.where((X[2] & q) != 0, t ^ (q - 1), t)
+        q >>= 1
+    key = np.zeros_like(X[0])
+    for b in range(bits - 1, -1, -1):
+        for i in range(3):
+            key = (key << 1) | (((X[i] ^ t) >> b) & 1)
+    return key
+
+
 def morton_sort_keys(x, spec, sub, mode=1):
     """The HR reorder key of positions x [3, N] for a grid spec (float32
     arithmetic): mode 1 the Z-order code of fine cells, mode 0 the grid cell
-    then the Z-order of its sub-cells.  Used to check the reorder's output."""
+    then the Z-order of its sub-cells, mode 2 the Hilbert index of fine cells.
+    Used to check the reorder's output."""
     x = np.asarray(x, dtype=np.float32)
     bits, fine = [], []
     for a in range(3):
@@ -84,6 +116,8 @@ def morton_sort_keys(x, spec, sub, mode=1):
         f = np.clip(np.floor((t - c) * np.float32(sub)), 0, sub - 1)
         fine.append(c.astype(np.int64) * sub + f.astype(np.int64))
         bits.append(int(np.ceil(np.log2(spec.dims[a] * sub))) if spec.dims[a] * sub > 1 else 0)
+    if mode == 2:
+        return hilbert_index(fine, max(bits))
     if mode == 0:
         c = [f // sub for f in fine]
         sb = [f % sub for f in fine]

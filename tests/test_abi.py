@@ -165,3 +165,19 @@ def test_host_grid_matches_oracle_definition(name, cell_factor):
     assert gi["cell_size"] == spec.cs
     assert np.float32(gi["inv_cell_size"]) == spec.inv_cs
     assert np.float32(gi["h2"]) == spec.h2_f
+
+
+@pytest.mark.parametrize("bits", [1, 2, 3, 4])
+def test_hilbert_reference_is_a_face_neighbour_walk(bits):
+    """The reorder test's Hilbert key: a bijection of the 2^bits cube onto
+    [0, 8^bits) that steps to a face neighbour at every increment, starting at
+    the origin."""
+    from gpu_util import hilbert_index
+    n = 1 << bits
+    g = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")).reshape(3, -1)
+    k = hilbert_index(g, bits)
+    assert np.array_equal(np.sort(k), np.arange(n ** 3))
+    walk = g[:, np.argsort(k)]
+    assert np.all(np.abs(np.diff(walk, axis=1)).sum(axis=0) == 1)
+    assert np.all(walk[:, 0] == 0)
+
