@@ -81,7 +81,7 @@ void release(upsample_batch b) {
   }
   b->n_graphs = 0;
   void* ptrs[] = {b->d_scenes, b->d_lr_blocks, b->d_tiles, b->d_walls, b->d_scene_of, b->g.keys, b->g.slot,
-                  b->g.tmp, b->g.perm, b->g.counts, b->g.local, b->g.chunk_sum, b->g.ticket,
+                  b->g.tmp, b->g.perm, b->g.counts, b->g.local, b->g.chunk_sum,
                   b->g.cell_start, b->g.lr_sorted};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
@@ -271,7 +271,6 @@ int upsample_batch_init(const upsample_scene* scenes, int32_t n_scenes, uint32_t
   chk(dalloc(&b->g.counts, n_cells));
   chk(dalloc(&b->g.local, n_cells));
   chk(dalloc(&b->g.chunk_sum, n_chunks + 2));
-  chk(dalloc(&b->g.ticket, 1));
   chk(dalloc(&b->g.cell_start, n_cells + 1));
   chk(dalloc(&b->g.lr_sorted, n_int));
   if (e != hipSuccess) {
@@ -287,7 +286,6 @@ int upsample_batch_init(const upsample_scene* scenes, int32_t n_scenes, uint32_t
   if (!walls.empty())
     chk(hipMemcpy(b->d_walls, walls.data(), sizeof(float) * walls.size(), hipMemcpyHostToDevice));
   chk(hipMemset(b->g.counts, 0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n_cells, 1)));
-  chk(hipMemset(b->g.ticket, 0, sizeof(uint32_t)));
   chk(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
   chk(hipDeviceSynchronize());
   if (e != hipSuccess) {
@@ -313,7 +311,6 @@ int upsample_batch_step(upsample_batch b, const float* lr_x, const float* lr_v, 
   hipError_t e = hipSuccess;
   if (b->counts_dirty) {
     e = hipMemsetAsync(b->g.counts, 0, sizeof(uint32_t) * (size_t)std::max<int64_t>(b->n_cells, 1), st);
-    if (e == hipSuccess) e = hipMemsetAsync(b->g.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return bhip(b, e, "batch_step");
     b->counts_dirty = false;
   }

@@ -1,11 +1,11 @@
 // Uniform-grid rebuild of the LR guide particles: the neighbour search the
-// paper runs with a compact-hashing library (Section 5.1), as four streaming
+// paper runs with a compact-hashing library (Section 5.1), as five streaming
 // kernels over structure-of-arrays input:
 //
 //   k_keys_count  cell key per LR particle, per-cell counts by atomic add
 //                 (the returned old count is the particle's arrival slot)
-//   k_scan_cells  exclusive scan of the counts in 2048-cell chunks; the last
-//                 block to finish scans the chunk totals; counts are re-zeroed
+//   k_scan_chunks exclusive scan of the counts in 2048-cell chunks (counts are
+//   k_scan_totals re-zeroed), then one block scans the chunk totals
 //   k_scatter     cell_start[] and an arrival-order placement per cell
 //   k_stable      rank inside the cell by original index (stable order), then
 //                 writes perm[] and the LR copy in sorted order (32 B / particle)
@@ -87,55 +87,73 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return off + inc - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_cells(uint32_t* __restrict__ counts, int64_t n_cells,
-                                                       uint32_t* __restrict__ local,
-                                                       uint32_t* chunk_sum, uint32_t* ticket,
-                                                       int n_chunks) {
-  __shared__ int is_last;
+// Scan of the counts, first step: each block scans one 2048-bin chunk (eight
+// consecutive bins per thread, two 16-byte loads where the chunk is whole),
+// writes the chunk-local exclusive offsets, zeroes the counts for the next
+// build and publishes the chunk total.  The chunk totals are scanned by the
+// next launch; the kernel boundary orders the two, so no block waits on
+// another and no device-scope fence is needed.
+__global__ __launch_bounds__(kBlock) void k_scan_chunks(uint32_t* __restrict__ counts, int64_t n_cells,
+                                                        uint32_t* __restrict__ local,
+                                                        uint32_t* __restrict__ chunk_sum) {
+  static_assert(kScanItems == 8, "two 16-byte loads per thread");
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  const bool whole = base + kScanItems <= n_cells;
+  if (whole) {
+    uint4* c4 = reinterpret_cast<uint4*>(counts + base);
+    const uint4 lo = c4[0], hi = c4[1];
+    v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w;
+    v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
+    c4[0] = make_uint4(0u, 0u, 0u, 0u);  // ready for the next build
+    c4[1] = make_uint4(0u, 0u, 0u, 0u);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t c = base + k;
+      v[k] = 0u;
+      if (c < n_cells) {
+        v[k] = counts[c];
+        counts[c] = 0u;
+      }
+    }
+  }
   uint32_t ex[kScanItems];
   uint32_t sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    int64_t c = base + k;
-    uint32_t v = 0;
-    if (c < n_cells) {
-      v = counts[c];
-      counts[c] = 0u;  // ready for the next build
-    }
     ex[k] = sum;
-    sum += v;
+    sum += v[k];
   }
   uint32_t total;
-  uint32_t off = block_exclusive_scan(sum, &total);
+  const uint32_t off = block_exclusive_scan(sum, &total);
+  if (whole) {
+    uint4* l4 = reinterpret_cast<uint4*>(local + base);
+    l4[0] = make_uint4(ex[0] + off, ex[1] + off, ex[2] + off, ex[3] + off);
+    l4[1] = make_uint4(ex[4] + off, ex[5] + off, ex[6] + off, ex[7] + off);
+  } else {
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    int64_t c = base + k;
-    if (c < n_cells) local[c] = ex[k] + off;
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t c = base + k;
+      if (c < n_cells) local[c] = ex[k] + off;
+    }
   }
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&chunk_sum[blockIdx.x], total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  // Last block: every chunk total is published; scan them in tiles of kBlock.
+  if (threadIdx.x == 0) chunk_sum[blockIdx.x] = total;
+}
+
+// Second step, one block: exclusive scan of the chunk totals in tiles of
+// kBlock; chunk_sum[n_chunks] receives the grand total.
+__global__ __launch_bounds__(kBlock) void k_scan_totals(uint32_t* __restrict__ chunk_sum, int n_chunks) {
   uint32_t carry = 0;
   for (int b0 = 0; b0 < n_chunks; b0 += kBlock) {
-    int b = b0 + (int)threadIdx.x;
-    uint32_t v = (b < n_chunks)
-                     ? __hip_atomic_load(&chunk_sum[b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
-                     : 0u;
+    const int b = b0 + (int)threadIdx.x;
+    const uint32_t v = b < n_chunks ? chunk_sum[b] : 0u;
     uint32_t tile;
-    uint32_t e = block_exclusive_scan(v, &tile);
+    const uint32_t e = block_exclusive_scan(v, &tile);
     if (b < n_chunks) chunk_sum[b] = carry + e;
     carry += tile;
   }
-  if (threadIdx.x == 0) {
-    chunk_sum[n_chunks] = carry;
-    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) chunk_sum[n_chunks] = carry;
 }
 
 __device__ __forceinline__ uint32_t cell_offset(const uint32_t* local, const uint32_t* chunk_sum,
@@ -515,11 +533,10 @@ __global__ __launch_bounds__(kBlock) void k_stable_batched(const uint32_t* __res
   out[dst] = o;
 }
 
-hipError_t scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t* chunk_sum,
-                     uint32_t* ticket, hipStream_t st) {
-  int n_chunks = (int)((n_bins + kScanChunk - 1) / kScanChunk);
-  hipLaunchKernelGGL(k_scan_cells, dim3(n_chunks), dim3(kBlock), 0, st, counts, n_bins, local,
-                     chunk_sum, ticket, n_chunks);
+hipError_t scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t* chunk_sum, hipStream_t st) {
+  const int n_chunks = (int)((n_bins + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(n_chunks), dim3(kBlock), 0, st, counts, n_bins, local, chunk_sum);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, st, chunk_sum, n_chunks);
   return hipGetLastError();
 }
 
@@ -532,7 +549,7 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
     hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, gc, lr_x, n_lr,
                        s.keys, s.slot, s.counts);
   }
-  hipError_t e = scan_bins(s.counts, n_cells, s.local, s.chunk_sum, s.ticket, st);
+  hipError_t e = scan_bins(s.counts, n_cells, s.local, s.chunk_sum, st);
   if (e != hipSuccess) return e;
   int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);
   int64_t span = n_lr > n_cells + 1 ? n_lr : n_cells + 1;
@@ -550,7 +567,7 @@ hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& 
     hipLaunchKernelGGL(k_keys_count_batched, dim3((unsigned)b.n_lr_blocks), dim3(kBlock), 0, st, b, s.keys,
                        s.slot, s.counts);
   }
-  hipError_t e = scan_bins(s.counts, b.n_cells, s.local, s.chunk_sum, s.ticket, st);
+  hipError_t e = scan_bins(s.counts, b.n_cells, s.local, s.chunk_sum, st);
   if (e != hipSuccess) return e;
   const int n_chunks = (int)((b.n_cells + kScanChunk - 1) / kScanChunk);
   const int64_t span = b.n_int > b.n_cells + 1 ? b.n_int : b.n_cells + 1;
@@ -573,7 +590,7 @@ hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* h
   hipLaunchKernelGGL(k_hr_keys_count, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)),
                      dim3(kBlock), 0, st, gc, hr_x, n_hr,
                      sub, mode, bits[0], bits[1], bits[2], s.keys, s.slot, s.src, s.counts);
-  hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, s.ticket, st);
+  hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
   if (e != hipSuccess) return e;
   const bool in_place = out_x == hr_x || out_v == hr_v;
   int32_t* perm = (perm_out != nullptr && !in_place) ? perm_out : s.perm;

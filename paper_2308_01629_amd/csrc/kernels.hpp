@@ -16,7 +16,6 @@ struct GridScratch {
   uint32_t* counts;      // [n_cells] per-cell count; zero between builds
   uint32_t* local;       // [n_cells] exclusive scan inside each scan chunk
   uint32_t* chunk_sum;   // [n_chunks + 1] chunk totals, then exclusive chunk offsets
-  uint32_t* ticket;      // [1] arrival counter of the scan's last-block step
   uint32_t* cell_start;  // [n_cells + 1]
   LRPoint* lr_sorted;    // [max_lr]
 };
@@ -39,7 +38,6 @@ struct HRSortScratch {
   uint32_t* counts;     // [n_bins], zero between sorts
   uint32_t* local;      // [n_bins]
   uint32_t* chunk_sum;  // [n_bins / kScanChunk + 2]
-  uint32_t* ticket;     // [1]
   int64_t n_cells;      // grid cells
   int64_t n_bins;       // bins allocated in counts / local
   int max_sub;          // largest sub-cell count per axis the bins are sized for (4, 2 or 1)

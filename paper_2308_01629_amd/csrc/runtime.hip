@@ -144,10 +144,10 @@ hipError_t dmalloc(T** p, int64_t count) {
 
 void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
-                  h->g.ticket, h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.src, h->hs.x,
-                  h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum, h->hs.ticket,
+                  h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.src, h->hs.x,
+                  h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum,
                   h->finite_flag, h->g2.keys, h->g2.slot, h->g2.tmp, h->g2.perm, h->g2.counts,
-                  h->g2.local, h->g2.chunk_sum, h->g2.ticket, h->g2.cell_start, h->g2.lr_sorted,
+                  h->g2.local, h->g2.chunk_sum, h->g2.cell_start, h->g2.lr_sorted,
                   h->run_perm};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
@@ -311,7 +311,6 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->g.counts, h->n_cells)
   ALLOC(h->g.local, h->n_cells)
   ALLOC(h->g.chunk_sum, h->n_chunks + 1)
-  ALLOC(h->g.ticket, 1)
   ALLOC(h->g.cell_start, h->n_cells + 1)
   ALLOC(h->g.lr_sorted, nl)
   ALLOC(h->hs.keys, nh)
@@ -346,13 +345,10 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->hs.counts, n_bins)
   ALLOC(h->hs.local, n_bins)
   ALLOC(h->hs.chunk_sum, n_bins / kScanChunk + 2)
-  ALLOC(h->hs.ticket, 1)
   ALLOC(h->finite_flag, 1)
 #undef ALLOC
   if (e == hipSuccess) e = hipMemset(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells);
-  if (e == hipSuccess) e = hipMemset(h->g.ticket, 0, sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemset(h->hs.counts, 0, sizeof(uint32_t) * (size_t)n_bins);
-  if (e == hipSuccess) e = hipMemset(h->hs.ticket, 0, sizeof(uint32_t));
   for (int k = 0; k < 2 * kTimingRing && e == hipSuccess; ++k) e = hipEventCreate(&h->ev[k]);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -396,7 +392,6 @@ int upsample_build_grid(upsample_handle h, const float* lr_x, const float* lr_v,
   hipError_t e = hipSuccess;
   if (h->counts_dirty) {
     e = hipMemsetAsync(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
-    if (e == hipSuccess) e = hipMemsetAsync(h->g.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "build_grid");
     h->counts_dirty = false;
   }
@@ -590,7 +585,6 @@ static int run_prepare(upsample_handle h, hipStream_t st) {
     ALLOC(h->g2.counts, h->n_cells)
     ALLOC(h->g2.local, h->n_cells)
     ALLOC(h->g2.chunk_sum, h->n_chunks + 1)
-    ALLOC(h->g2.ticket, 1)
     ALLOC(h->g2.cell_start, h->n_cells + 1)
     ALLOC(h->g2.lr_sorted, nl)
     ALLOC(h->run_perm, nh)
@@ -613,13 +607,11 @@ static int run_prepare(upsample_handle h, hipStream_t st) {
   }
   if (h->g2_dirty) {
     e = hipMemsetAsync(h->g2.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
-    if (e == hipSuccess) e = hipMemsetAsync(h->g2.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "run");
     h->g2_dirty = false;
   }
   if (h->counts_dirty) {
     e = hipMemsetAsync(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
-    if (e == hipSuccess) e = hipMemsetAsync(h->g.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "run");
     h->counts_dirty = false;
   }
@@ -650,7 +642,6 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
   if (rc != UPSAMPLE_OK) return rc;
   if (h->hr_counts_dirty && sort_every > 0) {
     hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)h->hs.n_bins, st);
-    if (e == hipSuccess) e = hipMemsetAsync(h->hs.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "run");
     h->hr_counts_dirty = false;
   }
@@ -732,7 +723,6 @@ int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, fl
     return fail(h, UPSAMPLE_ERR_GRID_TOO_LARGE, "grid too fine for the HR reorder (more than 2^24 Morton bins)");
   if (h->hr_counts_dirty) {
     hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)h->hs.n_bins, st);
-    if (e == hipSuccess) e = hipMemsetAsync(h->hs.ticket, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return hip_fail(h, e, "sort_hr");
     h->hr_counts_dirty = false;
   }
