@@ -194,7 +194,49 @@ struct DotStage {
     return make_float4(qx, qy, qz, -(fmaf(qz, qz, fmaf(qy, qy, qx * qx)) * inv_h2));
   }
   __device__ __forceinline__ float4 pad() const { return make_float4(0.0f, 0.0f, 0.0f, -3.0e38f); }
+  __device__ __forceinline__ float4 vel(float4 V) const { return V; }
 };
+
+// Velocity entries (V_j, 1): with them the sums (Ux, Uy, Uz, S) of a wave are
+// one matrix product, weights (64 lanes x entries) times entries (entries x 4).
+template <class Base>
+struct WithOnes : Base {
+  __device__ __forceinline__ float4 vel(float4 V) const { return make_float4(V.x, V.y, V.z, 1.0f); }
+};
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// One list entry of the matrix-core accumulation (v_mfma_f32_4x4x1f32, 16
+// blocks of 4 lanes): lane l supplies its weight w (A) and component l mod 4
+// of the entry's (Vx, Vy, Vz, 1) (B); register r of lane l accumulates
+// sum_c w(particle 4 floor(l/4) + r, c) * V_c[l mod 4].
+__device__ __forceinline__ v4f mfma_entry(float w, float b, v4f acc) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(w, b, acc, 0, 0, 0);
+}
+
+// Value of v at lane n of each quad (DPP quad_perm [n, n, n, n]).
+template <int N>
+__device__ __forceinline__ float quad_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), N * 0x55, 0xf, 0xf, false));
+}
+
+// Register i of lane 4q + n, for the lane 4q + i that calls it.
+template <int N>
+__device__ __forceinline__ float quad_pick(v4f acc, int i) {
+  const float t0 = quad_lane<N>(acc[0]), t1 = quad_lane<N>(acc[1]);
+  const float t2 = quad_lane<N>(acc[2]), t3 = quad_lane<N>(acc[3]);
+  return i == 0 ? t0 : (i == 1 ? t1 : (i == 2 ? t2 : t3));
+}
+
+// Transpose of each quad's 4 x 4 block: lane 4q + i receives register i of
+// lanes 4q + 0..3, i.e. (Ux, Uy, Uz, S) of its own particle.
+__device__ __forceinline__ void quad_sums(v4f acc, int lane, float& Ux, float& Uy, float& Uz, float& S) {
+  const int i = lane & 3;
+  Ux = quad_pick<0>(acc, i);
+  Uy = quad_pick<1>(acc, i);
+  Uz = quad_pick<2>(acc, i);
+  S = quad_pick<3>(acc, i);
+}
 
 // One block-sized tile of HR particles first .. first + kBlock - 1 (those
 // below a.n are live; the rest shadow the last particle and write nothing).
@@ -234,7 +276,54 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
       hi0 = fmaxf(hi0, ts.gb[g].hi[0]); hi1 = fmaxf(hi1, ts.gb[g].hi[1]); hi2 = fmaxf(hi2, ts.gb[g].hi[2]);
     }
     const float ext = fmaxf(hi0 - lo0, fmaxf(hi1 - lo1, hi2 - lo2));
-    if (!RIGID && ext * ext <= 4.0f * gc.h2) {
+    if (!RIGID && !TAPE) {
+      // weights in the vector unit, sums on the matrix cores
+      v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      const int comp = lane & 3;
+      // M as the integer maximum of the weights' bits: exact for w >= 0 (a
+      // -0 weight sorts lowest) and free of the NaN canonicalisation of fmaxf
+      int Mb = 0;
+      if (ext * ext <= 4.0f * gc.h2) {
+        const DotStage ds{0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2), inv_h2};
+        const float px = x - ds.cx, py = y - ds.cy, pz = z - ds.cz;
+        const float A = fmaf(-fmaf(pz, pz, fmaf(py, py, px * px)), inv_h2, 1.0f);
+        const float k2 = 2.0f * inv_h2;
+        const float Px = k2 * px, Py = k2 * py, Pz = k2 * pz;
+        tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
+          const float* lvc = reinterpret_cast<const float*>(lv) + comp;
+          for (uint32_t c0 = 0; c0 < nc; c0 += 4) {
+#pragma unroll
+            for (uint32_t c = c0; c < c0 + 4; ++c) {
+              const float4 Q = lp[c];
+              const float b = lvc[4 * c];
+              const float u = fmaxf(fmaf(Q.x, Px, fmaf(Q.y, Py, fmaf(Q.z, Pz, A + Q.w))), 0.0f);
+              const float w = u * u * u;
+              Mb = max(Mb, __float_as_int(w));
+              acc = mfma_entry(w, b, acc);
+            }
+          }
+        }, SortedTag(), WithOnes<DotStage>{ds});
+      } else {
+        tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
+          const float* lvc = reinterpret_cast<const float*>(lv) + comp;
+          for (uint32_t c0 = 0; c0 < nc; c0 += 4) {
+#pragma unroll
+            for (uint32_t c = c0; c < c0 + 4; ++c) {
+              const float4 Q = lp[c];
+              const float b = lvc[4 * c];
+              const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
+              const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
+              const float w = u * u * u;
+              Mb = max(Mb, __float_as_int(w));
+              acc = mfma_entry(w, b, acc);
+            }
+          }
+        }, SortedTag(), WithOnes<PlainStage>{});
+      }
+      M = __int_as_float(Mb);
+      quad_sums(acc, lane, Ux, Uy, Uz, S);
+    } else if (!RIGID && ext * ext <= 4.0f * gc.h2) {
       const DotStage ds{0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2), inv_h2};
       const float px = x - ds.cx, py = y - ds.cy, pz = z - ds.cz;
       const float A = fmaf(-fmaf(pz, pz, fmaf(py, py, px * px)), inv_h2, 1.0f);

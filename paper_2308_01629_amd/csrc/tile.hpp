@@ -214,24 +214,30 @@ struct SortedTag {
 };
 
 // Default staging: the candidate's position with its tag; padding entries sit
-// far away (weight exactly 0 for every lane).
+// far away (weight exactly 0 for every lane).  vel(V) gives the 16 bytes
+// stored in the velocity list (by default the LR copy's (V_j, index bits)).
 struct PlainStage {
   __device__ __forceinline__ float4 operator()(float4 P, uint32_t bits) const {
     return make_float4(P.x, P.y, P.z, __uint_as_float(bits));
   }
   __device__ __forceinline__ float4 pad() const { return make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f); }
+  __device__ __forceinline__ float4 vel(float4 V) const { return V; }
 };
 
 // Stream the candidates and hand the LDS lists to visit(nc, p_list, v_list)
 // in chunks; p_list / v_list point at this lane's group list.  tag(row, k, j,
 // flag) gives the 32 bits stored in the .w of the position entry.
 // stage(P, tag) gives the 16 bytes stored for a kept candidate (culling
-// always uses its absolute position); stage.pad() the padding entry.
-template <int G, class L, class Visit, class Tag = SortedTag, class Stage = PlainStage>
+// always uses its absolute position), stage.vel(V) its velocity entry and
+// stage.pad() the padding entry (whose velocity entry is zero).
+// Round > 1 pads every chunk to a multiple of Round entries, so that the
+// visitor can unroll by Round with immediate LDS offsets.
+template <int G, int Round = 1, class L, class Visit, class Tag = SortedTag, class Stage = PlainStage>
 __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridConst& gc,
                                            const LRPoint* __restrict__ lr, int lane, int wid,
                                            L& lds, Visit&& visit, Tag tag = Tag(), Stage stage = Stage()) {
   constexpr int kCap = L::kCap;
+  static_assert(Round >= 1 && kCap % Round == 0, "padded chunks must fit the list");
   static_assert(L::kRows == 64, "the streaming gives each lane one stencil row");
   const int grp = lane / (64 / G);
   const float cull2 = gc.h2 * 1.001f;
@@ -276,21 +282,22 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
         const uint32_t pos = cnt[g] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         lds.p[wid][g][pos] = pj;
-        lds.v[wid][g][pos] = V;
+        lds.v[wid][g][pos] = stage.vel(V);
       }
       cnt[g] += (uint32_t)__popcll(m);
       nmax = max(nmax, cnt[g]);
     }
     if (nmax + 64u <= (uint32_t)kCap && k0 + 64u < ts.total) continue;  // room for another pass
+    const uint32_t npad = (nmax + (uint32_t)(Round - 1)) / (uint32_t)Round * (uint32_t)Round;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      for (uint32_t q = cnt[g] + (uint32_t)lane; q < nmax; q += 64u) {
+      for (uint32_t q = cnt[g] + (uint32_t)lane; q < npad; q += 64u) {
         lds.p[wid][g][q] = far_p;
         lds.v[wid][g][q] = zero4;
       }
     }
     wave_lds_sync();
-    visit(__builtin_amdgcn_readfirstlane(nmax), &lds.p[wid][grp][0], &lds.v[wid][grp][0]);
+    visit(__builtin_amdgcn_readfirstlane(npad), &lds.p[wid][grp][0], &lds.v[wid][grp][0]);
 #pragma unroll
     for (int g = 0; g < G; ++g) cnt[g] = 0u;
     wave_lds_sync();
