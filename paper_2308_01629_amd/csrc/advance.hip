@@ -7,6 +7,8 @@
 // write consecutive floats (six fully coalesced 256-byte accesses per wave
 // each way).  Along x the cells of one (y, z) row of the stencil are adjacent
 // keys, so each row is one contiguous range of the sorted LR copy.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "tile.hpp"
 
@@ -206,6 +208,8 @@ struct WithOnes : Base {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+
+
 // One list entry of the matrix-core accumulation (v_mfma_f32_4x4x1f32, 16
 // blocks of 4 lanes): lane l supplies its weight w (A) and component l mod 4
 // of the entry's (Vx, Vy, Vz, 1) (B); register r of lane l accumulates
@@ -276,64 +280,74 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
       hi0 = fmaxf(hi0, ts.gb[g].hi[0]); hi1 = fmaxf(hi1, ts.gb[g].hi[1]); hi2 = fmaxf(hi2, ts.gb[g].hi[2]);
     }
     const float ext = fmaxf(hi0 - lo0, fmaxf(hi1 - lo1, hi2 - lo2));
-    if (!RIGID && !TAPE) {
+    if (!RIGID) {
       // weights in the vector unit, sums on the matrix cores
       v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
       const int comp = lane & 3;
       // M as the integer maximum of the weights' bits: exact for w >= 0 (a
       // -0 weight sorts lowest) and free of the NaN canonicalisation of fmaxf
       int Mb = 0;
+      // one list entry: lvf points at the velocity list as floats.  Without a
+      // tape the entries are (V_j, 1); with one they keep the index bits in
+      // .w for the argmax, and lanes of component 3 use 1 instead.
+      auto take = [&](float w, const float* lvf, uint32_t c) {
+        float b = lvf[4 * c + comp];
+        if (TAPE) {
+          b = comp == 3 ? 1.0f : b;
+          const uint32_t id = __float_as_uint(lvf[4 * c + 3]);
+          const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~id);
+          key = k > key ? k : key;
+        } else {
+          Mb = max(Mb, __float_as_int(w));
+        }
+        acc = mfma_entry(w, b, acc);
+      };
       if (ext * ext <= 4.0f * gc.h2) {
         const DotStage ds{0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2), inv_h2};
         const float px = x - ds.cx, py = y - ds.cy, pz = z - ds.cz;
         const float A = fmaf(-fmaf(pz, pz, fmaf(py, py, px * px)), inv_h2, 1.0f);
         const float k2 = 2.0f * inv_h2;
         const float Px = k2 * px, Py = k2 * py, Pz = k2 * pz;
+        using Stage = std::conditional_t<TAPE, DotStage, WithOnes<DotStage>>;
         tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
-          const float* lvc = reinterpret_cast<const float*>(lv) + comp;
+          const float* lvf = reinterpret_cast<const float*>(lv);
           for (uint32_t c0 = 0; c0 < nc; c0 += 4) {
 #pragma unroll
-            for (uint32_t c = c0; c < c0 + 4; ++c) {
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t c = c0 + (uint32_t)k;
               const float4 Q = lp[c];
-              const float b = lvc[4 * c];
               const float u = fmaxf(fmaf(Q.x, Px, fmaf(Q.y, Py, fmaf(Q.z, Pz, A + Q.w))), 0.0f);
-              const float w = u * u * u;
-              Mb = max(Mb, __float_as_int(w));
-              acc = mfma_entry(w, b, acc);
+              take(u * u * u, lvf, c);
             }
           }
-        }, SortedTag(), WithOnes<DotStage>{ds});
+        }, SortedTag(), Stage{ds});
       } else {
+        using Stage = std::conditional_t<TAPE, PlainStage, WithOnes<PlainStage>>;
         tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
-          const float* lvc = reinterpret_cast<const float*>(lv) + comp;
+          const float* lvf = reinterpret_cast<const float*>(lv);
           for (uint32_t c0 = 0; c0 < nc; c0 += 4) {
 #pragma unroll
-            for (uint32_t c = c0; c < c0 + 4; ++c) {
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t c = c0 + (uint32_t)k;
               const float4 Q = lp[c];
-              const float b = lvc[4 * c];
               const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
               const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
               const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
-              const float w = u * u * u;
-              Mb = max(Mb, __float_as_int(w));
-              acc = mfma_entry(w, b, acc);
+              take(u * u * u, lvf, c);
             }
           }
-        }, SortedTag(), WithOnes<PlainStage>{});
+        }, SortedTag(), Stage{});
       }
-      M = __int_as_float(Mb);
+      if (!TAPE) M = __int_as_float(Mb);
       quad_sums(acc, lane, Ux, Uy, Uz, S);
-    } else if (!RIGID && ext * ext <= 4.0f * gc.h2) {
-      const DotStage ds{0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2), inv_h2};
-      const float px = x - ds.cx, py = y - ds.cy, pz = z - ds.cz;
-      const float A = fmaf(-fmaf(pz, pz, fmaf(py, py, px * px)), inv_h2, 1.0f);
-      const float k2 = 2.0f * inv_h2;
-      const float Px = k2 * px, Py = k2 * py, Pz = k2 * pz;
+    } else {  // scenes with rigid LR particles: the membership test needs each pair
       tile_visit<G>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
         for (uint32_t c = 0; c < nc; ++c) {
           const float4 Q = lp[c];
           const float4 W = lv[c];
-          const float u = fmaxf(fmaf(Q.x, Px, fmaf(Q.y, Py, fmaf(Q.z, Pz, A + Q.w))), 0.0f);
+          const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
+          const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
           const float w = u * u * u;
           S += w;
           Ux = fmaf(w, W.x, Ux);
@@ -345,34 +359,13 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
           } else {
             M = fmaxf(M, w);
           }
+          if (RIGID) {
+            const uint32_t bits = __float_as_uint(Q.w);
+            // exact membership of a granular LR particle decides the rigid rule
+            if ((bits & 0x80000000u) == 0u && Q.x < 1.0e38f) gran |= sq_dist(Q.x, Q.y, Q.z, x, y, z) < gc.h2;
+          }
         }
-      }, SortedTag(), ds);
-    } else {
-    tile_visit<G>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
-      for (uint32_t c = 0; c < nc; ++c) {
-        const float4 Q = lp[c];
-        const float4 W = lv[c];
-        const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
-        const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
-        const float w = u * u * u;
-        S += w;
-        Ux = fmaf(w, W.x, Ux);
-        Uy = fmaf(w, W.y, Uy);
-        Uz = fmaf(w, W.z, Uz);
-        if (TAPE) {
-          const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~__float_as_uint(W.w));
-          key = k > key ? k : key;
-        } else {
-          M = fmaxf(M, w);
-        }
-        if (RIGID) {
-          const uint32_t bits = __float_as_uint(Q.w);
-          // exact membership of a granular LR particle decides the rigid rule
-          if ((bits & 0x80000000u) == 0u && Q.x < 1.0e38f) gran |= sq_dist(Q.x, Q.y, Q.z, x, y, z) < gc.h2;
-        }
-      }
-    });
+      });
     }
     if (TAPE) {
       M = __uint_as_float((uint32_t)(key >> 32));

@@ -260,19 +260,18 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
     wave_lds_sync();
     const int lo = (int)wave_prefix_max(lds.mark[wid][lane]);
     carried = __builtin_amdgcn_readlane(lo, 63);
+    // Lanes past the last candidate load the last one (its row is the one
+    // the prefix maximum gives them) and keep nothing: no branch around the
+    // loads.
+    const bool valid = k < ts.total;
+    const uint32_t kk = valid ? k : ts.total - 1u;
+    const uint32_t j = lds.rb[wid][lo] + (kk - lds.rp[wid][lo]);
+    const float4 P = lr[j].p;
+    const float4 V = lr[j].v;
+    const uint32_t bits = tag(lo, kk, j, P.w);
     bool keep[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) keep[g] = false;
-    float4 P = zero4, V = zero4;
-    uint32_t bits = 0;
-    if (k < ts.total) {
-      const uint32_t j = lds.rb[wid][lo] + (k - lds.rp[wid][lo]);
-      P = lr[j].p;
-      V = lr[j].v;
-      bits = tag(lo, k, j, P.w);
-#pragma unroll
-      for (int g = 0; g < G; ++g) keep[g] = box_dist2(ts.gb[g], P.x, P.y, P.z) <= cull2;
-    }
+    for (int g = 0; g < G; ++g) keep[g] = valid && box_dist2(ts.gb[g], P.x, P.y, P.z) <= cull2;
     const float4 pj = stage(P, bits);
     uint32_t nmax = 0;
 #pragma unroll
