@@ -211,14 +211,15 @@ int upsample_step_backward_taped(upsample_handle h,
  * consecutive LR frames (lr_x, lr_v: device [n_frames][3][n_lr]; lr_rigid, if
  * given, applies to every frame), i.e. n_frames upsample_step calls.  Before
  * step t the state is reordered as by upsample_sort_hr when sort_every > 0
- * and t % sort_every == 0.  Each frame's grid is built on an internal stream
- * into one of two buffers while the previous frame's step kernel runs; HIP
- * events order the two streams, and everything is done when the caller's
- * stream reaches the call's end.  perm_io (device int32 [n_hr], may be NULL)
- * maps positions to particles: on entry the particle at each position (for
- * instance 0, 1, 2, ...), on return the same after the reorders.  The
- * handle's grid afterwards is the last frame's.  The first call allocates a
- * second grid buffer and the internal stream.  Results per particle equal
+ * and t % sort_every == 0.  The grids are built on an internal stream in
+ * batches of 4 frames, into two sets of 4 grid buffers: batch k + 1 is built
+ * while the step kernels of batch k run.  HIP events order the two streams
+ * once per batch, and everything is done when the caller's stream reaches the
+ * call's end.  perm_io (device int32 [n_hr], may be NULL) maps positions to
+ * particles: on entry the particle at each position (for instance 0, 1, 2,
+ * ...), on return the same after the reorders.  The handle's grid afterwards
+ * is the last frame's.  The first call allocates seven more grid buffers and
+ * the internal stream.  Results per particle equal
  * those of the step-by-step loop up to float32 rounding (reorders change the
  * waves).
  */

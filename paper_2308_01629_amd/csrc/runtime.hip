@@ -12,6 +12,7 @@
 using namespace ups;
 
 static constexpr int kTimingRing = 256;
+static constexpr int kRunBatch = 4;  // frames per grid-build batch of upsample_run
 
 struct upsample_handle_s {
   upsample_params p;
@@ -22,11 +23,12 @@ struct upsample_handle_s {
   int n_chunks;
   GridScratch g;
   HRSortScratch hs;
-  // upsample_run: second grid buffer, its build stream and events, the
-  // permutation scratch (allocated at the first call)
-  GridScratch g2;
+  // upsample_run: the further grid buffers (with g, two sets of kRunBatch),
+  // their build stream and events, the permutation scratch (allocated at the
+  // first call)
+  GridScratch run_g[2 * kRunBatch - 1];
   bool run_ready;
-  bool g2_dirty;
+  bool run_dirty;
   hipStream_t side;
   hipEvent_t built[2], consumed[2], entry;
   int32_t* run_perm;
@@ -146,11 +148,14 @@ void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
                   h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.src, h->hs.x,
                   h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum,
-                  h->finite_flag, h->g2.keys, h->g2.slot, h->g2.tmp, h->g2.perm, h->g2.counts,
-                  h->g2.local, h->g2.chunk_sum, h->g2.cell_start, h->g2.lr_sorted,
-                  h->run_perm};
+                  h->finite_flag, h->run_perm};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
+  for (const GridScratch& g : h->run_g) {
+    void* rq[] = {g.keys, g.slot, g.tmp, g.perm, g.counts, g.local, g.chunk_sum, g.cell_start, g.lr_sorted};
+    for (void* q : rq)
+      if (q != nullptr) (void)hipFree(q);
+  }
   if (h->run_ready) {
     (void)hipStreamDestroy(h->side);
     for (int k = 0; k < 2; ++k) {
@@ -578,15 +583,17 @@ static int run_prepare(upsample_handle h, hipStream_t st) {
     const int64_t nl = h->p.max_lr, nh = h->p.max_hr;
 #define ALLOC(ptr, n) \
   if (e == hipSuccess) e = dmalloc(&(ptr), (n));
-    ALLOC(h->g2.keys, nl)
-    ALLOC(h->g2.slot, nl)
-    ALLOC(h->g2.tmp, nl)
-    ALLOC(h->g2.perm, nl)
-    ALLOC(h->g2.counts, h->n_cells)
-    ALLOC(h->g2.local, h->n_cells)
-    ALLOC(h->g2.chunk_sum, h->n_chunks + 1)
-    ALLOC(h->g2.cell_start, h->n_cells + 1)
-    ALLOC(h->g2.lr_sorted, nl)
+    for (GridScratch& g : h->run_g) {
+      ALLOC(g.keys, nl)
+      ALLOC(g.slot, nl)
+      ALLOC(g.tmp, nl)
+      ALLOC(g.perm, nl)
+      ALLOC(g.counts, h->n_cells)
+      ALLOC(g.local, h->n_cells)
+      ALLOC(g.chunk_sum, h->n_chunks + 1)
+      ALLOC(g.cell_start, h->n_cells + 1)
+      ALLOC(g.lr_sorted, nl)
+    }
     ALLOC(h->run_perm, nh)
 #undef ALLOC
     hipEvent_t* evs[5] = {&h->built[0], &h->built[1], &h->consumed[0], &h->consumed[1], &h->entry};
@@ -603,12 +610,13 @@ static int run_prepare(upsample_handle h, hipStream_t st) {
       return hip_fail(h, e, "run: allocation");
     }
     h->run_ready = true;
-    h->g2_dirty = true;
+    h->run_dirty = true;
   }
-  if (h->g2_dirty) {
-    e = hipMemsetAsync(h->g2.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
+  if (h->run_dirty) {
+    for (const GridScratch& g : h->run_g)
+      if (e == hipSuccess) e = hipMemsetAsync(g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
     if (e != hipSuccess) return hip_fail(h, e, "run");
-    h->g2_dirty = false;
+    h->run_dirty = false;
   }
   if (h->counts_dirty) {
     e = hipMemsetAsync(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
@@ -647,62 +655,79 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
   }
   h->has_rigid = lr_rigid != nullptr;
   const GridConst gc = grid_const(h);
-  GridScratch* buf[2] = {&h->g, &h->g2};
+  // Frames go in batches of kRunBatch: batch t uses buffer set t mod 2 (set
+  // 0 starts with the handle's own grid).  The side stream builds batch t + 1
+  // while the gathers of batch t run, once the gathers of batch t - 1 are done
+  // with that set; the main stream waits once per batch.  Per frame, only the
+  // gather (and a reorder when due) is queued on the caller's stream.
+  GridScratch* buf[2 * kRunBatch];
+  buf[0] = &h->g;
+  for (int k = 1; k < 2 * kRunBatch; ++k) buf[k] = &h->run_g[k - 1];
   const size_t frame = 3 * (size_t)n_lr;
+  const int n_batches = (n_frames + kRunBatch - 1) / kRunBatch;
   // the side stream starts after the caller's earlier work on the stream
   hipError_t e = hipEventRecord(h->entry, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->entry, 0);
-  auto build = [&](int f) -> hipError_t {
-    const int b = f & 1;
-    hipError_t r = hipStreamWaitEvent(h->side, h->consumed[b], 0);  // gather f - 2 is done with buffer b
-    if (r == hipSuccess)
+  auto build_batch = [&](int t) -> hipError_t {
+    const int set = t & 1;
+    hipError_t r = hipStreamWaitEvent(h->side, h->consumed[set], 0);  // batch t - 2 is done with the set
+    for (int j = 0; j < kRunBatch && r == hipSuccess; ++j) {
+      const int f = t * kRunBatch + j;
+      if (f >= n_frames) break;
       r = launch_build_grid(gc, lr_x + frame * (size_t)f, lr_v + frame * (size_t)f, lr_rigid, n_lr, h->n_cells,
-                            *buf[b], h->side);
-    if (r == hipSuccess) r = hipEventRecord(h->built[b], h->side);
+                            *buf[set * kRunBatch + j], h->side);
+    }
+    if (r == hipSuccess) r = hipEventRecord(h->built[set], h->side);
     return r;
   };
-  if (e == hipSuccess) e = build(0);
-  for (int f = 0; f < n_frames && e == hipSuccess; ++f) {
-    const int b = f & 1;
-    if (f + 1 < n_frames) e = build(f + 1);  // overlaps with the gather of frame f
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, h->built[b], 0);
+  if (e == hipSuccess) e = build_batch(0);
+  int last = 0;  // buffer of the last frame gathered
+  for (int t = 0; t < n_batches && e == hipSuccess; ++t) {
+    const int set = t & 1;
+    if (t + 1 < n_batches) e = build_batch(t + 1);  // overlaps with the gathers of batch t
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, h->built[set], 0);
     if (e != hipSuccess) break;
     h->grid_valid = true;
     h->grid_n_lr = n_lr;
-    const float* in_x = hr_x;
-    const float* in_v = hr_v;
-    if (sort_every > 0 && f % sort_every == 0 && n_hr > 0) {
-      // reorder into scratch; the step writes the state back into hr_x / hr_v
-      int32_t* p = perm_io != nullptr ? h->run_perm : nullptr;
-      e = launch_sort_hr(gc, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, h->tune.sort_sub, h->tune.sort_mode, h->hs, p,
-                         st);
-      if (e == hipSuccess && p != nullptr) e = launch_compose_perm(perm_io, p, n_hr, h->hs.slot, st);
-      if (e != hipSuccess) {
-        h->hr_counts_dirty = true;
-        break;
+    for (int j = 0; j < kRunBatch && e == hipSuccess; ++j) {
+      const int f = t * kRunBatch + j;
+      if (f >= n_frames) break;
+      const float* in_x = hr_x;
+      const float* in_v = hr_v;
+      if (sort_every > 0 && f % sort_every == 0 && n_hr > 0) {
+        // reorder into scratch; the step writes the state back into hr_x / hr_v
+        int32_t* p = perm_io != nullptr ? h->run_perm : nullptr;
+        e = launch_sort_hr(gc, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, h->tune.sort_sub, h->tune.sort_mode, h->hs, p,
+                           st);
+        if (e == hipSuccess && p != nullptr) e = launch_compose_perm(perm_io, p, n_hr, h->hs.slot, st);
+        if (e != hipSuccess) {
+          h->hr_counts_dirty = true;
+          break;
+        }
+        in_x = h->hs.x;
+        in_v = h->hs.v;
       }
-      in_x = h->hs.x;
-      in_v = h->hs.v;
+      last = set * kRunBatch + j;
+      rc = advance_impl(h, in_x, in_v, hr_x, hr_v, n_hr, stream, false, nullptr, nullptr, 0, nullptr, nullptr,
+                        buf[last]);
+      if (rc != UPSAMPLE_OK) {
+        h->counts_dirty = h->run_dirty = true;
+        (void)hipStreamSynchronize(h->side);
+        return rc;
+      }
     }
-    rc = advance_impl(h, in_x, in_v, hr_x, hr_v, n_hr, stream, false, nullptr, nullptr, 0, nullptr, nullptr,
-                      buf[b]);
-    if (rc != UPSAMPLE_OK) {
-      h->counts_dirty = h->g2_dirty = true;
-      (void)hipStreamSynchronize(h->side);
-      return rc;
-    }
-    e = hipEventRecord(h->consumed[b], st);
+    if (e == hipSuccess) e = hipEventRecord(h->consumed[set], st);
   }
   if (e != hipSuccess) {
-    h->counts_dirty = h->g2_dirty = true;
+    h->counts_dirty = h->run_dirty = true;
     (void)hipStreamSynchronize(h->side);
     return hip_fail(h, e, "run");
   }
   // the handle's grid is the last frame's
-  if (((n_frames - 1) & 1) == 1) {
+  if (last != 0) {
     const GridScratch t = h->g;
-    h->g = h->g2;
-    h->g2 = t;
+    h->g = *buf[last];
+    *buf[last] = t;
   }
   return UPSAMPLE_OK;
 }
