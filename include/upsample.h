@@ -306,10 +306,12 @@ int upsample_set_tuning(upsample_handle h, const upsample_tuning* t);
 int upsample_get_tuning(upsample_handle h, upsample_tuning* t);
 
 /*
- * Kernel-time probe for one handle: when enabled, upsample_advance records HIP
- * events around its gather kernel on the call's stream, and
+ * Kernel-time probe for one handle: when enabled, HIP events on the call's
+ * stream bracket the step kernels -- each launch of upsample_advance, and in
+ * upsample_run each stretch of consecutive step kernels of a batch (a reorder
+ * ends a stretch), so that no event packets sit between them -- and
  * upsample_timing_read returns the summed milliseconds and the number of
- * launches since the last read (it synchronises on the last event).
+ * kernel launches since the last read (it synchronises on the last event).
  */
 int upsample_timing_enable(upsample_handle h, int enable);
 int upsample_timing_read(upsample_handle h, double* advance_ms, int64_t* launches);

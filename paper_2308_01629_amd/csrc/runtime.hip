@@ -43,6 +43,9 @@ struct upsample_handle_s {
   hipEvent_t ev[2 * kTimingRing];  // start/stop pairs, reused round-robin
   int64_t timed_issued;            // pairs recorded since the last read
   int64_t timed_folded;            // pairs already summed into timed_ms
+  int32_t timed_n[kTimingRing];    // kernel launches between each pair's events
+  int64_t timed_launches;          // launches in the pairs already folded
+  int32_t seg_slot, seg_n;         // open pair: its slot and launches so far (seg_n < 0: none)
   double timed_ms;
   std::string last_error;
 };
@@ -290,6 +293,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return UPSAMPLE_ERR_NO_DEVICE;
   upsample_handle h = new (std::nothrow) upsample_handle_s();
   if (h == nullptr) return UPSAMPLE_ERR_OOM;
+  h->seg_n = -1;
   h->p = *p;
   std::memset(h->walls, 0, sizeof(h->walls));
   if (p->n_walls > 0) std::memcpy(h->walls, p->walls, sizeof(float) * UPSAMPLE_WALL_FLOATS * p->n_walls);
@@ -421,9 +425,38 @@ static hipError_t fold_timing(upsample_handle h, int64_t upto) {
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev[2 * slot], h->ev[2 * slot + 1]);
     if (e != hipSuccess) return e;
     h->timed_ms += ms;
+    h->timed_launches += h->timed_n[slot];
     h->timed_folded += 1;
   }
   return hipSuccess;
+}
+
+// Timing pairs bracket a run of consecutive step kernels on one stream (no
+// other work between them): one launch for upsample_advance, up to a batch
+// of frames in upsample_run.  A pair per launch would add its own event
+// packets to every kernel's bracket.
+static hipError_t timing_open(upsample_handle h, hipStream_t st) {
+  if (h->timed_issued - h->timed_folded >= kTimingRing) {
+    hipError_t e = fold_timing(h, h->timed_folded + 1);  // free the slot about to be reused
+    if (e != hipSuccess) return e;
+  }
+  h->seg_slot = (int32_t)(h->timed_issued % kTimingRing);
+  h->seg_n = 0;
+  return hipEventRecord(h->ev[2 * h->seg_slot], st);
+}
+
+static hipError_t timing_close(upsample_handle h, hipStream_t st) {
+  if (h->seg_n < 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (h->seg_n > 0) {
+    e = hipEventRecord(h->ev[2 * h->seg_slot + 1], st);
+    if (e == hipSuccess) {
+      h->timed_n[h->seg_slot] = h->seg_n;
+      h->timed_issued += 1;
+    }
+  }
+  h->seg_n = -1;
+  return e;
 }
 
 static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
@@ -462,21 +495,14 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
   a.groups = h->tune.gather_groups;
   a.tile_max = h->tune.tile_max;
   a.tape = tape;
+  // timed on its own unless the caller (upsample_run) has a pair open
   const bool timed = h->timing && !debug && n_hr > 0;
-  hipError_t e = hipSuccess;
-  int slot = 0;
-  if (timed) {
-    slot = (int)(h->timed_issued % kTimingRing);
-    if (h->timed_issued - h->timed_folded >= kTimingRing) {
-      e = fold_timing(h, h->timed_folded + 1);  // free the slot about to be reused
-      if (e != hipSuccess) return hip_fail(h, e, "timing");
-    }
-    e = hipEventRecord(h->ev[2 * slot], st);
-  }
+  const bool own = timed && h->seg_n < 0;
+  hipError_t e = own ? timing_open(h, st) : hipSuccess;
   if (e == hipSuccess) e = launch_advance(a, wall_table(h), debug, st);
-  if (e == hipSuccess && timed) e = hipEventRecord(h->ev[2 * slot + 1], st);
+  if (e == hipSuccess && timed) h->seg_n += 1;
+  if (e == hipSuccess && own) e = timing_close(h, st);
   if (e != hipSuccess) return hip_fail(h, e, "advance");
-  if (timed) h->timed_issued += 1;
   return UPSAMPLE_OK;
 }
 
@@ -696,6 +722,8 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
       const float* in_v = hr_v;
       if (sort_every > 0 && f % sort_every == 0 && n_hr > 0) {
         // reorder into scratch; the step writes the state back into hr_x / hr_v
+        e = timing_close(h, st);  // the reorder stays outside the timed stretch
+        if (e != hipSuccess) break;
         int32_t* p = perm_io != nullptr ? h->run_perm : nullptr;
         e = launch_sort_hr(gc, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, h->tune.sort_sub, h->tune.sort_mode, h->hs, p,
                            st);
@@ -708,18 +736,25 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
         in_v = h->hs.v;
       }
       last = set * kRunBatch + j;
+      if (h->timing && n_hr > 0 && h->seg_n < 0) {
+        e = timing_open(h, st);
+        if (e != hipSuccess) break;
+      }
       rc = advance_impl(h, in_x, in_v, hr_x, hr_v, n_hr, stream, false, nullptr, nullptr, 0, nullptr, nullptr,
                         buf[last]);
       if (rc != UPSAMPLE_OK) {
         h->counts_dirty = h->run_dirty = true;
+        (void)timing_close(h, st);
         (void)hipStreamSynchronize(h->side);
         return rc;
       }
     }
+    if (e == hipSuccess) e = timing_close(h, st);
     if (e == hipSuccess) e = hipEventRecord(h->consumed[set], st);
   }
   if (e != hipSuccess) {
     h->counts_dirty = h->run_dirty = true;
+    (void)timing_close(h, st);
     (void)hipStreamSynchronize(h->side);
     return hip_fail(h, e, "run");
   }
@@ -847,8 +882,9 @@ int upsample_timing_enable(upsample_handle h, int enable) {
   hipError_t e = fold_timing(h, h->timed_issued);
   if (e != hipSuccess) return hip_fail(h, e, "timing");
   h->timing = enable != 0;
+  h->seg_n = -1;
   h->timed_ms = 0.0;
-  h->timed_issued = h->timed_folded = 0;
+  h->timed_issued = h->timed_folded = h->timed_launches = 0;
   return UPSAMPLE_OK;
 }
 
@@ -857,9 +893,9 @@ int upsample_timing_read(upsample_handle h, double* advance_ms, int64_t* launche
   hipError_t e = fold_timing(h, h->timed_issued);
   if (e != hipSuccess) return hip_fail(h, e, "timing");
   *advance_ms = h->timed_ms;
-  *launches = h->timed_issued;
+  *launches = h->timed_launches;
   h->timed_ms = 0.0;
-  h->timed_issued = h->timed_folded = 0;
+  h->timed_issued = h->timed_folded = h->timed_launches = 0;
   return UPSAMPLE_OK;
 }
 

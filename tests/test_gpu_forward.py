@@ -420,3 +420,32 @@ def test_run_matches_step_loop_and_oracle(U, sort_every):
     # the handle's grid is the last frame's
     spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
     _grid_check(up, frames[-1][0], spec)
+
+
+def test_kernel_timing_probe_counts_launches(U):
+    """The timing probe counts every step kernel: one per upsample_advance,
+    one per frame of upsample_run (stretches cut at reorders and batches),
+    with a positive summed time; disabled, nothing is recorded."""
+    sc = configs.drain(scale=1 / 32)
+    T = 11
+    frames = [sc.lr_frame(t) for t in range(1, T + 1)]
+    LX = dev(np.stack([f[0] for f in frames]), torch)
+    LV = dev(np.stack([f[1] for f in frames]), torch)
+    up = U.from_scene(sc)
+    hx, hv = dev(sc.hr_x0, torch), dev(sc.hr_v0, torch)
+    up.build_grid(LX[0], LV[0])
+    up.timing_enable(True)
+    ox, ov = torch.empty_like(hx), torch.empty_like(hv)
+    for _ in range(3):
+        up.advance(hx, hv, ox, ov)
+    ms, k = up.timing_read()
+    assert k == 3 and ms > 0.0
+    for sort_every in (0, 3, 1):
+        up.run(LX, LV, hx, hv, sort_every=sort_every)
+        ms, k = up.timing_read()
+        log(f"timing probe: run of {T} frames, sort_every {sort_every}: {k} launches, {ms:.3f} ms")
+        assert k == T and ms > 0.0
+    up.timing_enable(False)
+    up.run(LX, LV, hx, hv, sort_every=3)
+    ms, k = up.timing_read()
+    assert k == 0 and ms == 0.0
