@@ -218,28 +218,34 @@ __device__ __forceinline__ v4f mfma_entry(float w, float b, v4f acc) {
   return __builtin_amdgcn_mfma_f32_4x4x1f32(w, b, acc, 0, 0, 0);
 }
 
-// Value of v at lane n of each quad (DPP quad_perm [n, n, n, n]).
+// Value of v at lane n of each quad (DPP quad_perm [n, n, n, n]; every lane
+// has a valid source).
 template <int N>
 __device__ __forceinline__ float quad_lane(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), N * 0x55, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), N * 0x55, 0xf, 0xf, true));
 }
 
-// Register i of lane 4q + n, for the lane 4q + i that calls it.
+// Register i of lane 4q + n, for the lane 4q + i that calls it (flat selects,
+// no branches).
 template <int N>
-__device__ __forceinline__ float quad_pick(v4f acc, int i) {
-  const float t0 = quad_lane<N>(acc[0]), t1 = quad_lane<N>(acc[1]);
-  const float t2 = quad_lane<N>(acc[2]), t3 = quad_lane<N>(acc[3]);
-  return i == 0 ? t0 : (i == 1 ? t1 : (i == 2 ? t2 : t3));
+__device__ __forceinline__ float quad_pick(v4f acc, bool i1, bool i2, bool i3) {
+  float o = quad_lane<N>(acc[0]);
+  const float t1 = quad_lane<N>(acc[1]), t2 = quad_lane<N>(acc[2]), t3 = quad_lane<N>(acc[3]);
+  o = i1 ? t1 : o;
+  o = i2 ? t2 : o;
+  o = i3 ? t3 : o;
+  return o;
 }
 
 // Transpose of each quad's 4 x 4 block: lane 4q + i receives register i of
 // lanes 4q + 0..3, i.e. (Ux, Uy, Uz, S) of its own particle.
 __device__ __forceinline__ void quad_sums(v4f acc, int lane, float& Ux, float& Uy, float& Uz, float& S) {
   const int i = lane & 3;
-  Ux = quad_pick<0>(acc, i);
-  Uy = quad_pick<1>(acc, i);
-  Uz = quad_pick<2>(acc, i);
-  S = quad_pick<3>(acc, i);
+  const bool i1 = i == 1, i2 = i == 2, i3 = i == 3;
+  Ux = quad_pick<0>(acc, i1, i2, i3);
+  Uy = quad_pick<1>(acc, i1, i2, i3);
+  Uz = quad_pick<2>(acc, i1, i2, i3);
+  S = quad_pick<3>(acc, i1, i2, i3);
 }
 
 // One block-sized tile of HR particles first .. first + kBlock - 1 (those
