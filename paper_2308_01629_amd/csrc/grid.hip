@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_hr_scatter(const uint32_t* __restric
     const uint32_t dst = cell_offset(local, chunk_sum, keys[q]) + slot[q];
     // defensive: counts started at zero, sources stay inside the block
     if (dst >= (uint64_t)n || i >= (uint64_t)n || l >= (uint32_t)kHrSpan) continue;
-    perm[dst] = (int32_t)i;
+    if (perm != nullptr) perm[dst] = (int32_t)i;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       xs[a * n + dst] = stage[a][l];
@@ -593,7 +593,8 @@ hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* h
   hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
   if (e != hipSuccess) return e;
   const bool in_place = out_x == hr_x || out_v == hr_v;
-  int32_t* perm = (perm_out != nullptr && !in_place) ? perm_out : s.perm;
+  // the old index of each new position is written only when it is asked for
+  int32_t* perm = perm_out == nullptr ? nullptr : (in_place ? s.perm : perm_out);
   hipLaunchKernelGGL(k_hr_scatter, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)), dim3(kBlock), 0, st,
                      s.keys, s.slot, s.src, n_hr,
                      s.local, s.chunk_sum, hr_x, hr_v, in_place ? s.x : out_x, in_place ? s.v : out_v,

@@ -25,9 +25,10 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
                              const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
                              const GridScratch& s, hipStream_t st);
 
-// HR reorder by the Morton (Z-order) code of fine cells (grid cells split into
-// sub^3 sub-cells), so that a wave's 64 consecutive particles sit in a compact
-// box and neighbouring waves are neighbours in space.
+// HR reorder by a space-filling key of fine cells (grid cells split into sub^3
+// sub-cells: Hilbert index, global Morton code, or cell then Morton order),
+// so that a wave's 64 consecutive particles sit in a compact box and
+// neighbouring waves are neighbours in space.
 struct HRSortScratch {
   uint32_t* keys;       // [max_hr]
   uint32_t* slot;       // [max_hr]

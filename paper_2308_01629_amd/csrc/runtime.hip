@@ -328,7 +328,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->hs.x, 3 * nh)
   ALLOC(h->hs.v, 3 * nh)
   ALLOC(h->hs.perm, nh)
-  // HR reorder bins: Morton codes of fine cells, at most 2^24 bins
+  // HR reorder bins: keys of fine cells, at most 2^24 bins
   h->hs.n_cells = h->n_cells;
   // both key modes must fit the bins allocated for max_sub
   auto bins_for = [&](int sub) {
@@ -664,7 +664,7 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
   if (n_lr > 0 && (lr_x == nullptr || lr_v == nullptr)) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "LR pointer is NULL");
   if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr)) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
   if (sort_every > 0 && n_hr > 0 && h->hs.max_sub == 0)
-    return fail(h, UPSAMPLE_ERR_GRID_TOO_LARGE, "grid too fine for the HR reorder (more than 2^24 Morton bins)");
+    return fail(h, UPSAMPLE_ERR_GRID_TOO_LARGE, "grid too fine for the HR reorder (more than 2^24 key bins)");
   int rc = check_device(h);
   if (rc != UPSAMPLE_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
@@ -780,7 +780,7 @@ int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, fl
   if (rc != UPSAMPLE_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
   if (h->hs.max_sub == 0)
-    return fail(h, UPSAMPLE_ERR_GRID_TOO_LARGE, "grid too fine for the HR reorder (more than 2^24 Morton bins)");
+    return fail(h, UPSAMPLE_ERR_GRID_TOO_LARGE, "grid too fine for the HR reorder (more than 2^24 key bins)");
   if (h->hr_counts_dirty) {
     hipError_t e = hipMemsetAsync(h->hs.counts, 0, sizeof(uint32_t) * (size_t)h->hs.n_bins, st);
     if (e != hipSuccess) return hip_fail(h, e, "sort_hr");

@@ -5,8 +5,9 @@
 // 16-lane DPP rows).  tile_setup() reduces the lanes' positions to per-group
 // bounding boxes and lists the (y, z) rows of the union of the lanes' cell
 // stencils; tile_visit() streams the LR particles of those rows through the
-// wave (one candidate per lane, a binary search over the row prefix sums) and
-// keeps a candidate in a group's LDS list when its distance to the group's box
+// wave (one candidate per lane; each round of 64 finds its candidates' rows by
+// a prefix maximum over row-start marks) and keeps a candidate in a group's
+// LDS list when its distance to the group's box
 // is below the support (a conservative test: every LR particle within the
 // support of some lane of the group is kept).  Lists are handed to the caller's
 // visitor in chunks, padded to a common length with far-away dummies whose

@@ -244,7 +244,8 @@ class Upsampler:
         return hr_x, hr_v
 
     def sort_hr(self, hr_x, hr_v, with_perm: bool = True, out_x=None, out_v=None):
-        """Reorders the HR state by grid cell / Morton sub-cell: in place by
+        """Reorders the HR state by the sub-cell key of the handle's tuning
+        (Hilbert by default; upsample_sort_hr): in place by
         default, or into out_x / out_v.  Returns the old index of each new
         position (int32) or None."""
         n = _soa(hr_x, "hr_x").shape[1]
