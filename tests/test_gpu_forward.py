@@ -449,3 +449,30 @@ def test_kernel_timing_probe_counts_launches(U):
     up.run(LX, LV, hx, hv, sort_every=3)
     ms, k = up.timing_read()
     assert k == 0 and ms == 0.0
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 40001])
+def test_ragged_counts_matrix_core_path(U, n):
+    """Non-rigid steps (sums on the matrix cores) at HR counts that end inside
+    a wave and a quad: plain and taped steps against the oracle on every
+    particle, the taped sums S and M against the oracle's, and the two steps'
+    outputs bit-identical."""
+    sc = build_scene("heap", 3000, 40001, seed=[11, 7])
+    prm = sc.params()
+    X, V = sc.lr_frame(3)
+    rng = np.random.default_rng(n)
+    hr_x = np.ascontiguousarray(sc.hr_x0[:, :n])
+    hr_v = rng.normal(0, 0.5, hr_x.shape).astype(np.float32)
+    up = U.from_scene(sc, max_lr=X.shape[1])
+    X_d, V_d, x_d, v_d = dev(X, torch), dev(V, torch), dev(hr_x, torch), dev(hr_v, torch)
+    x1, v1 = up.step(X_d, V_d, None, x_d, v_d)
+    tape = torch.empty((6, n), dtype=torch.float32, device="cuda")
+    x2, v2 = up.step(X_d, V_d, None, x_d, v_d, tape=tape)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2) and torch.equal(v1, v2)
+    o = O.step(X, V, None, hr_x, hr_v, prm)
+    s = compare_step(host(x1), host(v1), X, V, None, hr_x, hr_v, prm, sc.box_length, oracle_out=o)
+    t = host(tape)
+    np.testing.assert_allclose(t[0], o["S"], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(t[4], o["M"], rtol=1e-5, atol=1e-7)
+    log(f"ragged n={n}: {s}")
