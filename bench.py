@@ -309,7 +309,7 @@ def batched_leg(args, torch, Upsampler, steps=10, warmup=2):
     t0 = time.time()
     scenes = configs.batched(64)
     # kappa per geometry from the autotuner, run on the largest scene of each
-    # geometry over its first ten frames; the persistent kernel has fixed launch
+    # geometry over its first ten frames; the batched kernel has fixed launch
     # knobs, so the tuned kappas are kept only if a short batched trial beats
     # the default kappa (all off the timed path)
     from paper_2308_01629_amd.upsampler import autotune
@@ -407,7 +407,7 @@ def batched_leg(args, torch, Upsampler, steps=10, warmup=2):
             "n_hr_total": b.total_hr, "steps": steps, "batched_ms_per_step": t_b, "plain_ms_per_step": t_p,
             "speedup": t_p / t_b, "batched_hr_updates_per_s": b.total_hr / (t_b / 1e3),
             "plain_hr_updates_per_s": b.total_hr / (t_p / 1e3), "bit_identical": bool(same),
-            "tiles": info["tiles"], "persistent_blocks": info["persistent_blocks"],
+            "tiles": info["tiles"], "grid_blocks": info["grid_blocks"],
             "graphs_captured": info["graphs_captured"], "kappa_autotuned": kappa, "kappa_used": kappa_used}
 
 

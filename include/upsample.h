@@ -366,9 +366,9 @@ int upsample_autotune(const upsample_params* p, const float* lr_x, const float* 
  * max_hr and flags are ignored); its counts are fixed at init.
  *
  * One step rebuilds the grids of all scenes with one counting sort over the
- * cells of every scene and advances all HR particles with one persistent
- * kernel over a table of (scene, 256-particle tile) entries, laid out so that
- * each of the chip's XCDs works through a contiguous range of tiles.  The
+ * cells of every scene and advances all HR particles with one kernel over a
+ * table of (scene, 256-particle tile) entries, one block per entry, laid out
+ * so that each of the chip's XCDs works through a contiguous range of tiles.  The
  * launches are captured into a HIP graph (on an internal stream) once per
  * distinct set of buffer pointers -- the last four sets are kept -- and the
  * graph is replayed on the caller's stream; with UPSAMPLE_BATCH_EAGER they
@@ -400,8 +400,8 @@ int upsample_batch_step(upsample_batch b, const float* lr_x, const float* lr_v, 
                         void* stream);
 int upsample_batch_destroy(upsample_batch b);  /* waits for the device; NULL is a no-op */
 const char* upsample_batch_last_error(upsample_batch b);
-/* out[0] total_lr, out[1] total_hr, out[2] HR tiles, out[3] persistent blocks,
- * out[4] graphs captured so far */
+/* out[0] total_lr, out[1] total_hr, out[2] HR tiles, out[3] blocks of the
+ * step kernel's grid (one per tile), out[4] graphs captured so far */
 int upsample_batch_info(upsample_batch b, int64_t* out);
 
 #ifdef __cplusplus

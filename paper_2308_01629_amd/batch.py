@@ -98,5 +98,5 @@ class Batch:
     def info(self) -> dict:
         out = (ctypes.c_int64 * 5)()
         self._check(self._L.upsample_batch_info(self._b, out))
-        return {"total_lr": out[0], "total_hr": out[1], "tiles": out[2], "persistent_blocks": out[3],
+        return {"total_lr": out[0], "total_hr": out[1], "tiles": out[2], "grid_blocks": out[3],
                 "graphs_captured": out[4]}

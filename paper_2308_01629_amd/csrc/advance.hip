@@ -248,20 +248,31 @@ __device__ __forceinline__ void quad_sums(v4f acc, int lane, float& Ux, float& U
   S = quad_pick<3>(acc, i1, i2, i3);
 }
 
+// One lane's HR state: the particle first + threadIdx.x, or the last particle
+// for idle lanes past n.
+struct HRLane {
+  float x, y, z, vx, vy, vz;
+};
+__device__ __forceinline__ HRLane load_lane(const AdvanceArgs& a, int64_t first) {
+  const int64_t n = a.ld;
+  const int64_t i0 = first + threadIdx.x;
+  const int64_t i = i0 < a.n ? i0 : a.n - 1;
+  return HRLane{a.hx[i], a.hx[n + i], a.hx[2 * n + i], a.hv[i], a.hv[n + i], a.hv[2 * n + i]};
+}
+
 // One block-sized tile of HR particles first .. first + kBlock - 1 (those
 // below a.n are live; the rest shadow the last particle and write nothing).
 // TAPE: also record (S, Ux, Uy, Uz, M, argmax) per particle for the adjoint.
 template <bool RIGID, int G, bool TAPE = false>
 __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* __restrict__ walls,
-                                             GatherLDS<G>& lds, int64_t first) {
+                                             GatherLDS<G>& lds, int64_t first, const HRLane& st) {
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t n = a.ld;
   const int64_t i0 = first + threadIdx.x;
   const bool live = i0 < a.n;
   const int64_t i = live ? i0 : a.n - 1;  // idle lanes shadow the last particle
-  const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
-  const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
+  const float x = st.x, y = st.y, z = st.z;
+  const float vx = st.vx, vy = st.vy, vz = st.vz;
   const GridConst& gc = a.gc;
 
   float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
@@ -400,11 +411,13 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* 
 template <bool RIGID, int G, bool TAPE = false>
 __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
   __shared__ GatherLDS<G> lds;
-  advance_tile<RIGID, G, TAPE>(a, wt.w, lds, (int64_t)blockIdx.x * kBlock);
+  const int64_t first = (int64_t)blockIdx.x * kBlock;
+  advance_tile<RIGID, G, TAPE>(a, wt.w, lds, first, load_lane(a, first));
 }
 
-// Batched step: a persistent grid strides over the (scene, first particle)
-// tile table; each tile reads its scene's constants from the scene table.
+// Batched step: block k takes entries k, k + grid, ... of the (scene, first
+// particle) tile table (one entry when the grid has a block per tile); each
+// tile reads its scene's constants from the scene table.
 template <bool RIGID>
 __global__ __launch_bounds__(kBlock, 5) void k_advance_batched(BatchAdvanceArgs b) {
   __shared__ GatherLDS<1> lds;
@@ -429,7 +442,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_advance_batched(BatchAdvanceArgs 
     a.groups = 1;
     a.tile_max = b.tile_max;
     a.tape = nullptr;
-    advance_tile<RIGID, 1>(a, b.walls + sc.wall_off, lds, (int64_t)tile.first);
+    advance_tile<RIGID, 1>(a, b.walls + sc.wall_off, lds, (int64_t)tile.first, load_lane(a, (int64_t)tile.first));
   }
 }
 
@@ -453,13 +466,6 @@ hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool deb
   else
     hipLaunchKernelGGL((k_advance_tiled<false, 1>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
   return hipGetLastError();
-}
-
-int advance_batched_blocks_per_cu(bool rigid) {
-  int nb = 0;
-  hipError_t e = rigid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advance_batched<true>, kBlock, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_advance_batched<false>, kBlock, 0);
-  return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_advance_batched(const BatchAdvanceArgs& b, int grid, hipStream_t st) {

@@ -124,7 +124,6 @@ struct BatchAdvanceArgs {
   int tile_max;
   int rigid;
 };
-int advance_batched_blocks_per_cu(bool rigid);
 hipError_t launch_advance_batched(const BatchAdvanceArgs& b, int grid, hipStream_t st);
 
 // Batched grid rebuild: one key / count / scan / scatter / stable pass over
