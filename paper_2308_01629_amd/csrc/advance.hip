@@ -415,15 +415,31 @@ __global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTab
   advance_tile<RIGID, G, TAPE>(a, wt.w, lds, first, load_lane(a, first));
 }
 
+// A copy of *p for a wave-uniform p into data that stays unchanged for the
+// whole kernel, read through the constant address space: the compiler then
+// issues scalar loads and keeps the values in scalar registers.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  typedef const __attribute__((address_space(4))) uint32_t* ConstDword;
+  const ConstDword q = (ConstDword)(const void*)p;
+  T out;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) o[k] = q[k];
+  return out;
+}
+
 // Batched step: block k takes entries k, k + grid, ... of the (scene, first
 // particle) tile table (one entry when the grid has a block per tile); each
-// tile reads its scene's constants from the scene table.
+// tile reads its scene's constants from the scene table.  7 blocks per CU:
+// 72 VGPRs without spills (the scene constants are in scalar registers).
 template <bool RIGID>
-__global__ __launch_bounds__(kBlock, 5) void k_advance_batched(BatchAdvanceArgs b) {
+__global__ __launch_bounds__(kBlock, 7) void k_advance_batched(BatchAdvanceArgs b) {
   __shared__ GatherLDS<1> lds;
   for (int64_t t = blockIdx.x; t < b.n_tiles; t += gridDim.x) {
-    const BatchTile tile = b.tiles[t];
-    const BatchScene& sc = b.scenes[tile.scene];
+    const BatchTile tile = load_uniform(b.tiles + t);
+    const BatchScene sc = load_uniform(b.scenes + tile.scene);
     AdvanceArgs a;
     a.gc = sc.gc;
     a.sc = sc.sc;
