@@ -90,11 +90,13 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
   return r;
 }
 
-__device__ __forceinline__ void apply_walls(const float* __restrict__ walls, int n_walls, float r_hr,
+// WP: a pointer to the wall table, generic or in the constant address space.
+template <class WP>
+__device__ __forceinline__ void apply_walls(WP walls, int n_walls, float r_hr,
                                             float ox, float oy, float oz, float& x, float& y, float& z,
                                             float& vx, float& vy, float& vz) {
   for (int k = 0; k < n_walls; ++k) {
-    const float* w = &walls[k * UPSAMPLE_WALL_FLOATS];
+    const auto w = walls + k * UPSAMPLE_WALL_FLOATS;
     const float nx = w[0], ny = w[1], nz = w[2], d = w[3];
     const float pen = fmaf(nz, z, fmaf(ny, y, nx * x)) - d;
     if (pen < r_hr) {  // rare: most particles are clear of most walls
@@ -126,7 +128,8 @@ __device__ __forceinline__ void apply_walls(const float* __restrict__ walls, int
 }
 
 // Shepard average, blend, symplectic Euler and walls for one HR particle.
-__device__ __forceinline__ void finish(const AdvanceArgs& a, const float* __restrict__ walls, int64_t i, float x,
+template <class WP>
+__device__ __forceinline__ void finish(const AdvanceArgs& a, WP walls, int64_t i, float x,
                                       float y, float z, float vx, float vy, float vz, float S,
                                       float Ux, float Uy, float Uz, float M, bool* A_out) {
   // Shepard average and blend parameter (Section 4); empty support -> v~ = 0, alpha = 1.
@@ -263,8 +266,8 @@ __device__ __forceinline__ HRLane load_lane(const AdvanceArgs& a, int64_t first)
 // One block-sized tile of HR particles first .. first + kBlock - 1 (those
 // below a.n are live; the rest shadow the last particle and write nothing).
 // TAPE: also record (S, Ux, Uy, Uz, M, argmax) per particle for the adjoint.
-template <bool RIGID, int G, bool TAPE = false>
-__device__ __forceinline__ void advance_tile(const AdvanceArgs& a, const float* __restrict__ walls,
+template <bool RIGID, int G, bool TAPE = false, class WP>
+__device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
                                              GatherLDS<G>& lds, int64_t first, const HRLane& st) {
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -458,7 +461,9 @@ __global__ __launch_bounds__(kBlock, 7) void k_advance_batched(BatchAdvanceArgs 
     a.groups = 1;
     a.tile_max = b.tile_max;
     a.tape = nullptr;
-    advance_tile<RIGID, 1>(a, b.walls + sc.wall_off, lds, (int64_t)tile.first, load_lane(a, (int64_t)tile.first));
+    typedef const __attribute__((address_space(4))) float* ConstFloat;  // scalar loads of the scene's walls
+    advance_tile<RIGID, 1>(a, (ConstFloat)(const void*)(b.walls + sc.wall_off), lds, (int64_t)tile.first,
+                           load_lane(a, (int64_t)tile.first));
   }
 }
 
