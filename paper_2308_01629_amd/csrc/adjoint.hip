@@ -477,15 +477,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
     float* const dst1 = lr_grad(ca1);
     float* const dst2 = lr_grad(ca2);
     auto pair_pass = [&](uint32_t nc, const float4* lp, const float4* lv) {
-      // two candidates per iteration; the next pair is read ahead
-      float4 QA = lp[0], WA = lv[0];
-      float4 QB = lp[nc > 1 ? 1 : 0], WB = lv[nc > 1 ? 1 : 0];
+      // two candidates per iteration (no read-ahead: its register rotation
+      // cost 6 VALU per candidate and held the kernel at 88 VGPRs)
       for (uint32_t c = 0; c < nc; c += 2) {
         const bool has_b = c + 1 < nc;
-        const uint32_t cn = c + 2 < nc ? c + 2 : c;
-        const uint32_t cn1 = cn + 1 < nc ? cn + 1 : cn;
-        const float4 QA2 = lp[cn], WA2 = lv[cn];
-        const float4 QB2 = lp[cn1], WB2 = lv[cn1];
+        const uint32_t cb = has_b ? c + 1 : c;
+        const float4 QA = lp[c], WA = lv[c];
+        const float4 QB = lp[cb], WB = lv[cb];
         const Six va = pair_contrib(QA, WA, x, y, z, inv_h2, k2, arg, bk);
         Six vb;
         if (has_b) {
@@ -511,7 +509,6 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
             unsafeAtomicAdd(dst2 + ib, r2);
           }
         }
-        QA = QA2; WA = WA2; QB = QB2; WB = WB2;
       }
     };
     if (block_acc) {
