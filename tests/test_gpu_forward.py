@@ -476,3 +476,22 @@ def test_ragged_counts_matrix_core_path(U, n):
     np.testing.assert_allclose(t[0], o["S"], rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(t[4], o["M"], rtol=1e-5, atol=1e-7)
     log(f"ragged n={n}: {s}")
+
+
+def test_sort_hr_key_table_follows_tuning(U):
+    """One handle, the reorder key switched between sorts: each reorder is
+    ordered by the key of the tuning in force (the per-fine-cell key table is
+    rebuilt when the tuning changes)."""
+    sc = configs.drain(scale=1 / 64)
+    up = U.from_scene(sc)
+    spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
+    shuffle = np.random.default_rng(21).permutation(sc.n_hr)
+    hx = dev(sc.hr_x0[:, shuffle].copy(), torch)
+    hv = dev(np.random.default_rng(22).normal(size=sc.hr_x0.shape).astype(np.float32), torch)
+    for sub, mode in ((2, 2), (1, 0), (2, 1), (1, 2), (2, 2)):
+        up.set_tuning(sort_sub=sub, sort_mode=mode)
+        ox, ov = torch.empty_like(hx), torch.empty_like(hv)
+        perm = up.sort_hr(hx, hv, out_x=ox, out_v=ov).long()
+        torch.cuda.synchronize()
+        assert torch.equal(ox, hx[:, perm]) and torch.equal(ov, hv[:, perm]), (sub, mode)
+        assert np.all(np.diff(morton_sort_keys(host(ox), spec, sub, mode)) >= 0), (sub, mode)
