@@ -221,6 +221,12 @@ __device__ __forceinline__ v4f mfma_entry(float w, float b, v4f acc) {
   return __builtin_amdgcn_mfma_f32_4x4x1f32(w, b, acc, 0, 0, 0);
 }
 
+// max(u, 0)^3 for u <= 1 (the kernel's argument never exceeds 1 but by
+// rounding): (u u) u clamped to [0, 1], the clamp folded into the multiply.
+__device__ __forceinline__ float cube01(float u) {
+  return __builtin_amdgcn_fmed3f((u * u) * u, 0.0f, 1.0f);
+}
+
 // Value of v at lane n of each quad (DPP quad_perm [n, n, n, n]; every lane
 // has a valid source).
 template <int N>
@@ -331,14 +337,19 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
         using Stage = std::conditional_t<TAPE, DotStage, WithOnes<DotStage>>;
         tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
           const float* lvf = reinterpret_cast<const float*>(lv);
-          for (uint32_t c0 = 0; c0 < nc; c0 += 4) {
+          auto step = [&](uint32_t c) {
+            const float4 Q = lp[c];
+            take(cube01(fmaf(Q.x, Px, fmaf(Q.y, Py, fmaf(Q.z, Pz, A + Q.w)))), lvf, c);
+          };
+          // eight entries per trip (one address update), then a last four
+          uint32_t c0 = 0;
+          for (; c0 + 8u <= nc; c0 += 8u) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const uint32_t c = c0 + (uint32_t)k;
-              const float4 Q = lp[c];
-              const float u = fmaxf(fmaf(Q.x, Px, fmaf(Q.y, Py, fmaf(Q.z, Pz, A + Q.w))), 0.0f);
-              take(u * u * u, lvf, c);
-            }
+            for (int k = 0; k < 8; ++k) step(c0 + (uint32_t)k);
+          }
+          if (c0 < nc) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) step(c0 + (uint32_t)k);
           }
         }, SortedTag(), Stage{ds});
       } else {
@@ -352,8 +363,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
               const float4 Q = lp[c];
               const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
               const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-              const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
-              take(u * u * u, lvf, c);
+              take(cube01(fmaf(-sq, inv_h2, 1.0f)), lvf, c);
             }
           }
         }, SortedTag(), Stage{});
@@ -412,7 +422,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
 }
 
 template <bool RIGID, int G, bool TAPE = false>
-__global__ __launch_bounds__(kBlock) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
+__global__ __launch_bounds__(kBlock, 7) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
   __shared__ GatherLDS<G> lds;
   const int64_t first = (int64_t)blockIdx.x * kBlock;
   advance_tile<RIGID, G, TAPE>(a, wt.w, lds, first, load_lane(a, first));

@@ -269,6 +269,10 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
     const uint32_t j = lds.rb[wid][lo] + (kk - lds.rp[wid][lo]);
     const float4 P = lr[j].p;
     const float4 V = lr[j].v;
+    // V is stored only by lanes that keep their candidate; taking it here
+    // stops the compiler from sinking its load behind the cull, so both
+    // loads of the round share one round trip
+    asm volatile("" ::"v"(V.x), "v"(V.y), "v"(V.z), "v"(V.w));
     const uint32_t bits = tag(lo, kk, j, P.w);
     bool keep[G];
 #pragma unroll
