@@ -293,6 +293,10 @@ int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* 
  * LR gradients, 0 one particle per lane with per-pair atomics (scenes with
  * rigid LR particles always use the latter).  tile_max / adjoint_tile_max: a
  * wave whose stencil rows hold more LR candidates than this walks per lane.
+ * wall_cull: 1 (default) lets a wave of the step kernel skip the walls whose
+ * planes lie farther than r_hr from the neighbourhood of the cells its
+ * particles occupy (a per-cell table built at init for grids of up to 2^22
+ * cells); 0 tests every wall for every particle.  Results are the same.
  */
 typedef struct {
   int32_t gather_groups;
@@ -301,6 +305,7 @@ typedef struct {
   int32_t sort_mode;
   int32_t tile_max;
   int32_t adjoint_tile_max;
+  int32_t wall_cull;
 } upsample_tuning;
 int upsample_set_tuning(upsample_handle h, const upsample_tuning* t);
 int upsample_get_tuning(upsample_handle h, upsample_tuning* t);

@@ -61,7 +61,8 @@ class GridInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("gather_groups", ctypes.c_int32), ("sort_sub", ctypes.c_int32),
                 ("adjoint_tiled", ctypes.c_int32), ("sort_mode", ctypes.c_int32),
-                ("tile_max", ctypes.c_int32), ("adjoint_tile_max", ctypes.c_int32)]
+                ("tile_max", ctypes.c_int32), ("adjoint_tile_max", ctypes.c_int32),
+                ("wall_cull", ctypes.c_int32)]
 
 
 class AutotuneResult(ctypes.Structure):

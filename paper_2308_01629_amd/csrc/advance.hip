@@ -90,13 +90,34 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
   return r;
 }
 
+// A copy of *p for a wave-uniform p into data that stays unchanged for the
+// whole kernel, read through the constant address space: the compiler then
+// issues scalar loads and keeps the values in scalar registers.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  typedef const __attribute__((address_space(4))) uint32_t* ConstDword;
+  const ConstDword q = (ConstDword)(const void*)p;
+  T out;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) o[k] = q[k];
+  return out;
+}
+
 // WP: a pointer to the wall table, generic or in the constant address space.
+// need: the walls the wave tests (bit k: wall k); a wall whose bit is clear
+// has its plane at least r_hr from every lane's position, so its test would
+// fail for all of them.  A push moves a particle off the position those bits
+// were cleared for, so after one every later wall is tested.
 template <class WP>
-__device__ __forceinline__ void apply_walls(WP walls, int n_walls, float r_hr,
+__device__ __forceinline__ void apply_walls(WP walls, int n_walls, uint32_t need, float r_hr,
                                             float ox, float oy, float oz, float& x, float& y, float& z,
                                             float& vx, float& vy, float& vz) {
   for (int k = 0; k < n_walls; ++k) {
+    if (((need >> k) & 1u) == 0u) continue;
     const auto w = walls + k * UPSAMPLE_WALL_FLOATS;
+    bool pushed = false;
     const float nx = w[0], ny = w[1], nz = w[2], d = w[3];
     const float pen = fmaf(nz, z, fmaf(ny, y, nx * x)) - d;
     if (pen < r_hr) {  // rare: most particles are clear of most walls
@@ -122,16 +143,54 @@ __device__ __forceinline__ void apply_walls(WP walls, int n_walls, float r_hr,
           vy = fmaf(-vn, ny, vy);
           vz = fmaf(-vn, nz, vz);
         }
+        pushed = true;
       }
     }
+    if (need != ~0u && __ballot(pushed) != 0ull) need = ~0u;
   }
+}
+
+// The walls a wave tests: those flagged in the mask of cell c (uniform
+// values), valid for particles inside that cell's neighbourhood; mask ~0
+// when there is no mask table or the wave's box is too wide.  The region's
+// bounds are formed only where they are used, so that nothing but scalar
+// registers is held across the candidate walk.
+struct WallCull {
+  uint32_t mask;
+  int c[3];
+};
+__device__ __forceinline__ WallCull all_walls() { return WallCull{~0u, {0, 0, 0}}; }
+
+// Cull for a wave whose box corners lie in cells (x0, y0, z0) .. (x1, y1, z1)
+// (uniform values): the mask table covers the neighbourhood of reach + 1
+// cells around each cell, so for a box of at most two cells per axis the
+// mask of its first cell serves (one scalar load), with the region running
+// reach + 1 cells beyond that cell on each side.
+__device__ __forceinline__ WallCull wall_cull(const GridConst& gc, const uint32_t* __restrict__ wall_mask,
+                                              int x0, int x1, int y0, int y1, int z0, int z1) {
+  WallCull wc = all_walls();
+  if (wall_mask == nullptr) return wc;
+  x0 = __builtin_amdgcn_readfirstlane(x0);
+  x1 = __builtin_amdgcn_readfirstlane(x1);
+  y0 = __builtin_amdgcn_readfirstlane(y0);
+  y1 = __builtin_amdgcn_readfirstlane(y1);
+  z0 = __builtin_amdgcn_readfirstlane(z0);
+  z1 = __builtin_amdgcn_readfirstlane(z1);
+  if (x1 - x0 > 1 || y1 - y0 > 1 || z1 - z0 > 1) return wc;
+  const uint32_t sy = (uint32_t)gc.dims[0], sz = sy * (uint32_t)gc.dims[1];
+  wc.mask = load_uniform(wall_mask + ((uint32_t)x0 + sy * (uint32_t)y0 + sz * (uint32_t)z0));
+  wc.c[0] = x0;
+  wc.c[1] = y0;
+  wc.c[2] = z0;
+  return wc;
 }
 
 // Shepard average, blend, symplectic Euler and walls for one HR particle.
 template <class WP>
 __device__ __forceinline__ void finish(const AdvanceArgs& a, WP walls, int64_t i, float x,
                                       float y, float z, float vx, float vy, float vz, float S,
-                                      float Ux, float Uy, float Uz, float M, bool* A_out) {
+                                      float Ux, float Uy, float Uz, float M, bool* A_out,
+                                      const WallCull& wc = all_walls()) {
   // Shepard average and blend parameter (Section 4); empty support -> v~ = 0, alpha = 1.
   float tx = 0.f, ty = 0.f, tz = 0.f;
   bool A = true;
@@ -147,7 +206,21 @@ __device__ __forceinline__ void finish(const AdvanceArgs& a, WP walls, int64_t i
   const float fx = fmaf(dt, a.sc.g[0], vx), fy = fmaf(dt, a.sc.g[1], vy), fz = fmaf(dt, a.sc.g[2], vz);
   float nvx = fmaf(alpha, fx - tx, tx), nvy = fmaf(alpha, fy - ty, ty), nvz = fmaf(alpha, fz - tz, tz);
   float nx = fmaf(dt, nvx, x), ny = fmaf(dt, nvy, y), nz = fmaf(dt, nvz, z);
-  apply_walls(walls, a.sc.n_walls, a.sc.r_hr, x, y, z, nx, ny, nz, nvx, nvy, nvz);
+  uint32_t need = ~0u;
+  if (wc.mask != ~0u) {
+    // the culled set holds if every (live) lane's new position lies in the
+    // neighbourhood of cells c - reach - 1 .. c + reach + 1
+    const GridConst& gc = a.gc;
+    const int M = gc.reach + 1;
+    const bool in = nx >= fmaf((float)(wc.c[0] - M), gc.cs, gc.lo[0]) &&
+                    nx <= fmaf((float)(wc.c[0] + M + 1), gc.cs, gc.lo[0]) &&
+                    ny >= fmaf((float)(wc.c[1] - M), gc.cs, gc.lo[1]) &&
+                    ny <= fmaf((float)(wc.c[1] + M + 1), gc.cs, gc.lo[1]) &&
+                    nz >= fmaf((float)(wc.c[2] - M), gc.cs, gc.lo[2]) &&
+                    nz <= fmaf((float)(wc.c[2] + M + 1), gc.cs, gc.lo[2]);
+    if (__ballot(!in) == 0ull) need = wc.mask;
+  }
+  apply_walls(walls, a.sc.n_walls, need, a.sc.r_hr, x, y, z, nx, ny, nz, nvx, nvy, nvz);
   const int64_t n = a.ld;
   a.hx_out[i] = nx;
   a.hx_out[n + i] = ny;
@@ -289,6 +362,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
   // TAPE: (weight bits << 32 | ~index) -- its unsigned maximum is the largest
   // weight and, among equal weights, the smallest index
   uint64_t key = 0ull;
+  WallCull wc = all_walls();
   const TileSetup<G> ts = tile_setup<G>(gc, a.cell_start, x, y, z, lane, wid, lds);
   if (ts.nrows > lds.kRows || ts.total > (uint32_t)a.tile_max) {
     // spread-out wave: every lane walks its own stencil
@@ -306,6 +380,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
       hi0 = fmaxf(hi0, ts.gb[g].hi[0]); hi1 = fmaxf(hi1, ts.gb[g].hi[1]); hi2 = fmaxf(hi2, ts.gb[g].hi[2]);
     }
     const float ext = fmaxf(hi0 - lo0, fmaxf(hi1 - lo1, hi2 - lo2));
+    wc = wall_cull(gc, a.wall_mask, ts.bx0, ts.bx1, ts.by0, ts.by1, ts.bz0, ts.bz1);
     if (!RIGID) {
       // weights in the vector unit, sums on the matrix cores
       v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -408,7 +483,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
   }
   if (live) {
     bool A;
-    finish(a, walls, i, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, &A);
+    finish(a, walls, i, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, &A, wc);
     if (TAPE) {
       const int64_t m = a.n;
       a.tape[i] = S;
@@ -426,21 +501,6 @@ __global__ __launch_bounds__(kBlock, 7) void k_advance_tiled(AdvanceArgs a, Wall
   __shared__ GatherLDS<G> lds;
   const int64_t first = (int64_t)blockIdx.x * kBlock;
   advance_tile<RIGID, G, TAPE>(a, wt.w, lds, first, load_lane(a, first));
-}
-
-// A copy of *p for a wave-uniform p into data that stays unchanged for the
-// whole kernel, read through the constant address space: the compiler then
-// issues scalar loads and keeps the values in scalar registers.
-template <class T>
-__device__ __forceinline__ T load_uniform(const T* p) {
-  static_assert(sizeof(T) % 4 == 0, "whole dwords");
-  typedef const __attribute__((address_space(4))) uint32_t* ConstDword;
-  const ConstDword q = (ConstDword)(const void*)p;
-  T out;
-  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
-#pragma unroll
-  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) o[k] = q[k];
-  return out;
 }
 
 // Batched step: block k takes entries k, k + grid, ... of the (scene, first
@@ -468,6 +528,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_advance_batched(BatchAdvanceArgs 
     a.dbg_ids = nullptr;
     a.dbg_max_k = 0;
     a.dbg_branch = nullptr;
+    a.wall_mask = nullptr;
     a.groups = 1;
     a.tile_max = b.tile_max;
     a.tape = nullptr;

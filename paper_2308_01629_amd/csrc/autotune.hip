@@ -84,6 +84,7 @@ bool cache_lookup(const char* path, const std::string& key, upsample_autotune_re
       r->tuning.tile_max = (int32_t)tm;
       r->tuning.adjoint_tile_max = (int32_t)am;
       r->tuning.adjoint_tiled = 1;
+      r->tuning.wall_cull = 1;
       r->advance_ms = (float)ms;
       found = true;  // the last matching line wins
     }

@@ -161,6 +161,7 @@ int upsample_batch_init(const upsample_scene* scenes, int32_t n_scenes, uint32_t
       b.sc.g[a] = d.params.g[a];
     }
     b.gc.inv_cs = gi.inv_cell_size;
+    b.gc.cs = (float)gi.cell_size;
     b.gc.reach = gi.reach;
     b.gc.h2 = gi.h2;
     b.gc.inv_h2 = gi.inv_h2;

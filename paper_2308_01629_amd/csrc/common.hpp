@@ -22,6 +22,7 @@ struct GridConst {
   float lo[3];
   float inv_cs;
   int dims[3];
+  float cs;       // fl32(cell size): bounds of cell boxes
   int reach;
   float h2;       // fl32(9 r^2): membership threshold
   float inv_h2;   // fl32(1 / (9 r^2)): weight scale

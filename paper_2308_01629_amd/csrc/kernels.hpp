@@ -87,6 +87,10 @@ struct AdvanceArgs {
   uint32_t* dbg_ids;
   int64_t dbg_max_k;
   uint8_t* dbg_branch;
+  // [n_cells] per cell, bit k set when wall k can come within r_hr of the
+  // cell's neighbourhood (cells c - reach - 1 .. c + reach + 1); null: every
+  // wave tests every wall
+  const uint32_t* wall_mask;
   int groups;    // lane groups per wave in the tiled gather: 1, 2 or 4 (a tuning knob)
   int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
   float* tape;   // [6][n] (S, Ux, Uy, Uz, M, argmax bits) or null

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -13,6 +14,7 @@ using namespace ups;
 
 static constexpr int kTimingRing = 256;
 static constexpr int kRunBatch = 4;  // frames per grid-build batch of upsample_run
+static constexpr int64_t kWallMaskMaxCells = (int64_t)1 << 22;  // larger grids test every wall
 
 struct upsample_handle_s {
   upsample_params p;
@@ -33,6 +35,7 @@ struct upsample_handle_s {
   hipEvent_t built[2], consumed[2], entry;
   int32_t* run_perm;
   uint32_t* finite_flag;
+  uint32_t* wall_mask;  // [n_cells] walls near each cell's neighbourhood, or null
   bool grid_valid;
   bool counts_dirty;     // an interrupted build may have left counts non-zero
   bool hr_counts_dirty;  // same for the HR sort bins
@@ -151,7 +154,7 @@ void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
                   h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.src, h->hs.x,
                   h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum,
-                  h->finite_flag, h->run_perm};
+                  h->finite_flag, h->run_perm, h->wall_mask};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
   for (const GridScratch& g : h->run_g) {
@@ -169,6 +172,46 @@ void free_scratch(upsample_handle h) {
   }
 }
 
+// Per grid cell, bit k set when wall k's plane can come within r_hr of the
+// cell's neighbourhood, the box of cells c - reach - 1 .. c + reach + 1 on
+// each axis (not clamped to the grid): the minimum of n . p - d over the box,
+// in double, against r_hr plus a margin far above the float32 rounding of the
+// kernel's wall test and of its region bounds.  A particle inside the box
+// cannot meet a wall whose bit is clear.
+std::vector<uint32_t> wall_masks(const upsample_handle h) {
+  const upsample_grid_info& gi = h->gi;
+  const double cs = gi.cell_size;
+  const int M = gi.reach + 1;  // neighbourhood radius in cells
+  double scale = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    scale = std::fmax(scale, std::fabs((double)gi.lo[a]) + (double)(gi.dims[a] + M + 1) * cs);
+  }
+  double dmax = 0.0;
+  for (int k = 0; k < h->p.n_walls; ++k) dmax = std::fmax(dmax, std::fabs((double)h->walls[k * UPSAMPLE_WALL_FLOATS + 3]));
+  const double eps = 1e-5 * (1.0 + scale + dmax);
+  const double half = (2 * M + 1) * cs * 0.5;  // half-width of a neighbourhood box
+  std::vector<uint32_t> m((size_t)gi.n_cells, 0u);
+  for (int k = 0; k < h->p.n_walls; ++k) {
+    const float* w = h->walls + k * UPSAMPLE_WALL_FLOATS;
+    const double n0 = w[0], n1 = w[1], n2 = w[2], d = w[3];
+    const double spread = (std::fabs(n0) + std::fabs(n1) + std::fabs(n2)) * half;
+    const double limit = (double)h->p.r_hr + eps;
+    const uint32_t bit = 1u << k;
+    size_t c = 0;
+    for (int z = 0; z < gi.dims[2]; ++z) {
+      const double pz = n2 * ((double)gi.lo[2] + (z + 0.5) * cs);
+      for (int y = 0; y < gi.dims[1]; ++y) {
+        const double pyz = pz + n1 * ((double)gi.lo[1] + (y + 0.5) * cs);
+        for (int x = 0; x < gi.dims[0]; ++x, ++c) {
+          const double centre = pyz + n0 * ((double)gi.lo[0] + (x + 0.5) * cs) - d;
+          if (centre - spread < limit) m[c] |= bit;
+        }
+      }
+    }
+  }
+  return m;
+}
+
 GridConst grid_const(const upsample_handle h) {
   GridConst gc;
   for (int a = 0; a < 3; ++a) {
@@ -176,6 +219,7 @@ GridConst grid_const(const upsample_handle h) {
     gc.dims[a] = h->gi.dims[a];
   }
   gc.inv_cs = h->gi.inv_cell_size;
+  gc.cs = (float)h->gi.cell_size;
   gc.reach = h->gi.reach;
   gc.h2 = h->gi.h2;
   gc.inv_h2 = h->gi.inv_h2;
@@ -303,6 +347,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   h->tune.adjoint_tiled = 1;
   h->tune.tile_max = 512;
   h->tune.adjoint_tile_max = 384;
+  h->tune.wall_cull = 1;
   h->n_cells = h->gi.n_cells;
   h->n_chunks = (int)((h->n_cells + kScanChunk - 1) / kScanChunk);
   if (hipGetDevice(&h->device) != hipSuccess) {
@@ -355,7 +400,13 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->hs.local, n_bins)
   ALLOC(h->hs.chunk_sum, n_bins / kScanChunk + 2)
   ALLOC(h->finite_flag, 1)
+  const bool cull_walls = p->n_walls > 0 && h->n_cells <= kWallMaskMaxCells;
+  if (cull_walls) ALLOC(h->wall_mask, h->n_cells)
 #undef ALLOC
+  if (e == hipSuccess && cull_walls) {
+    const std::vector<uint32_t> m = wall_masks(h);
+    e = hipMemcpy(h->wall_mask, m.data(), sizeof(uint32_t) * m.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMemset(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells);
   if (e == hipSuccess) e = hipMemset(h->hs.counts, 0, sizeof(uint32_t) * (size_t)n_bins);
   for (int k = 0; k < 2 * kTimingRing && e == hipSuccess; ++k) e = hipEventCreate(&h->ev[k]);
@@ -492,6 +543,7 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
   a.dbg_ids = ids;
   a.dbg_max_k = max_k;
   a.dbg_branch = branch;
+  a.wall_mask = h->tune.wall_cull != 0 ? h->wall_mask : nullptr;
   a.groups = h->tune.gather_groups;
   a.tile_max = h->tune.tile_max;
   a.tape = tape;
@@ -864,6 +916,8 @@ int upsample_set_tuning(upsample_handle h, const upsample_tuning* t) {
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "tile_max must be >= 0");
   if (t->adjoint_tiled != 0 && t->adjoint_tiled != 1)
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "adjoint_tiled must be 0 or 1");
+  if (t->wall_cull != 0 && t->wall_cull != 1)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "wall_cull must be 0 or 1");
   if (t->sort_sub > h->hs.max_sub ||
       (h->p.max_hr > 0 && h->hs.max_sub > 0 && sort_bins(h->gi.dims, t->sort_sub, t->sort_mode) > h->hs.n_bins))
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_sub / sort_mode exceed the bins allocated for this grid");

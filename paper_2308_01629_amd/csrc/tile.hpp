@@ -128,6 +128,7 @@ struct TileSetup {
   int nrows;       // > the LDS row capacity: the wave is too spread out for a shared list
   uint32_t total;  // candidates streamed (sum of row lengths)
   int X0, Y0, Z0, ny;  // first cell of the rows; rows run y-fastest
+  int bx0, bx1, by0, by1, bz0, bz1;  // cells of the wave box's corners
   uint32_t my_start, my_len;  // row `lane` (rows <= 64): first streamed index and length
 };
 
@@ -159,12 +160,15 @@ __device__ __forceinline__ TileSetup<G> tile_setup(const GridConst& gc,
   // Cell coordinates are monotone in position: the cells of the wave box
   // corners bound every lane's cell, so these rows hold every lane's stencil.
   const int R = gc.reach;
-  const int X0 = max(cell_coord(unord(w0x), gc.lo[0], gc.inv_cs, gc.dims[0]) - R, 0);
-  const int X1 = min(cell_coord(unord(w1x), gc.lo[0], gc.inv_cs, gc.dims[0]) + R, gc.dims[0] - 1);
-  const int Y0 = max(cell_coord(unord(w0y), gc.lo[1], gc.inv_cs, gc.dims[1]) - R, 0);
-  const int Y1 = min(cell_coord(unord(w1y), gc.lo[1], gc.inv_cs, gc.dims[1]) + R, gc.dims[1] - 1);
-  const int Z0 = max(cell_coord(unord(w0z), gc.lo[2], gc.inv_cs, gc.dims[2]) - R, 0);
-  const int Z1 = min(cell_coord(unord(w1z), gc.lo[2], gc.inv_cs, gc.dims[2]) + R, gc.dims[2] - 1);
+  ts.bx0 = cell_coord(unord(w0x), gc.lo[0], gc.inv_cs, gc.dims[0]);
+  ts.bx1 = cell_coord(unord(w1x), gc.lo[0], gc.inv_cs, gc.dims[0]);
+  ts.by0 = cell_coord(unord(w0y), gc.lo[1], gc.inv_cs, gc.dims[1]);
+  ts.by1 = cell_coord(unord(w1y), gc.lo[1], gc.inv_cs, gc.dims[1]);
+  ts.bz0 = cell_coord(unord(w0z), gc.lo[2], gc.inv_cs, gc.dims[2]);
+  ts.bz1 = cell_coord(unord(w1z), gc.lo[2], gc.inv_cs, gc.dims[2]);
+  const int X0 = max(ts.bx0 - R, 0), X1 = min(ts.bx1 + R, gc.dims[0] - 1);
+  const int Y0 = max(ts.by0 - R, 0), Y1 = min(ts.by1 + R, gc.dims[1] - 1);
+  const int Z0 = max(ts.bz0 - R, 0), Z1 = min(ts.bz1 + R, gc.dims[2] - 1);
   const int ny = Y1 - Y0 + 1;
   ts.nrows = ny * (Z1 - Z0 + 1);
   ts.total = 0u;

@@ -291,7 +291,8 @@ class Upsampler:
         return count, ids, branch
 
     # -- launch-shape knobs
-    TUNING_KEYS = ("gather_groups", "sort_sub", "adjoint_tiled", "sort_mode", "tile_max", "adjoint_tile_max")
+    TUNING_KEYS = ("gather_groups", "sort_sub", "adjoint_tiled", "sort_mode", "tile_max", "adjoint_tile_max",
+                   "wall_cull")
 
     def set_tuning(self, **kw) -> None:
         """Set launch-shape knobs (upsample_tuning); unnamed knobs keep their value."""

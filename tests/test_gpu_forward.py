@@ -495,3 +495,35 @@ def test_sort_hr_key_table_follows_tuning(U):
         torch.cuda.synchronize()
         assert torch.equal(ox, hx[:, perm]) and torch.equal(ov, hv[:, perm]), (sub, mode)
         assert np.all(np.diff(morton_sort_keys(host(ox), spec, sub, mode)) >= 0), (sub, mode)
+
+
+@pytest.mark.parametrize("speed", [0.0, 6.0])
+def test_wall_cull_is_exact(U, speed):
+    # A wave skips the walls whose planes lie farther than r_hr from the
+    # neighbourhood of its cells, when every new position stays inside it;
+    # the step must equal the one that tests every wall, bit for bit.  At 6 m/s
+    # particles move about three cells in a step: many leave the region (all
+    # walls tested) and many are pushed (every later wall tested).
+    sc = configs.drain(scale=1 / 16)
+    X, V = sc.lr_frame(3)
+    up = U.from_scene(sc)
+    assert up.get_tuning()["wall_cull"] == 1
+    rng = np.random.default_rng(9)
+    v0 = (sc.hr_v0 + speed * rng.normal(size=sc.hr_v0.shape)).astype(np.float32)
+    hx, hv = dev(sc.hr_x0, torch), dev(v0, torch)
+    up.sort_hr(hx, hv, with_perm=False)
+    out = []
+    for cull in (1, 0):
+        up.set_tuning(wall_cull=cull)
+        out.append(up.step(dev(X, torch), dev(V, torch), None, hx, hv))
+    torch.cuda.synchronize()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    # the walls did act: pushed particles end exactly r_hr from a plane
+    x = host(out[0][0]).astype(np.float64)
+    W = sc.walls.astype(np.float64)
+    pen = W[:, :3] @ x - W[:, 3:4]
+    pushed = int(np.sum(np.any(np.abs(pen - sc.r_hr) < 1e-6, axis=0)))
+    log(f"wall cull speed={speed}: {pushed} particles at a wall")
+    assert pushed > 0 or speed == 0.0
+    with pytest.raises(Exception):
+        up.set_tuning(wall_cull=2)
