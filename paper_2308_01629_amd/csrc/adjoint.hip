@@ -291,7 +291,8 @@ __device__ __forceinline__ Six pair_contrib(float4 Q, float4 W, float x, float y
   const uint32_t id = __float_as_uint(W.w);
   const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
   const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-  const float t = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
+  // 1 - sq / h^2 <= 1, so the [0, 1] clamp (folded into the fma) is max(., 0)
+  const float t = __builtin_amdgcn_fmed3f(fmaf(-sq, inv_h2, 1.0f), 0.0f, 1.0f);
   const float t2 = t * t;
   const float w = t2 * t;
   const float gw = fmaf(bk.gUz, W.z, fmaf(bk.gUy, W.y, bk.gUx * W.x)) + bk.gS + (id == arg ? bk.gM : 0.0f);
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
           const float4 W = lv[c];
           const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
           const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-          const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
+          const float u = __builtin_amdgcn_fmed3f(fmaf(-sq, inv_h2, 1.0f), 0.0f, 1.0f);
           const float w = u * u * u;
           const uint32_t id = __float_as_uint(W.w);
           S += w;
