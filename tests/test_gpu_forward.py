@@ -527,3 +527,44 @@ def test_wall_cull_is_exact(U, speed):
     assert pushed > 0 or speed == 0.0
     with pytest.raises(Exception):
         up.set_tuning(wall_cull=2)
+
+
+def test_wall_cull_is_exact_with_32_walls(U):
+    # The six box walls plus 26 planes through the box (clipped and not, one
+    # with a hole), so that every bit of the per-cell masks is in use and
+    # fast particles meet several walls in one step: culled and unculled
+    # steps must agree bit for bit.
+    from workloads.generators import wall
+    sc = configs.plain()
+    X, V = sc.lr_frame(1)
+    rng = np.random.default_rng(31)
+    lo, hi = np.asarray(sc.domain_lo, np.float64), np.asarray(sc.domain_hi, np.float64)
+    walls = [np.asarray(w, np.float32) for w in sc.walls]
+    while len(walls) < 32:
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        p = lo + (hi - lo) * rng.uniform(0.2, 0.8, size=3)
+        k = len(walls)
+        if k % 3 == 0:
+            walls.append(wall(n, float(n @ p), a=(0.0, 1.0, 0.0), b=float(p[1])))
+        elif k == 31:
+            walls.append(wall(n, float(n @ p), o=tuple(p), R=0.1))
+        else:
+            walls.append(wall(n, float(n @ p)))
+    walls = np.stack(walls)
+    up = U(sc.r_lr, sc.r_hr, sc.dt, sc.g, sc.domain_lo, sc.domain_hi, walls=walls,
+           max_lr=X.shape[1], max_hr=sc.n_hr)
+    v0 = (3.0 * rng.normal(size=sc.hr_x0.shape)).astype(np.float32)
+    hx, hv = dev(sc.hr_x0, torch), dev(v0, torch)
+    up.sort_hr(hx, hv, with_perm=False)
+    out = []
+    for cull in (1, 0):
+        up.set_tuning(wall_cull=cull)
+        out.append(up.step(dev(X, torch), dev(V, torch), None, hx, hv))
+    torch.cuda.synchronize()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    x = host(out[0][0]).astype(np.float64)
+    W = walls.astype(np.float64)
+    at = np.abs(W[:, :3] @ x - W[:, 3:4] - sc.r_hr) < 1e-6
+    log(f"32 walls: {int(at.any(0).sum())} particles at a wall, {int(at.any(1).sum())} walls met")
+    assert at[6:].any(1).sum() >= 4  # several of the inner planes pushed particles
