@@ -90,6 +90,16 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
   return r;
 }
 
+// Element o of the array at p, addressed as a base pointer (uniform across
+// the wave, so in scalar registers) plus a 32-bit lane offset, instead of a
+// 64-bit address per lane.
+__device__ __forceinline__ const float* col(const float* p, uint32_t o) {
+  return reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + (uint32_t)(o * 4u));
+}
+__device__ __forceinline__ float* col(float* p, uint32_t o) {
+  return reinterpret_cast<float*>(reinterpret_cast<char*>(p) + (uint32_t)(o * 4u));
+}
+
 // A copy of *p for a wave-uniform p into data that stays unchanged for the
 // whole kernel, read through the constant address space: the compiler then
 // issues scalar loads and keeps the values in scalar registers.
@@ -185,9 +195,10 @@ __device__ __forceinline__ WallCull wall_cull(const GridConst& gc, const uint32_
   return wc;
 }
 
-// Shepard average, blend, symplectic Euler and walls for one HR particle.
+// Shepard average, blend, symplectic Euler and walls for one HR particle, the
+// particle first + o (first uniform).
 template <class WP>
-__device__ __forceinline__ void finish(const AdvanceArgs& a, WP walls, int64_t i, float x,
+__device__ __forceinline__ void finish(const AdvanceArgs& a, WP walls, int64_t first, uint32_t o, float x,
                                       float y, float z, float vx, float vy, float vz, float S,
                                       float Ux, float Uy, float Uz, float M, bool* A_out,
                                       const WallCull& wc = all_walls()) {
@@ -222,12 +233,14 @@ __device__ __forceinline__ void finish(const AdvanceArgs& a, WP walls, int64_t i
   }
   apply_walls(walls, a.sc.n_walls, need, a.sc.r_hr, x, y, z, nx, ny, nz, nvx, nvy, nvz);
   const int64_t n = a.ld;
-  a.hx_out[i] = nx;
-  a.hx_out[n + i] = ny;
-  a.hx_out[2 * n + i] = nz;
-  a.hv_out[i] = nvx;
-  a.hv_out[n + i] = nvy;
-  a.hv_out[2 * n + i] = nvz;
+  float* const px = a.hx_out + first;
+  float* const pv = a.hv_out + first;
+  *col(px, o) = nx;
+  *col(px + n, o) = ny;
+  *col(px + 2 * n, o) = nz;
+  *col(pv, o) = nvx;
+  *col(pv + n, o) = nvy;
+  *col(pv + 2 * n, o) = nvz;
   *A_out = A;
 }
 
@@ -243,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_advance(AdvanceArgs a, WallTable wt)
   uint32_t* ids = (DEBUG && a.dbg_ids != nullptr) ? a.dbg_ids + i * a.dbg_max_k : nullptr;
   const Sums s = gather<DEBUG, true>(a.gc, a.lr, a.cell_start, x, y, z, ids, a.dbg_max_k);
   bool A;
-  finish(a, wt.w, i, x, y, z, vx, vy, vz, s.S, s.Ux, s.Uy, s.Uz, s.M, &A);
+  finish(a, wt.w, (int64_t)blockIdx.x * kBlock, threadIdx.x, x, y, z, vx, vy, vz, s.S, s.Ux, s.Uy, s.Uz, s.M, &A);
   if (DEBUG) {
     if (a.dbg_count != nullptr) a.dbg_count[i] = s.count;
     if (a.dbg_branch != nullptr)
@@ -266,10 +279,14 @@ using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries /
 // takes one add and three fmas per candidate.  Used only for waves whose box
 // is at most 2h wide, where the cancellation stays far below the tolerance.
 struct DotStage {
+  static constexpr bool kCentred = true;
   float cx, cy, cz, inv_h2;
-  __device__ __forceinline__ float4 operator()(float4 P, uint32_t) const {
-    const float qx = P.x - cx, qy = P.y - cy, qz = P.z - cz;
+  float hx, hy, hz;  // half-extents of the wave box
+  __device__ __forceinline__ float4 centred(float qx, float qy, float qz) const {
     return make_float4(qx, qy, qz, -(fmaf(qz, qz, fmaf(qy, qy, qx * qx)) * inv_h2));
+  }
+  __device__ __forceinline__ float4 operator()(float4 P, uint32_t) const {
+    return centred(P.x - cx, P.y - cy, P.z - cz);
   }
   __device__ __forceinline__ float4 pad() const { return make_float4(0.0f, 0.0f, 0.0f, -3.0e38f); }
   __device__ __forceinline__ float4 vel(float4 V) const { return V; }
@@ -330,6 +347,14 @@ __device__ __forceinline__ void quad_sums(v4f acc, int lane, float& Ux, float& U
   S = quad_pick<3>(acc, i1, i2, i3);
 }
 
+// The lane's particle within the tile at first: threadIdx.x, or the tile's
+// last particle for idle lanes past n.
+__device__ __forceinline__ uint32_t lane_offset(const AdvanceArgs& a, int64_t first) {
+  const int64_t last = a.n - 1 - first;
+  const uint32_t lastc = (uint32_t)(last < kBlock - 1 ? last : kBlock - 1);
+  return min((uint32_t)threadIdx.x, lastc);
+}
+
 // One lane's HR state: the particle first + threadIdx.x, or the last particle
 // for idle lanes past n.
 struct HRLane {
@@ -337,9 +362,11 @@ struct HRLane {
 };
 __device__ __forceinline__ HRLane load_lane(const AdvanceArgs& a, int64_t first) {
   const int64_t n = a.ld;
-  const int64_t i0 = first + threadIdx.x;
-  const int64_t i = i0 < a.n ? i0 : a.n - 1;
-  return HRLane{a.hx[i], a.hx[n + i], a.hx[2 * n + i], a.hv[i], a.hv[n + i], a.hv[2 * n + i]};
+  const uint32_t o = lane_offset(a, first);
+  const float* const px = a.hx + first;
+  const float* const pv = a.hv + first;
+  return HRLane{*col(px, o), *col(px + n, o), *col(px + 2 * n, o),
+                *col(pv, o), *col(pv + n, o), *col(pv + 2 * n, o)};
 }
 
 // One block-sized tile of HR particles first .. first + kBlock - 1 (those
@@ -350,9 +377,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
                                              GatherLDS<G>& lds, int64_t first, const HRLane& st) {
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t i0 = first + threadIdx.x;
-  const bool live = i0 < a.n;
-  const int64_t i = live ? i0 : a.n - 1;  // idle lanes shadow the last particle
+  const bool live = first + (int64_t)threadIdx.x < a.n;  // idle lanes shadow the last particle
   const float x = st.x, y = st.y, z = st.z;
   const float vx = st.vx, vy = st.vy, vz = st.vz;
   const GridConst& gc = a.gc;
@@ -404,7 +429,8 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
         acc = mfma_entry(w, b, acc);
       };
       if (ext * ext <= 4.0f * gc.h2) {
-        const DotStage ds{0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2), inv_h2};
+        const DotStage ds{0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2), inv_h2,
+                          0.5f * (hi0 - lo0), 0.5f * (hi1 - lo1), 0.5f * (hi2 - lo2)};
         const float px = x - ds.cx, py = y - ds.cy, pz = z - ds.cz;
         const float A = fmaf(-fmaf(pz, pz, fmaf(py, py, px * px)), inv_h2, 1.0f);
         const float k2 = 2.0f * inv_h2;
@@ -483,15 +509,17 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
   }
   if (live) {
     bool A;
-    finish(a, walls, i, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, &A, wc);
+    const uint32_t o = threadIdx.x;
+    finish(a, walls, first, o, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, &A, wc);
     if (TAPE) {
       const int64_t m = a.n;
-      a.tape[i] = S;
-      a.tape[m + i] = Ux;
-      a.tape[2 * m + i] = Uy;
-      a.tape[3 * m + i] = Uz;
-      a.tape[4 * m + i] = M;
-      a.tape[5 * m + i] = __uint_as_float(arg);
+      float* const pt = a.tape + first;
+      *col(pt, o) = S;
+      *col(pt + m, o) = Ux;
+      *col(pt + 2 * m, o) = Uy;
+      *col(pt + 3 * m, o) = Uz;
+      *col(pt + 4 * m, o) = M;
+      *col(pt + 5 * m, o) = __uint_as_float(arg);
     }
   }
 }

@@ -222,6 +222,7 @@ struct SortedTag {
 // far away (weight exactly 0 for every lane).  vel(V) gives the 16 bytes
 // stored in the velocity list (by default the LR copy's (V_j, index bits)).
 struct PlainStage {
+  static constexpr bool kCentred = false;
   __device__ __forceinline__ float4 operator()(float4 P, uint32_t bits) const {
     return make_float4(P.x, P.y, P.z, __uint_as_float(bits));
   }
@@ -237,6 +238,10 @@ struct PlainStage {
 // stage.pad() the padding entry (whose velocity entry is zero).
 // Round > 1 pads every chunk to a multiple of Round entries, so that the
 // visitor can unroll by Round with immediate LDS offsets.
+// A stage with kCentred stores entries relative to the wave box's centre
+// (cx, cy, cz) and half-extents (hx, hy, hz); with one group the cull then
+// works on q = X - c, |q| - half per axis, and stage.centred(q) forms the
+// entry from the same q.
 template <int G, int Round = 1, class L, class Visit, class Tag = SortedTag, class Stage = PlainStage>
 __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridConst& gc,
                                            const LRPoint* __restrict__ lr, int lane, int wid,
@@ -279,9 +284,19 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
     asm volatile("" ::"v"(V.x), "v"(V.y), "v"(V.z), "v"(V.w));
     const uint32_t bits = tag(lo, kk, j, P.w);
     bool keep[G];
+    float4 pj;
+    if constexpr (Stage::kCentred && G == 1) {
+      const float qx = P.x - stage.cx, qy = P.y - stage.cy, qz = P.z - stage.cz;
+      const float dx = fmaxf(fabsf(qx) - stage.hx, 0.0f);
+      const float dy = fmaxf(fabsf(qy) - stage.hy, 0.0f);
+      const float dz = fmaxf(fabsf(qz) - stage.hz, 0.0f);
+      keep[0] = valid && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= cull2;
+      pj = stage.centred(qx, qy, qz);
+    } else {
 #pragma unroll
-    for (int g = 0; g < G; ++g) keep[g] = valid && box_dist2(ts.gb[g], P.x, P.y, P.z) <= cull2;
-    const float4 pj = stage(P, bits);
+      for (int g = 0; g < G; ++g) keep[g] = valid && box_dist2(ts.gb[g], P.x, P.y, P.z) <= cull2;
+      pj = stage(P, bits);
+    }
     uint32_t nmax = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
