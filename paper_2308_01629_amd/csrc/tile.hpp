@@ -287,10 +287,13 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
     float4 pj;
     if constexpr (Stage::kCentred && G == 1) {
       const float qx = P.x - stage.cx, qy = P.y - stage.cy, qz = P.z - stage.cz;
-      const float dx = fmaxf(fabsf(qx) - stage.hx, 0.0f);
-      const float dy = fmaxf(fabsf(qy) - stage.hy, 0.0f);
-      const float dz = fmaxf(fabsf(qz) - stage.hz, 0.0f);
-      keep[0] = valid && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= cull2;
+      // max(|q| - half, 0) by the [0, 1] output clamp of the subtraction:
+      // capping a distance at 1 only keeps more candidates, and culls the
+      // same ones when the support is below 1
+      const float dx = __builtin_amdgcn_fmed3f(fabsf(qx) - stage.hx, 0.0f, 1.0f);
+      const float dy = __builtin_amdgcn_fmed3f(fabsf(qy) - stage.hy, 0.0f, 1.0f);
+      const float dz = __builtin_amdgcn_fmed3f(fabsf(qz) - stage.hz, 0.0f, 1.0f);
+      keep[0] = valid & (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= cull2);  // no branch
       pj = stage.centred(qx, qy, qz);
     } else {
 #pragma unroll
@@ -300,7 +303,7 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
     uint32_t nmax = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const uint64_t m = __ballot(keep[g]);
+      const uint64_t m = __builtin_amdgcn_ballot_w64(keep[g]);
       if (keep[g]) {
         const uint32_t pos = cnt[g] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
