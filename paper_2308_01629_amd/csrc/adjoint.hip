@@ -286,13 +286,23 @@ __device__ __forceinline__ void reduce12(const Six& av, const Six& bv, float* r0
 // Gradient contributions of one (HR particle, LR candidate) pair: the six LR
 // components (dL/dV, dL/dX) are returned, the HR position term is subtracted
 // from bk.g{x,y,z}.
-__device__ __forceinline__ Six pair_contrib(float4 Q, float4 W, float x, float y, float z, float inv_h2,
-                                            float k2, uint32_t arg, Back& bk) {
-  const uint32_t id = __float_as_uint(W.w);
-  const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
-  const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+struct PairGeom {
+  float dx, dy, dz, t;  // X_j - x and max(1 - |X_j - x|^2 / h^2, 0)
+};
+__device__ __forceinline__ PairGeom pair_geom(float4 Q, float x, float y, float z, float inv_h2) {
+  PairGeom g;
+  g.dx = Q.x - x;
+  g.dy = Q.y - y;
+  g.dz = Q.z - z;
+  const float sq = fmaf(g.dz, g.dz, fmaf(g.dy, g.dy, g.dx * g.dx));
   // 1 - sq / h^2 <= 1, so the [0, 1] clamp (folded into the fma) is max(., 0)
-  const float t = __builtin_amdgcn_fmed3f(fmaf(-sq, inv_h2, 1.0f), 0.0f, 1.0f);
+  g.t = __builtin_amdgcn_fmed3f(fmaf(-sq, inv_h2, 1.0f), 0.0f, 1.0f);
+  return g;
+}
+
+__device__ __forceinline__ Six pair_contrib(const PairGeom& pg, float4 W, float k2, uint32_t arg, Back& bk) {
+  const uint32_t id = __float_as_uint(W.w);
+  const float dx = pg.dx, dy = pg.dy, dz = pg.dz, t = pg.t;
   const float t2 = t * t;
   const float w = t2 * t;
   const float gw = fmaf(bk.gUz, W.z, fmaf(bk.gUy, W.y, bk.gUx * W.x)) + bk.gS + (id == arg ? bk.gM : 0.0f);
@@ -477,39 +487,53 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
     float* const dst0 = lr_grad(ca0);
     float* const dst1 = lr_grad(ca1);
     float* const dst2 = lr_grad(ca2);
-    auto pair_pass = [&](uint32_t nc, const float4* lp, const float4* lv) {
-      // two candidates per iteration (no read-ahead: its register rotation
-      // cost 6 VALU per candidate and held the kernel at 88 VGPRs)
-      for (uint32_t c = 0; c < nc; c += 2) {
-        const bool has_b = c + 1 < nc;
-        const uint32_t cb = has_b ? c + 1 : c;
-        const float4 QA = lp[c], WA = lv[c];
-        const float4 QB = lp[cb], WB = lv[cb];
-        const Six va = pair_contrib(QA, WA, x, y, z, inv_h2, k2, arg, bk);
-        Six vb;
-        if (has_b) {
-          vb = pair_contrib(QB, WB, x, y, z, inv_h2, k2, arg, bk);
+    // Wave-summed LR parts of two candidates, added by the row-tail lanes
+    // (slots / ids of candidates a and b; a lone candidate passes zeros as b
+    // and its own slot, so the adds stay branch-free).
+    auto flush = [&](const Six& va, const Six& vb, uint32_t sa, uint32_t sbb, uint32_t ia, uint32_t ib) {
+      float r0, r1, r2;
+      reduce12(va, vb, &r0, &r1, &r2);
+      if (row_tail) {
+        if (block_acc) {
+          atomicAdd(&acc[ca0][sa], r0);
+          atomicAdd(&acc[ca1][cb1 ? sbb : sa], r1);
+          atomicAdd(&acc[ca2][sbb], r2);
         } else {
+          unsafeAtomicAdd(dst0 + ia, r0);
+          unsafeAtomicAdd(dst1 + (cb1 ? ib : ia), r1);
+          unsafeAtomicAdd(dst2 + ib, r2);
+        }
+      }
+    };
+    // About a quarter of a list's entries lie beyond the support of every
+    // lane (the wave's particles do not fill its box): their terms are zero
+    // for all lanes, so a ballot skips them.  The others are reduced two at a
+    // time, the first of a pair held until the second arrives.
+    auto pair_pass = [&](uint32_t nc, const float4* lp, const float4* lv) {
+      Six held;
+      uint32_t hs = 0u, hi = 0u;
+      bool holding = false;  // uniform
+      for (uint32_t c = 0; c < nc; ++c) {
+        const float4 Q = lp[c];
+        const PairGeom pg = pair_geom(Q, x, y, z, inv_h2);
+        if (__builtin_amdgcn_ballot_w64(pg.t > 0.0f) == 0ull) continue;
+        const float4 W = lv[c];
+        const Six v = pair_contrib(pg, W, k2, arg, bk);
+        if (!holding) {
+          held = v;
+          hs = __float_as_uint(Q.w);
+          hi = __float_as_uint(W.w);
+          holding = true;
+        } else {
+          flush(held, v, hs, __float_as_uint(Q.w), hi, __float_as_uint(W.w));
+          holding = false;
+        }
+      }
+      if (holding) {
+        Six zero;
 #pragma unroll
-          for (int q = 0; q < 6; ++q) vb.v[q] = 0.0f;
-        }
-        float r0, r1, r2;
-        reduce12(va, vb, &r0, &r1, &r2);
-        // Without a second candidate, QB / WB repeat the first one and its
-        // components are zero: the adds below stay branch-free.
-        if (row_tail) {
-          const uint32_t sa = __float_as_uint(QA.w), sbb = __float_as_uint(QB.w);
-          const uint32_t ia = __float_as_uint(WA.w), ib = __float_as_uint(WB.w);
-          if (block_acc) {
-            atomicAdd(&acc[ca0][sa], r0);
-            atomicAdd(&acc[ca1][cb1 ? sbb : sa], r1);
-            atomicAdd(&acc[ca2][sbb], r2);
-          } else {
-            unsafeAtomicAdd(dst0 + ia, r0);
-            unsafeAtomicAdd(dst1 + (cb1 ? ib : ia), r1);
-            unsafeAtomicAdd(dst2 + ib, r2);
-          }
-        }
+        for (int q = 0; q < 6; ++q) zero.v[q] = 0.0f;
+        flush(held, zero, hs, hs, hi, hi);
       }
     };
     if (block_acc) {
