@@ -563,15 +563,31 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
         if (brp[mid] <= t) lo = mid; else hi = mid;
       }
       const uint32_t j = brb[lo] + (t - brp[lo]);
-      const uint32_t id = __float_as_uint(a.lr[j].v.w);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         const float v = acc[c][t];
-        if (v != 0.0f) {
-          float* dst = c < 3 ? a.g_lr_v + (int64_t)c * nl : a.g_lr_x + (int64_t)(c - 3) * nl;
-          unsafeAtomicAdd(dst + id, v);
-        }
+        if (v != 0.0f) unsafeAtomicAdd(a.g_sorted + (int64_t)c * nl + j, v);
       }
+    }
+  }
+}
+
+// The block flushes' sums, by sorted index, added into the caller's LR
+// gradients by original index (the sorted copy is a permutation of the LR
+// particles, so each destination has one writer), zeroing them behind.
+__global__ __launch_bounds__(kBlock) void k_lr_grad_unsort(const LRPoint* __restrict__ lr, float* g_sorted,
+                                                          int64_t nl, float* g_lr_x, float* g_lr_v) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= nl) return;
+  const uint32_t id = __float_as_uint(lr[j].v.w);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    float* src = g_sorted + (int64_t)c * nl + j;
+    const float v = *src;
+    if (v != 0.0f) {
+      float* dst = c < 3 ? g_lr_v + (int64_t)c * nl : g_lr_x + (int64_t)(c - 3) * nl;
+      dst[id] += v;
+      *src = 0.0f;
     }
   }
 }
@@ -581,10 +597,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
 hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st) {
   if (a.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((a.n + kBlock - 1) / kBlock);
-  if (a.sc.has_rigid || !a.tiled)
+  if (a.sc.has_rigid || !a.tiled) {
     hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(kBlock), 0, st, a, walls);
-  else
+  } else {
     hipLaunchKernelGGL(k_adjoint_tiled, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    if (a.n_lr > 0)
+      hipLaunchKernelGGL(k_lr_grad_unsort, dim3((unsigned)((a.n_lr + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                         st, a.lr, a.g_sorted, a.n_lr, a.g_lr_x, a.g_lr_v);
+  }
   return hipGetLastError();
 }
 

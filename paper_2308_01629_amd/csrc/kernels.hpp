@@ -163,6 +163,11 @@ struct AdjointArgs {
   float* gv_in;
   float* g_lr_x;
   float* g_lr_v;
+  // [6][n_lr] LR gradients by sorted index (dL/dV, then dL/dX), zero between
+  // calls: the tiled kernel's block flush adds here, where the slots of one
+  // row are consecutive addresses; launch_adjoint then adds it into g_lr_v /
+  // g_lr_x by original index and zeroes it again
+  float* g_sorted;
   int64_t n;
   int64_t n_lr;
   int tiled;     // 1: wave-tiled kernel (non-rigid scenes), 0: one particle per lane

@@ -35,10 +35,12 @@ struct upsample_handle_s {
   hipEvent_t built[2], consumed[2], entry;
   int32_t* run_perm;
   uint32_t* finite_flag;
+  float* g_sorted;      // [6][max_lr] adjoint LR gradients by sorted index, zero between calls
   uint32_t* wall_mask;  // [n_cells] walls near each cell's neighbourhood, or null
   bool grid_valid;
   bool counts_dirty;     // an interrupted build may have left counts non-zero
   bool hr_counts_dirty;  // same for the HR sort bins
+  bool g_sorted_dirty;   // a failed backward may have left g_sorted non-zero
   int64_t grid_n_lr;
   bool has_rigid;
   upsample_tuning tune;
@@ -154,7 +156,7 @@ void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
                   h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.src, h->hs.x,
                   h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum,
-                  h->finite_flag, h->run_perm, h->wall_mask};
+                  h->finite_flag, h->run_perm, h->wall_mask, h->g_sorted};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
   for (const GridScratch& g : h->run_g) {
@@ -400,6 +402,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->hs.local, n_bins)
   ALLOC(h->hs.chunk_sum, n_bins / kScanChunk + 2)
   ALLOC(h->finite_flag, 1)
+  ALLOC(h->g_sorted, 6 * nl)
   const bool cull_walls = p->n_walls > 0 && h->n_cells <= kWallMaskMaxCells;
   if (cull_walls) ALLOC(h->wall_mask, h->n_cells)
 #undef ALLOC
@@ -409,6 +412,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   }
   if (e == hipSuccess) e = hipMemset(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells);
   if (e == hipSuccess) e = hipMemset(h->hs.counts, 0, sizeof(uint32_t) * (size_t)n_bins);
+  if (e == hipSuccess && nl > 0) e = hipMemset(h->g_sorted, 0, sizeof(float) * (size_t)(6 * nl));
   for (int k = 0; k < 2 * kTimingRing && e == hipSuccess; ++k) e = hipEventCreate(&h->ev[k]);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -625,13 +629,21 @@ static int backward_impl(upsample_handle h, const float* lr_x, const float* lr_v
   a.gv_in = gv_in;
   a.g_lr_x = g_lr_x;
   a.g_lr_v = g_lr_v;
+  a.g_sorted = h->g_sorted;
   a.n = n_hr;
   a.n_lr = n_lr;
   a.tiled = h->tune.adjoint_tiled;
   a.tile_max = h->tune.adjoint_tile_max;
   a.tape = tape;
-  hipError_t e = launch_adjoint(a, wall_table(h), st);
+  hipError_t e = hipSuccess;
+  if (h->g_sorted_dirty && n_lr > 0)
+    e = hipMemsetAsync(h->g_sorted, 0, sizeof(float) * (size_t)(6 * h->p.max_lr), st);
+  if (e == hipSuccess) {
+    h->g_sorted_dirty = true;
+    e = launch_adjoint(a, wall_table(h), st);
+  }
   if (e != hipSuccess) return hip_fail(h, e, "step_backward");
+  h->g_sorted_dirty = false;
   return UPSAMPLE_OK;
 }
 
