@@ -241,24 +241,6 @@ __device__ __forceinline__ float swap_sum32(float a, float b) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Wave sums of six per-lane values.  Returns q0, q1 such that lane 15 / 31 /
-// 47 / 63 of q0 hold the totals of a0 / a1 / a3 / a4 and lanes 15 / 47 of q1
-// hold the totals of a2 / a5.
-//   permlane32_swap(u, w) -> [u.lo, w.lo] and [u.hi, w.hi]: their sum carries
-//   u's 32-lane partials in lanes 0-31 and w's in lanes 32-63;
-//   permlane16_swap(u, w) -> [u.r0, w.r0, u.r2, w.r2] and [u.r1, w.r1, u.r3, w.r3]
-//   (rows of 16 lanes): their sum halves the partials again; a DPP row sum ends it.
-__device__ __forceinline__ void reduce6(float a0, float a1, float a2, float a3, float a4, float a5,
-                                        float* q0, float* q1) {
-  const float p0 = swap_sum32(a0, a3);
-  const float p1 = swap_sum32(a1, a4);
-  const float p2 = swap_sum32(a2, a5);
-  const auto t01 = __builtin_amdgcn_permlane16_swap(__float_as_uint(p0), __float_as_uint(p1), false, false);
-  const auto t22 = __builtin_amdgcn_permlane16_swap(__float_as_uint(p2), __float_as_uint(p2), false, false);
-  *q0 = row_sum(__uint_as_float(t01[0]) + __uint_as_float(t01[1]));
-  *q1 = row_sum(__uint_as_float(t22[0]) + __uint_as_float(t22[1]));
-}
-
 // Wave sums of twelve per-lane values (two candidates a, b; six components
 // each).  After the 32- and 16-lane swap levels the three registers hold,
 // row by row (rows of 16 lanes),

@@ -524,8 +524,10 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
   }
 }
 
+// Seven waves per SIMD asked of the register allocator; with four lane groups
+// the LDS lists (35 KB per block) allow four.
 template <bool RIGID, int G, bool TAPE = false>
-__global__ __launch_bounds__(kBlock, 7) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
+__global__ __launch_bounds__(kBlock, G == 4 ? 4 : 7) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
   __shared__ GatherLDS<G> lds;
   const int64_t first = (int64_t)blockIdx.x * kBlock;
   advance_tile<RIGID, G, TAPE>(a, wt.w, lds, first, load_lane(a, first));
