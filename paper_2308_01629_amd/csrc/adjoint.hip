@@ -308,7 +308,7 @@ __device__ __forceinline__ Six pair_contrib(const PairGeom& pg, float4 W, float 
 // flattened rows is one LR particle (sorted order).  Waves add their
 // wave-summed contributions to an LDS accumulator acc[component][slot] and the
 // block adds the non-zero slots to global memory once at the end.
-constexpr int kAccCap = 512;        // accumulator slots per block (26.8 KB of LDS in all: 6 blocks per CU)
+constexpr int kAccCap = 352;        // accumulator slots per block (22.4 KB of LDS in all: 7 blocks per CU)
 constexpr int kBlockRows = 256;     // at most one row per thread
 constexpr int kAdjListCap = 64;     // LDS candidate entries per wave and flush
 constexpr int kAdjRows = 64;        // stencil rows of one wave
