@@ -529,7 +529,8 @@ def test_wall_cull_is_exact(U, speed):
         up.set_tuning(wall_cull=2)
 
 
-def test_wall_cull_is_exact_with_32_walls(U):
+@pytest.mark.parametrize("groups", [1, 4])
+def test_wall_cull_is_exact_with_32_walls(U, groups):
     # The six box walls plus 26 planes through the box (clipped and not, one
     # with a hole), so that every bit of the per-cell masks is in use and
     # fast particles meet several walls in one step: culled and unculled
@@ -554,6 +555,7 @@ def test_wall_cull_is_exact_with_32_walls(U):
     walls = np.stack(walls)
     up = U(sc.r_lr, sc.r_hr, sc.dt, sc.g, sc.domain_lo, sc.domain_hi, walls=walls,
            max_lr=X.shape[1], max_hr=sc.n_hr)
+    up.set_tuning(gather_groups=groups)
     v0 = (3.0 * rng.normal(size=sc.hr_x0.shape)).astype(np.float32)
     hx, hv = dev(sc.hr_x0, torch), dev(v0, torch)
     up.sort_hr(hx, hv, with_perm=False)
@@ -566,5 +568,5 @@ def test_wall_cull_is_exact_with_32_walls(U):
     x = host(out[0][0]).astype(np.float64)
     W = walls.astype(np.float64)
     at = np.abs(W[:, :3] @ x - W[:, 3:4] - sc.r_hr) < 1e-6
-    log(f"32 walls: {int(at.any(0).sum())} particles at a wall, {int(at.any(1).sum())} walls met")
+    log(f"32 walls, {groups} group(s): {int(at.any(0).sum())} particles at a wall, {int(at.any(1).sum())} walls met")
     assert at[6:].any(1).sum() >= 4  # several of the inner planes pushed particles
