@@ -562,14 +562,21 @@ __global__ __launch_bounds__(kBlock) void k_lr_grad_unsort(const LRPoint* __rest
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= nl) return;
   const uint32_t id = __float_as_uint(lr[j].v.w);
+  // all twelve loads first (one round trip), then the stores
+  float v[6], old[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v[c] = g_sorted[(int64_t)c * nl + j];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    float* src = g_sorted + (int64_t)c * nl + j;
-    const float v = *src;
-    if (v != 0.0f) {
+    const float* dst = c < 3 ? g_lr_v + (int64_t)c * nl : g_lr_x + (int64_t)(c - 3) * nl;
+    old[c] = dst[id];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    if (v[c] != 0.0f) {
       float* dst = c < 3 ? g_lr_v + (int64_t)c * nl : g_lr_x + (int64_t)(c - 3) * nl;
-      dst[id] += v;
-      *src = 0.0f;
+      dst[id] = old[c] + v[c];
+      g_sorted[(int64_t)c * nl + j] = 0.0f;
     }
   }
 }
