@@ -5,7 +5,8 @@
 //   k_keys_count  cell key per LR particle, per-cell counts by atomic add
 //                 (the returned old count is the particle's arrival slot)
 //   k_scan_chunks exclusive scan of the counts in 2048-cell chunks (counts are
-//   k_scan_totals re-zeroed), then one block scans the chunk totals
+//   k_scan_totals re-zeroed), then one block scans the chunk totals (grids
+//                 of at most 256 chunks skip it: every scatter block scans them)
 //   k_scatter     cell_start[] and an arrival-order placement per cell
 //   k_stable      rank inside the cell by original index (stable order), then
 //                 writes perm[] and the LR copy in sorted order (32 B / particle)
@@ -161,6 +162,10 @@ __device__ __forceinline__ uint32_t cell_offset(const uint32_t* local, const uin
   return local[k] + chunk_sum[k / (uint32_t)kScanChunk];
 }
 
+// SCAN_TOTALS: chunk_sum holds the chunks' raw totals (at most kBlock
+// chunks), and every block scans them in LDS itself, which saves the
+// one-block launch over the totals on small grids.
+template <bool SCAN_TOTALS>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ slot, int64_t n,
                                                     const uint32_t* __restrict__ local,
@@ -168,11 +173,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
                                                     int64_t n_cells, int n_chunks,
                                                     uint32_t* __restrict__ tmp,
                                                     uint32_t* __restrict__ cell_start) {
+  __shared__ uint32_t offs[SCAN_TOTALS ? kBlock + 1 : 1];
+  const uint32_t* csum = chunk_sum;
+  if (SCAN_TOTALS) {
+    const uint32_t v = (int)threadIdx.x < n_chunks ? chunk_sum[threadIdx.x] : 0u;
+    uint32_t total;
+    const uint32_t e = block_exclusive_scan(v, &total);
+    offs[threadIdx.x] = e;
+    if (threadIdx.x == 0) offs[n_chunks] = total;
+    __syncthreads();
+    csum = offs;
+  }
   int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t < n_cells) cell_start[t] = cell_offset(local, chunk_sum, (uint32_t)t);
-  if (t == n_cells) cell_start[t] = chunk_sum[n_chunks];
+  if (t < n_cells) cell_start[t] = cell_offset(local, csum, (uint32_t)t);
+  if (t == n_cells) cell_start[t] = csum[n_chunks];
   if (t < n) {
-    const uint32_t pos = cell_offset(local, chunk_sum, keys[t]) + slot[t];
+    const uint32_t pos = cell_offset(local, csum, keys[t]) + slot[t];
     if (pos < (uint64_t)n) tmp[pos] = (uint32_t)t;  // always true when counts started at zero
   }
 }
@@ -549,12 +565,20 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
     hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, gc, lr_x, n_lr,
                        s.keys, s.slot, s.counts);
   }
-  hipError_t e = scan_bins(s.counts, n_cells, s.local, s.chunk_sum, st);
-  if (e != hipSuccess) return e;
   int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);
   int64_t span = n_lr > n_cells + 1 ? n_lr : n_cells + 1;
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, n_lr,
-                     s.local, s.chunk_sum, n_cells, n_chunks, s.tmp, s.cell_start);
+  if (n_chunks <= kBlock) {
+    // small grid: the chunk scan, then the scatter scans the chunk totals itself
+    hipLaunchKernelGGL(k_scan_chunks, dim3(n_chunks), dim3(kBlock), 0, st, s.counts, n_cells, s.local,
+                       s.chunk_sum);
+    hipLaunchKernelGGL(k_scatter<true>, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, n_lr,
+                       s.local, s.chunk_sum, n_cells, n_chunks, s.tmp, s.cell_start);
+  } else {
+    hipError_t e = scan_bins(s.counts, n_cells, s.local, s.chunk_sum, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter<false>, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, n_lr,
+                       s.local, s.chunk_sum, n_cells, n_chunks, s.tmp, s.cell_start);
+  }
   if (n_lr > 0) {
     hipLaunchKernelGGL(k_stable, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, s.tmp, s.keys,
                        s.cell_start, n_lr, lr_x, lr_v, lr_rigid, s.perm, s.lr_sorted);
@@ -571,7 +595,7 @@ hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& 
   if (e != hipSuccess) return e;
   const int n_chunks = (int)((b.n_cells + kScanChunk - 1) / kScanChunk);
   const int64_t span = b.n_int > b.n_cells + 1 ? b.n_int : b.n_cells + 1;
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, b.n_int, s.local,
+  hipLaunchKernelGGL(k_scatter<false>, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, b.n_int, s.local,
                      s.chunk_sum, b.n_cells, n_chunks, s.tmp, s.cell_start);
   if (b.n_int > 0) {
     hipLaunchKernelGGL(k_stable_batched, dim3(blocks_for(b.n_int)), dim3(kBlock), 0, st, s.tmp, s.keys,
