@@ -124,7 +124,7 @@ def test_rollout_gradient(U):
     loss.backward()
     torch.cuda.synchronize()
     L, g_X, g_V, gx0, _ = O.rollout_loss_grad(frames, sc.lr_rigid, sc.hr_x0, sc.hr_v0, sc.params(), sc.target)
-    assert abs(float(loss) - L) <= 1e-5 * abs(L)
+    assert abs(float(loss.detach()) - L) <= 1e-5 * abs(L)
     e_v = rel(host(LV.grad).reshape(T, -1), np.stack(g_V).reshape(T, -1))
     e_x = rel(host(LX.grad).reshape(T, -1), np.stack(g_X).reshape(T, -1))
     e_0 = rel(host(x0.grad), gx0)
