@@ -240,7 +240,8 @@ def place_hr(geom: Geometry, lr: np.ndarray, r_lr: float, n: int,
 # ---------------------------------------------------------------------------
 
 class LRTrajectory:
-    """Frames t = 1, 2, ... of LR positions and velocities (float32 SoA).
+    """Frames t = 1, 2, ... of LR positions and velocities (float32 SoA), one
+    per LR time step ``dt`` (frame 0 is the initial state at rest).
 
     V^{t+1} = flow(X^t) + F(X^t) * field_gain + eta,   eta ~ N(0, sigma^2) per component,
     X^{t+1} = confine(X^t + dt V^{t+1}).
@@ -252,6 +253,7 @@ class LRTrajectory:
                  field_gain: float, sigma: float = 0.05, recycle_rng=None):
         self.geom, self.r, self.dt = geom, r, dt
         self.X = X0.astype(np.float64).copy()
+        self.X0 = self.X.copy()
         self.rigid = rigid.astype(bool)
         self.field, self.rng, self.flow = fld, noise_rng, flow
         self.gain, self.sigma = field_gain, sigma
@@ -294,9 +296,13 @@ class LRTrajectory:
                             np.ascontiguousarray(V.T, dtype=F32)))
 
     def frame(self, t: int) -> Tuple[np.ndarray, np.ndarray]:
-        """LR (X, V) after t steps (t >= 1), each float32 [3, N_L]."""
-        if t < 1:
-            raise ValueError("frames start at t = 1")
+        """LR (X, V) after t steps, each float32 [3, N_L] (t = 0: the initial
+        positions at rest)."""
+        if t < 0:
+            raise ValueError("frames start at t = 0")
+        if t == 0:
+            return (np.ascontiguousarray(self.X0.T, dtype=F32),
+                    np.zeros((3, self.X0.shape[0]), dtype=F32))
         while len(self.frames) < t:
             self._advance()
         return self.frames[t - 1]
@@ -324,6 +330,7 @@ class Scene:
     target: Optional[np.ndarray] = None   # [3, N_H] float32 (differentiation config)
     c1: float = 512.0 / 729.0
     c2: float = 0.6
+    dt_lr: Optional[float] = None         # LR frame interval (None: one LR frame per HR step, dt)
 
     @property
     def n_lr(self) -> int:
@@ -357,9 +364,12 @@ FLOWS = {"plain": ("none", 1.0), "column": ("slump", 0.25), "heap": ("slump", 0.
 def build_scene(geometry: str, n_lr: int, n_hr: int, seed, r_lr: Optional[float] = None,
                 dt: float = DT_60, gravity: Sequence[float] = GRAVITY, with_walls: bool = True,
                 rigid_floor: bool = False, hr_radius_ratio: Optional[float] = None,
-                with_target: bool = False, name: Optional[str] = None) -> Scene:
+                with_target: bool = False, name: Optional[str] = None,
+                dt_lr: Optional[float] = None) -> Scene:
     """Build a seeded scene.  ``r_lr`` defaults to the radius whose lattice fill
-    of the geometry's nominal volume holds about ``n_lr`` sites."""
+    of the geometry's nominal volume holds about ``n_lr`` sites.  ``dt_lr``:
+    the LR frames' own time step (Section 5.2: 0.005 s) when the LR
+    trajectory is sub-stepped against the HR step ``dt``."""
     geom = make_geometry(geometry, with_walls)
     sj, sf, sn, sh, st = (np.random.default_rng(s) for s in _seeds(seed))
     auto = r_lr is None
@@ -387,8 +397,8 @@ def build_scene(geometry: str, n_lr: int, n_hr: int, seed, r_lr: Optional[float]
     r_hr = r_lr * ratio
     P = place_hr(geom, X[rigid == 0], r_lr, n_hr, sh, cell=2.0 * r_lr)
     flow, gain = FLOWS[geometry]
-    traj = LRTrajectory(geom, X, rigid, r_lr, dt, SmoothField.draw(sf), sn, flow, gain,
-                        recycle_rng=np.random.default_rng(sn.integers(1 << 62)))
+    traj = LRTrajectory(geom, X, rigid, r_lr, dt if dt_lr is None else dt_lr, SmoothField.draw(sf), sn, flow,
+                        gain, recycle_rng=np.random.default_rng(sn.integers(1 << 62)))
     target = None
     if with_target:
         target = np.ascontiguousarray((P + st.normal(0.0, 0.05, size=P.shape)).T, dtype=F32)
@@ -398,7 +408,8 @@ def build_scene(geometry: str, n_lr: int, n_hr: int, seed, r_lr: Optional[float]
                  domain_lo=geom.lo.astype(F32), domain_hi=geom.hi.astype(F32), walls=walls,
                  lr_x0=np.ascontiguousarray(X.T, dtype=F32), lr_rigid=rigid,
                  hr_x0=np.ascontiguousarray(P.T, dtype=F32),
-                 hr_v0=np.zeros((3, n_hr), dtype=F32), traj=traj, target=target)
+                 hr_v0=np.zeros((3, n_hr), dtype=F32), traj=traj, target=target,
+                 dt_lr=None if dt_lr is None else float(dt_lr))
 
 
 NOMINAL_FILL_VOLUME = {
