@@ -11,9 +11,12 @@ uploaded before timing: the timed region starts with all LR frames and the HR
 state resident in HBM.
 
 Prints ONE JSON line.  Besides the headline value it carries the roofline of the
-dominant kernel (the fused gather, timed with HIP events on its own stream),
-the oracle timed on the host cores on a bounded sample, the backward/forward
-time ratio on the differentiation workload and the batched-vs-plain speedup.
+dominant kernel (the fused gather, timed with HIP events on its own stream,
+and, while its sources are the ones profiled, the average of the same
+launches in the committed rocprofv3 kernel trace), the same figures for the
+column and plain workloads, the oracle timed on the host cores on a bounded
+sample, the backward/forward time ratio on the differentiation workload and
+the batched-vs-plain speedup.
 """
 from __future__ import annotations
 
@@ -54,7 +57,7 @@ def parse():
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched legs")
-    ap.add_argument("--only", choices=["drain", "diff", "batched"], default=None,
+    ap.add_argument("--only", choices=["drain", "column", "plain", "diff", "batched"], default=None,
                     help="run one leg only (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel 4 times (scale for the "
@@ -73,33 +76,81 @@ def source_hash(*names):
 GATHER_SOURCES = ("advance.hip", "tile.hpp", "common.hpp")
 
 
-def traffic_from_profiles():
-    """HBM bytes per gather launch from the committed rocprofv3 PMC summary,
-    only while the kernel's sources are the ones it was measured on."""
-    path = os.path.join(ROOT, "profiles", "advance_drain_traffic.md")
+def profile_record(name, key):
+    """A machine-readable ``key: value`` line of a committed rocprofv3 summary
+    under profiles/, only while the gather's sources hash to the
+    ``source_hash`` line of the same file (the kernel it was measured on)."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         lines = open(path).read().splitlines()
     except OSError:
         return None
     rec = {}
     for ln in lines:
-        if ":" in ln and ln.split(":", 1)[0] in ("source_hash", "hbm_bytes_per_launch"):
+        if ":" in ln and ln.split(":", 1)[0] in ("source_hash", key):
             k, v = ln.split(":", 1)
             rec[k] = v.strip()
     if rec.get("source_hash") != source_hash(*GATHER_SOURCES):
         return None
     try:
-        return float(rec["hbm_bytes_per_launch"])
+        return float(rec[key])
     except (KeyError, ValueError):
         return None
 
 
-def drain_leg(args, torch, Upsampler):
+def traffic_from_profiles():
+    """HBM bytes per drain gather launch from the committed PMC summary."""
+    return profile_record("advance_drain_traffic.md", "hbm_bytes_per_launch")
+
+
+def host_cpu():
+    """Cores and model of the host this runs on (for the oracle baseline)."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model}
+
+
+def gather_bytes(n_hr, n_lr, n_cells):
+    """Algorithmic HBM bytes of one gather launch: 48 B per HR particle (read
+    x, v; write x', v'), 32 B per LR particle (its sorted copy, read once),
+    4 B per cell-table entry."""
+    return 48 * n_hr + 32 * n_lr + 4 * (n_cells + 1)
+
+
+def roofline(adv_s, n_hr, n_lr, n_cells, traffic=None, profile_us=None):
+    b = gather_bytes(n_hr, n_lr, n_cells)
+    rf = {"bound": "hbm", "kernel": "k_advance_tiled (fused gather/blend/integrate/walls)",
+          "achieved": b / adv_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+          "frac": b / adv_s / HBM_PEAK, "traffic": traffic,
+          "algorithmic_bytes_per_launch": b, "avg_launch_us": adv_s * 1e6,
+          "measured_by": "HIP events around the timed gathers (bench.py)"}
+    if profile_us is not None:
+        rf["profile_avg_launch_us"] = profile_us
+        rf["profile_frac"] = b / (profile_us * 1e-6) / HBM_PEAK
+    return rf
+
+
+def drain_leg(args, torch, Upsampler, name="drain", steps=None, warmup=None, repeats=None):
+    """A workload timed through upsample_run (drain: the headline; column and
+    plain: the same measurement at their sizes)."""
     from workloads import configs
     t0 = time.time()
-    sc = configs.drain()
-    n_frames = args.warmup + args.steps
-    log(f"drain: {sc.n_lr} LR, {sc.n_hr} HR, generating {n_frames} LR frames")
+    sc = getattr(configs, name)()
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    repeats = args.repeats if repeats is None else repeats
+    n_frames = warmup + steps
+    log(f"{name}: {sc.n_lr} LR, {sc.n_hr} HR, generating {n_frames} LR frames")
     frames = [sc.lr_frame(t) for t in range(1, n_frames + 1)]
     LX = torch.from_numpy(np.stack([f[0] for f in frames])).cuda()
     LV = torch.from_numpy(np.stack([f[1] for f in frames])).cuda()
@@ -114,7 +165,7 @@ def drain_leg(args, torch, Upsampler):
         k = max(1, min(args.sort_every or 10, LX.shape[0]))
         up = Upsampler.tuned(sc, LX[:k], LV[:k], hx, hv)
         tune = up.autotune
-        log(f"drain: autotune {tune}")
+        log(f"{name}: autotune {tune}")
     if args.sort_sub:
         up.set_tuning(sort_sub=args.sort_sub)
     if args.sort_mode >= 0:
@@ -122,7 +173,7 @@ def drain_leg(args, torch, Upsampler):
     if args.groups:
         up.set_tuning(gather_groups=args.groups)
     gi = up.grid_info()
-    log(f"drain: setup {time.time() - t0:.1f}s, grid {gi['dims']} reach {gi['reach']} tuning {up.get_tuning()}")
+    log(f"{name}: setup {time.time() - t0:.1f}s, grid {gi['dims']} reach {gi['reach']} tuning {up.get_tuning()}")
     up.sort_hr(hx, hv, with_perm=False)
     # HR state ping-pongs between two buffer pairs in the step loop: the
     # reorder writes the other pair; upsample_run works in place
@@ -143,43 +194,41 @@ def drain_leg(args, torch, Upsampler):
                 state[0], state[1], state[2], state[3] = state[2], state[3], state[0], state[1]
             up.step(LX[t], LV[t], None, state[0], state[1], out_x=state[0], out_v=state[1])
 
-    run(0, args.warmup)
+    run(0, warmup)
     torch.cuda.synchronize()
     # every repeat replays the same K steps from the same post-warm-up state
     x_snap, v_snap = state[0].clone(), state[1].clone()
     times = []
-    for rep in range(args.repeats + 1):
+    for rep in range(repeats + 1):
         state[0].copy_(x_snap)
         state[1].copy_(v_snap)
-        timed_kernel = rep == args.repeats   # last pass: per-launch events on the gather kernel
+        timed_kernel = rep == repeats   # last pass: per-launch events on the gather kernel
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         s0.record()
-        run(args.warmup, args.steps, timed_kernel=timed_kernel)
+        run(warmup, steps, timed_kernel=timed_kernel)
         s1.record()
         torch.cuda.synchronize()
         if timed_kernel:
             adv_ms, launches = up.timing_read()
             up.timing_enable(False)
-            log(f"drain: gather kernel {adv_ms * 1e3 / max(launches, 1):.1f} us/launch over {launches}")
+            log(f"{name}: gather kernel {adv_ms * 1e3 / max(launches, 1):.1f} us/launch over {launches}")
         else:
             times.append(s0.elapsed_time(s1) / 1e3)
-            log(f"drain: repeat {rep}: {times[-1] * 1e3 / args.steps:.4f} ms/step")
+            log(f"{name}: repeat {rep}: {times[-1] * 1e3 / steps:.4f} ms/step")
     elapsed = float(np.median(times))
-    ms_step = elapsed * 1e3 / args.steps
+    ms_step = elapsed * 1e3 / steps
     n_cells = gi["n_cells"]
-    adv_bytes = 48 * sc.n_hr + 32 * sc.n_lr + 4 * (n_cells + 1)
     step_bytes = 48 * sc.n_hr + 89 * sc.n_lr + 8 * n_cells
     adv_s = adv_ms / 1e3 / max(launches, 1)
-    traffic = traffic_from_profiles()
-    rf = {"bound": "hbm", "kernel": "k_advance_tiled (fused gather/blend/integrate/walls)",
-          "achieved": adv_bytes / adv_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-          "frac": adv_bytes / adv_s / HBM_PEAK, "traffic": traffic,
-          "algorithmic_bytes_per_launch": adv_bytes, "avg_launch_us": adv_s * 1e6}
-    res = {"value": sc.n_hr * args.steps / elapsed, "ms_per_step": ms_step,
+    is_drain = name == "drain"
+    rf = roofline(adv_s, sc.n_hr, sc.n_lr, n_cells,
+                  traffic=traffic_from_profiles() if is_drain else None,
+                  profile_us=profile_record("advance_drain_trace.md", "timed_pass_avg_us") if is_drain else None)
+    res = {"value": sc.n_hr * steps / elapsed, "ms_per_step": ms_step,
            "step_hbm_frac": step_bytes / (ms_step / 1e3) / HBM_PEAK,
-           "config": {"workload": "drain", "n_lr": sc.n_lr, "n_hr": sc.n_hr, "r_lr": sc.r_lr,
+           "config": {"workload": name, "n_lr": sc.n_lr, "n_hr": sc.n_hr, "r_lr": sc.r_lr,
                       "r_hr": sc.r_hr, "dt": sc.dt, "walls": int(sc.walls.shape[0]),
                       "grid": list(gi["dims"]), "reach": gi["reach"], "sort_every": args.sort_every,
                       "entry": "upsample_step loop" if args.step_loop else "upsample_run",
@@ -205,6 +254,7 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
     LX = torch.from_numpy(np.stack([f[0] for f in frames])).cuda()
     LV = torch.from_numpy(np.stack([f[1] for f in frames])).cuda()
     up = Upsampler.from_scene(sc)
+    n_cells = up.grid_info()["n_cells"]
     x0 = torch.from_numpy(sc.hr_x0).cuda()
     v0 = torch.from_numpy(sc.hr_v0).cuda()
     y = torch.from_numpy(sc.target).cuda()
@@ -265,6 +315,11 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
     bwd()
     fwd_taped()
     bwd_taped()
+    # the gather kernel alone on the plain forward (HIP events per launch)
+    up.timing_enable(True)
+    fwd()
+    adv_ms, launches = up.timing_read()
+    up.timing_enable(False)
     t_f = timed(fwd) / steps
     t_b = timed(bwd) / steps
     t_ft = timed(fwd_taped) / steps
@@ -289,10 +344,13 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
         f"{t_bt / t_ft:.2f}; plain forward {t_f * 1e3:.1f}, recomputing backward {t_b * 1e3:.1f} (ratio "
         f"{t_b / t_f:.2f}); rollout fwd {t_rf:.2f} ms, fwd+bwd {t_rfb:.2f} ms")
     return {"workload": "diff", "n_lr": sc.n_lr, "n_hr": sc.n_hr,
-            "ratio": t_bt / t_ft, "ratio_definition": "taped backward / taped forward, per step",
-            "forward_taped_us_per_step": t_ft * 1e3, "backward_taped_us_per_step": t_bt * 1e3,
+            "ratio": t_b / t_f,
+            "ratio_definition": "t(upsample_step_backward) / t(upsample_step) per step, each with its grid "
+                                "rebuild; the backward recomputes the forward sums",
             "forward_us_per_step": t_f * 1e3, "backward_recompute_us_per_step": t_b * 1e3,
-            "ratio_recompute_vs_plain_forward": t_b / t_f,
+            "ratio_taped": t_bt / t_ft,
+            "forward_taped_us_per_step": t_ft * 1e3, "backward_taped_us_per_step": t_bt * 1e3,
+            "forward_gather_roofline": roofline(adv_ms / 1e3 / max(launches, 1), sc.n_hr, sc.n_lr, n_cells),
             "rollout_steps": steps, "checkpoint_every": every, "reorder_every": reorder_every,
             "rollout_forward_ms": t_rf,
             "rollout_forward_backward_ms": t_rfb, "rollout_backward_over_forward": (t_rfb - t_rf) / t_rf}
@@ -426,7 +484,7 @@ def cpu_baseline(sc, frames, budget_s=12.0):
         t_used += time.perf_counter() - t0
         done += n
     return {"value": done / t_used, "unit": "HR particle-updates/s", "cores": O.WORKERS,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": f"{done} HR particles of the drain workload (random {n}-particle batches, "
                       f"full 65,536-particle LR frame), one step each, {t_used:.1f} s; numpy "
                       f"float64, KD-tree queries on {O.WORKERS} threads"}
@@ -451,6 +509,14 @@ def main():
     if args.only in (None, "drain"):
         d = drain_leg(args, torch, Upsampler)
         out.update({k: d[k] for k in ("value", "ms_per_step", "config", "roofline", "step_hbm_frac")})
+    for name in ("column", "plain"):
+        if args.only == name or (args.only is None and not args.no_extras):
+            # the other single-scene workloads: updates/s and the gather's roofline
+            w = drain_leg(args, torch, Upsampler, name=name, steps=100 if name == "column" else 10,
+                          warmup=10 if name == "column" else 2, repeats=3)
+            out[name] = {"value": w["value"], "unit": "HR particle-updates/s", "ms_per_step": w["ms_per_step"],
+                         "steps": 100 if name == "column" else 10, "config": w["config"],
+                         "roofline": w["roofline"], "step_hbm_frac": w["step_hbm_frac"]}
     if args.only == "diff" or (args.only is None and not args.no_extras):
         out["backward_forward"] = diff_leg(args, torch, Upsampler)
     if args.only == "batched" or (args.only is None and not args.no_extras):

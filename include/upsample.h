@@ -57,6 +57,15 @@ extern "C" {
 
 /* flags */
 #define UPSAMPLE_FLAG_VALIDATE      1u  /* scan inputs for NaN/Inf (synchronises the stream) */
+/* Deterministic LR gradients in upsample_step_backward(_taped): the HR pass
+ * records each particle's adjoint coefficients instead of adding to the LR
+ * gradients, the HR particles are sorted by cell (stable), and each LR
+ * particle's gradient is summed by one wave over its HR neighbours in a fixed
+ * order with a fixed lane reduction, then added by one writer.  No float
+ * atomics: repeated calls give the same bits.  Costs a per-lane HR pass, the HR
+ * sort and the LR pass; init allocates 8 B per cell and 56 B per HR particle
+ * (max_hr) more. */
+#define UPSAMPLE_FLAG_DETERMINISTIC_BWD 2u
 
 typedef struct upsample_handle_s* upsample_handle;
 
@@ -174,7 +183,8 @@ int upsample_step(upsample_handle h,
  * smallest LR index) and the wall activations are held at their forward values.
  * Rebuilds the grid from lr_x (so the handle's grid afterwards is that frame's).
  * LR gradients are accumulated with float atomics: summation order, and so the
- * last bits, may differ between runs.
+ * last bits, may differ between runs -- unless the handle was created with
+ * UPSAMPLE_FLAG_DETERMINISTIC_BWD (then they are bitwise reproducible).
  */
 int upsample_step_backward(upsample_handle h,
                            const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
@@ -228,6 +238,30 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
                  int32_t sort_every, int32_t* perm_io, void* stream);
 
 /*
+ * Multi-rate run (Section 5.2): LR frames at their own time step dt_lr (the
+ * paper's LR simulation steps at 0.005 s, the HR upsampling at 0.0167 s), HR
+ * steps of the handle's dt.  lr_x, lr_v: device [n_frames][3][n_lr], frame k
+ * at time t_lr0 + k dt_lr (n_frames >= 2).  HR step n (0 <= n < n_steps)
+ * advances the state from t_hr0 + n dt to t_hr0 + (n + 1) dt against the LR
+ * state at its end (Section 4's time level t + 1): with
+ *   s = (t_hr0 + (n + 1) dt - t_lr0) / dt_lr,  k = floor(s),  theta = s - k
+ * (in double; a step ending on the last frame takes k = n_frames - 2,
+ * theta = 1), the LR state is the linear interpolation in time between frames
+ * k and k + 1, in float32 with theta rounded to float32 and each operation
+ * rounded separately:  X = X_k + fl(theta fl(X_{k+1} - X_k)),  V likewise.
+ * The interpolation is fused into the grid build (the keys and the sorted
+ * copy compute it identically); otherwise the run is upsample_run's: grids
+ * built on the internal stream in batches, a reorder every sort_every steps,
+ * perm_io composed through the reorders, the state advanced in place.  A
+ * step ending before frame 0 or after the last frame is INVALID_ARG (checked
+ * before any work is enqueued).
+ */
+int upsample_run_multirate(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                           int64_t n_lr, int32_t n_frames, double t_lr0, double dt_lr, double t_hr0,
+                           int32_t n_steps, float* hr_x, float* hr_v, int64_t n_hr, int32_t sort_every,
+                           int32_t* perm_io, void* stream);
+
+/*
  * Reorder HR particles by the key that upsample_tuning's sort_mode selects
  * over cells split into sort_sub^3 sub-cells (by default the Hilbert index of
  * the sub-cells), so that consecutive particles -- the lanes of one wave of
@@ -277,6 +311,38 @@ int upsample_debug_grid(upsample_handle h, uint32_t* keys, uint32_t* perm,
 int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* hr_v,
                              int64_t n_hr, uint32_t* count, uint32_t* ids, int64_t max_k,
                              uint8_t* branch, void* stream);
+
+/* upsample_debug_lr_sorted copies the last build's LR state in sorted order --
+ * the positions and velocities the step kernel reads, after any interpolation
+ * in time -- into device [3][n_lr] arrays (either may be NULL). */
+int upsample_debug_lr_sorted(upsample_handle h, float* x_sorted, float* v_sorted, void* stream);
+
+/*
+ * upsample_debug_step_members runs the step kernel of upsample_advance --
+ * the same template instance path for this handle's tuning and scene (wave
+ * tiles, box cull of the candidates, weight form, matrix-core sums, per-lane
+ * walk for spread-out waves) with the same arithmetic -- against the last
+ * grid, writes the stepped state to hr_x_out, hr_v_out ([3][n_hr], equal bit
+ * for bit to upsample_advance's), and exports per HR particle what its walk
+ * saw:
+ *   count[i]       entries of its candidate list meeting the membership
+ *                  predicate above (so: the size of its neighbour set (Section
+ *                  4's sums run over it), if the cull kept every member)
+ *   ids[i * max_k + c]  their original LR indices, in walk order (max_k > 0
+ *                  when ids is given; entries past max_k are counted only)
+ *   count_w[i]     entries whose weight, as the kernel computed it, is > 0
+ *                  (the entries that enter the sums)
+ *   w_disagree[i]  the largest weight over entries on which those two tests
+ *                  disagree: the kernel's weight, or the separately rounded
+ *                  direct form max(0, 1 - s / h2)^3 of the exact s; 0 if none
+ * Any export pointer may be NULL.  All device pointers; errors as
+ * upsample_advance.  For parity tests: the kernel timed by upsample_advance
+ * and upsample_run is checked here member by member.
+ */
+int upsample_debug_step_members(upsample_handle h, const float* hr_x, const float* hr_v,
+                                float* hr_x_out, float* hr_v_out, int64_t n_hr, uint32_t* count,
+                                uint32_t* ids, int64_t max_k, uint32_t* count_w, float* w_disagree,
+                                void* stream);
 
 /*
  * Launch-shape knobs of a handle (results do not depend on them beyond float

@@ -25,6 +25,7 @@ MAX_WALLS = 32
 WALL_FLOATS = 12
 DEFAULT_CELL_FACTOR = 1.0001
 FLAG_VALIDATE = 1
+FLAG_DETERMINISTIC_BWD = 2
 BATCH_EAGER = 1
 
 
@@ -98,10 +99,14 @@ SIGNATURES = {
     "upsample_step_backward_taped": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
                                             _P]),
     "upsample_run": (_INT, [_P, _P, _P, _P, _I64, _I32, _P, _P, _I64, _I32, _P, _P]),
+    "upsample_run_multirate": (_INT, [_P, _P, _P, _P, _I64, _I32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, _I32, _P, _P, _I64, _I32, _P, _P]),
+    "upsample_debug_lr_sorted": (_INT, [_P, _P, _P, _P]),
     "upsample_sort_hr": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _P]),
     "upsample_permute": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _INT, _P]),
     "upsample_debug_grid": (_INT, [_P, _P, _P, _P, _P]),
     "upsample_debug_neighbors": (_INT, [_P, _P, _P, _I64, _P, _P, _I64, _P, _P]),
+    "upsample_debug_step_members": (_INT, [_P, _P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P]),
     "upsample_set_tuning": (_INT, [_P, ctypes.POINTER(Tuning)]),
     "upsample_get_tuning": (_INT, [_P, ctypes.POINTER(Tuning)]),
     "upsample_timing_enable": (_INT, [_P, _INT]),

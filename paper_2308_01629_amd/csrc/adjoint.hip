@@ -16,6 +16,11 @@
 //                    to global memory by six lanes (two atomic instructions);
 //   k_adjoint        one particle per lane, its own stencil walk, atomics per
 //                    pair: spread-out waves and scenes with rigid LR particles.
+// Deterministic LR gradients take a third route: k_adjoint_det writes each HR
+// particle's adjoint coefficients, and k_adjoint_det_lr gives every LR
+// particle one wave that walks its HR neighbours (HR sorted by cell, stable)
+// in a fixed order and reduces over the lanes in a fixed pattern; each LR
+// gradient then has one writer and no float atomic is involved.
 #include "kernels.hpp"
 #include "tile.hpp"
 
@@ -131,7 +136,11 @@ __device__ __forceinline__ void stencil_bounds(const GridConst& gc, float x, flo
   }
 }
 
-// One particle, its own stencil walk, float atomics per member pair.
+// One particle, its own stencil walk, float atomics per member pair.  DET:
+// no LR gradient is added; the particle's coefficients (dL/dU, dL/dS, dL/dM,
+// argmax bits; zeros when the rigid rule drops its support) go to
+// a.det_coef for the LR pass, and only the HR position terms are summed here.
+template <bool DET = false>
 __device__ __forceinline__ void adjoint_lane(const AdjointArgs& a, const WallTable& wt, int64_t i) {
   const int64_t n = a.n;
   const GridConst& gc = a.gc;
@@ -181,6 +190,14 @@ __device__ __forceinline__ void adjoint_lane(const AdjointArgs& a, const WallTab
   }
   Back bk = backprop(a.sc, wt, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, a.gx_out[i], a.gx_out[n + i],
                      a.gx_out[2 * n + i], a.gv_out[i], a.gv_out[n + i], a.gv_out[2 * n + i]);
+  if (DET) {
+    a.det_coef[i] = gran ? bk.gUx : 0.0f;
+    a.det_coef[n + i] = gran ? bk.gUy : 0.0f;
+    a.det_coef[2 * n + i] = gran ? bk.gUz : 0.0f;
+    a.det_coef[3 * n + i] = gran ? bk.gS : 0.0f;
+    a.det_coef[4 * n + i] = gran ? bk.gM : 0.0f;
+    a.det_coef[5 * n + i] = __uint_as_float(gran ? arg : 0xffffffffu);
+  }
   if (gran) {
     const float k2 = -6.0f * gc.inv_h2;  // dw/ds = -3 t^2 / h2, times 2 for ds/dX
     const int64_t nl = a.n_lr;
@@ -198,14 +215,16 @@ __device__ __forceinline__ void adjoint_lane(const AdjointArgs& a, const WallTab
             const float w = t * t * t;
             float gw = fmaf(bk.gUz, V.z, fmaf(bk.gUy, V.y, bk.gUx * V.x)) + bk.gS;
             if (id == arg) gw += bk.gM;
-            unsafeAtomicAdd(&a.g_lr_v[id], w * bk.gUx);
-            unsafeAtomicAdd(&a.g_lr_v[nl + id], w * bk.gUy);
-            unsafeAtomicAdd(&a.g_lr_v[2 * nl + id], w * bk.gUz);
             const float c = gw * k2 * t * t;
             const float dx = P.x - x, dy = P.y - y, dz = P.z - z;
-            unsafeAtomicAdd(&a.g_lr_x[id], c * dx);
-            unsafeAtomicAdd(&a.g_lr_x[nl + id], c * dy);
-            unsafeAtomicAdd(&a.g_lr_x[2 * nl + id], c * dz);
+            if (!DET) {
+              unsafeAtomicAdd(&a.g_lr_v[id], w * bk.gUx);
+              unsafeAtomicAdd(&a.g_lr_v[nl + id], w * bk.gUy);
+              unsafeAtomicAdd(&a.g_lr_v[2 * nl + id], w * bk.gUz);
+              unsafeAtomicAdd(&a.g_lr_x[id], c * dx);
+              unsafeAtomicAdd(&a.g_lr_x[nl + id], c * dy);
+              unsafeAtomicAdd(&a.g_lr_x[2 * nl + id], c * dz);
+            }
             bk.gx = fmaf(-c, dx, bk.gx);
             bk.gy = fmaf(-c, dy, bk.gy);
             bk.gz = fmaf(-c, dz, bk.gz);
@@ -225,6 +244,77 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a, WallTable wt)
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
   adjoint_lane(a, wt, i);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adjoint_det(AdjointArgs a, WallTable wt) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  adjoint_lane<true>(a, wt, i);
+}
+
+// Sum over the wave by a fixed butterfly: the same inputs give the same bits.
+__device__ __forceinline__ float wave_sum_fixed(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// One wave per LR particle (sorted index js = 4 blockIdx.x + wave): its HR
+// neighbours come from the HR grid (stable cell order) over the stencil of
+// its own cell, each lane taking every 64th candidate of the walk; the terms
+// of a member pair are those of adjoint_lane, from the pair's HR coefficients
+// and the same separately rounded squared distance.  Lane 0 adds the wave's
+// sums into the caller's gradients (one writer per LR particle).
+__global__ __launch_bounds__(kBlock) void k_adjoint_det_lr(AdjointArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t js = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (js >= a.n_lr) return;
+  const GridConst& gc = a.gc;
+  const LRPoint L = a.lr[js];
+  const uint32_t id = __float_as_uint(L.v.w);
+  const uint32_t* hcs = a.hr_cell_start;
+  const LRPoint* hs = a.hr_sorted;
+  const int64_t n = a.n;
+  const float k2 = -6.0f * gc.inv_h2;
+  int lo[3], hi[3];
+  stencil_bounds(gc, L.p.x, L.p.y, L.p.z, lo, hi);
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int zz = lo[2]; zz <= hi[2]; ++zz)
+    for (int yy = lo[1]; yy <= hi[1]; ++yy) {
+      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
+      const uint32_t b = hcs[row + (uint32_t)lo[0]], e = hcs[row + (uint32_t)hi[0] + 1u];
+      for (uint32_t q = b + (uint32_t)lane; q < e; q += 64u) {
+        const float4 H = hs[q].p;
+        const float s = sq_dist(L.p.x, L.p.y, L.p.z, H.x, H.y, H.z);
+        if (s < gc.h2) {
+          const int64_t i = (int64_t)__float_as_uint(hs[q].v.w);
+          const float gUx = a.det_coef[i], gUy = a.det_coef[n + i], gUz = a.det_coef[2 * n + i];
+          const float gS = a.det_coef[3 * n + i], gM = a.det_coef[4 * n + i];
+          const uint32_t arg = __float_as_uint(a.det_coef[5 * n + i]);
+          const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
+          const float w = t * t * t;
+          float gw = fmaf(gUz, L.v.z, fmaf(gUy, L.v.y, gUx * L.v.x)) + gS;
+          if (id == arg) gw += gM;
+          const float c = gw * k2 * t * t;
+          acc[0] += w * gUx;
+          acc[1] += w * gUy;
+          acc[2] += w * gUz;
+          acc[3] += c * (L.p.x - H.x);
+          acc[4] += c * (L.p.y - H.y);
+          acc[5] += c * (L.p.z - H.z);
+        }
+      }
+    }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) acc[c] = wave_sum_fixed(acc[c]);
+  if (lane == 0) {
+    const int64_t nl = a.n_lr;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.g_lr_v[c * nl + id] += acc[c];
+      a.g_lr_x[c * nl + id] += acc[3 + c];
+    }
+  }
 }
 
 // Sum over 16 lanes of a row; lane 15 of the row receives it.
@@ -583,10 +673,23 @@ __global__ __launch_bounds__(kBlock) void k_lr_grad_unsort(const LRPoint* __rest
 
 }  // namespace
 
-hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st) {
+hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st,
+                          const GridScratch* hr_grid) {
   if (a.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((a.n + kBlock - 1) / kBlock);
-  if (a.sc.has_rigid || !a.tiled) {
+  if (a.det_coef != nullptr) {
+    if (hr_grid == nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adjoint_det, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    if (a.n_lr > 0) {
+      const int64_t n_cells = (int64_t)a.gc.dims[0] * a.gc.dims[1] * a.gc.dims[2];
+      hipError_t e = launch_build_grid(a.gc, a.hx, a.hv, nullptr, a.n, n_cells, *hr_grid, st);
+      if (e != hipSuccess) return e;
+      AdjointArgs b = a;
+      b.hr_cell_start = hr_grid->cell_start;
+      b.hr_sorted = hr_grid->lr_sorted;
+      hipLaunchKernelGGL(k_adjoint_det_lr, dim3((unsigned)((a.n_lr + kWaves - 1) / kWaves)), dim3(kBlock), 0, st, b);
+    }
+  } else if (a.sc.has_rigid || !a.tiled) {
     hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(kBlock), 0, st, a, walls);
   } else {
     hipLaunchKernelGGL(k_adjoint_tiled, dim3(blocks), dim3(kBlock), 0, st, a, walls);

@@ -20,7 +20,17 @@ struct Sums {
   bool gran;
   uint32_t count;
   uint32_t arg;  // TAPE: original index of the largest weight (ties: smallest index)
+  uint32_t count_w;  // DEBUG: candidates whose computed weight is > 0
+  float wdis;        // DEBUG: largest weight where that test and membership disagree
 };
+
+// Weight of squared distance s in the direct form, each operation rounded
+// separately: the debug exports' reference for entries on which the kernel's
+// weight test and the exact membership predicate disagree.
+__device__ __forceinline__ float direct_weight(float s, float inv_h2) {
+  const float t = fmaxf(1.0f - s * inv_h2, 0.0f);
+  return (t * t) * t;
+}
 
 // Walk the stencil of HR position (x, y, z) and accumulate the weighted sums
 // over candidates of positive weight.  The float32 membership predicate
@@ -31,7 +41,7 @@ template <bool DEBUG, bool RIGID, bool TAPE = false>
 __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __restrict__ lr,
                                        const uint32_t* __restrict__ cell_start, float x, float y,
                                        float z, uint32_t* ids, int64_t max_k) {
-  Sums r{0.f, 0.f, 0.f, 0.f, 0.f, false, 0u, 0xffffffffu};
+  Sums r{0.f, 0.f, 0.f, 0.f, 0.f, false, 0u, 0xffffffffu, 0u, 0.f};
   const int R = gc.reach;
   const int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
   const int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
@@ -53,9 +63,10 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
         const float dx = P.x - x, dy = P.y - y, dz = P.z - z;
         const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const float t = fmaxf(fmaf(-sq, gc.inv_h2, 1.0f), 0.0f);
+        const float w = t * t * t;
+        if (DEBUG) r.count_w += w > 0.0f ? 1u : 0u;
         if (t > 0.0f) {
           const float4 V = lr[j].v;
-          const float w = t * t * t;
           r.S += w;
           r.Ux = fmaf(w, V.x, r.Ux);
           r.Uy = fmaf(w, V.y, r.Uy);
@@ -69,13 +80,15 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
         // support membership (the exact predicate) decides the rigid rule
         // and the neighbour lists
         if (DEBUG || (RIGID && !r.gran && P.w == 0.0f)) {
-          if (sq_dist(P.x, P.y, P.z, x, y, z) < gc.h2) {
+          const float s = sq_dist(P.x, P.y, P.z, x, y, z);
+          if (s < gc.h2) {
             r.gran |= (P.w == 0.0f);
             if (DEBUG) {
               if (ids != nullptr && (int64_t)r.count < max_k) ids[r.count] = __float_as_uint(lr[j].v.w);
               r.count += 1u;
             }
           }
+          if (DEBUG && ((s < gc.h2) != (w > 0.0f))) r.wdis = fmaxf(r.wdis, fmaxf(w, direct_weight(s, gc.inv_h2)));
         }
       }
     }
@@ -273,30 +286,61 @@ constexpr int kGatherRows = 64;
 template <int G>
 using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries / G : 64), kGatherRows>;
 
-// Staging of the dot-product form: q = X - c relative to the wave's box
-// centre c and B = -|q|^2 / h^2, so that for a lane at p = x - c
-//   u = 1 - |q - p|^2 / h^2 = (1 - |p|^2 / h^2) + B + (2 / h^2) p . q
-// takes one add and three fmas per candidate.  Used only for waves whose box
-// is at most 2h wide, where the cancellation stays far below the tolerance.
-struct DotStage {
+// The cull of a one-group wave in centred form: candidates are tested on
+// q = X - c against the wave box's centre c and half-extents (tile_visit),
+// and the list keeps their absolute positions.  Lanes then evaluate the
+// weight in the direct form d = X_j - x_i, 1 - |d|^2 / h^2, whose argument
+// is accurate to a few float32 units of 1.  (An expanded dot-product form,
+// (1 - |p|^2/h^2) - |q|^2/h^2 + 2 p.q / h^2 relative to the box centre, saves
+// three operations per entry but cancels terms as large as 12 for boxes 2h
+// wide, with errors of several 1e-6 in the argument: more than the per-step
+// velocity tolerance allows in dense supports.)
+struct CentredCull : PlainStage {
   static constexpr bool kCentred = true;
-  float cx, cy, cz, inv_h2;
+  float cx, cy, cz;
   float hx, hy, hz;  // half-extents of the wave box
-  __device__ __forceinline__ float4 centred(float qx, float qy, float qz) const {
-    return make_float4(qx, qy, qz, -(fmaf(qz, qz, fmaf(qy, qy, qx * qx)) * inv_h2));
-  }
-  __device__ __forceinline__ float4 operator()(float4 P, uint32_t) const {
-    return centred(P.x - cx, P.y - cy, P.z - cz);
-  }
-  __device__ __forceinline__ float4 pad() const { return make_float4(0.0f, 0.0f, 0.0f, -3.0e38f); }
-  __device__ __forceinline__ float4 vel(float4 V) const { return V; }
+  __device__ __forceinline__ float4 centred(float4 P, uint32_t bits) const { return (*this)(P, bits); }
 };
 
 // Velocity entries (V_j, 1): with them the sums (Ux, Uy, Uz, S) of a wave are
 // one matrix product, weights (64 lanes x entries) times entries (entries x 4).
 template <class Base>
 struct WithOnes : Base {
-  __device__ __forceinline__ float4 vel(float4 V) const { return make_float4(V.x, V.y, V.z, 1.0f); }
+  __device__ __forceinline__ float4 vel(float4 V, uint32_t /*bits*/) const { return make_float4(V.x, V.y, V.z, 1.0f); }
+};
+
+// Debug twin of a stage: the velocity entry keeps the candidate's sorted
+// index in .w (padding: all ones), so that the walk can look up the
+// candidate's absolute position for the exact predicate.  Culling and the
+// position entries are the base stage's.
+template <class Base>
+struct WithSortedIndex : Base {
+  __device__ __forceinline__ float4 vel(float4 V, uint32_t bits) const {
+    return make_float4(V.x, V.y, V.z, __uint_as_float(bits & 0x7fffffffu));
+  }
+  __device__ __forceinline__ float4 pad_vel() const { return make_float4(0.f, 0.f, 0.f, __uint_as_float(~0u)); }
+};
+
+// Member accounting of the debug instance of the step kernel, per lane.
+struct DebugWalk {
+  uint32_t* ids;  // this lane's id row, or null (idle lanes, no id export)
+  int64_t max_k;
+  uint32_t count, count_w;
+  float wdis;
+  // One list entry: w as the kernel computed it, the candidate's absolute
+  // position P and original index.
+  __device__ __forceinline__ void see(float w, float px, float py, float pz, uint32_t orig, float x, float y,
+                                      float z, const GridConst& gc) {
+    const float s = sq_dist(px, py, pz, x, y, z);
+    const bool member = s < gc.h2;
+    const bool pos = w > 0.0f;
+    if (member) {
+      if (ids != nullptr && (int64_t)count < max_k) ids[count] = orig;
+      count += 1u;
+    }
+    count_w += pos ? 1u : 0u;
+    if (member != pos) wdis = fmaxf(wdis, fmaxf(w, direct_weight(s, gc.inv_h2)));
+  }
 };
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -372,9 +416,14 @@ __device__ __forceinline__ HRLane load_lane(const AdvanceArgs& a, int64_t first)
 // One block-sized tile of HR particles first .. first + kBlock - 1 (those
 // below a.n are live; the rest shadow the last particle and write nothing).
 // TAPE: also record (S, Ux, Uy, Uz, M, argmax) per particle for the adjoint.
-template <bool RIGID, int G, bool TAPE = false, class WP>
+// DBG: the same arithmetic, plus per-lane member exports (AdvanceArgs dbg_*):
+// the exact predicate on every list entry (or stencil candidate), the count
+// of entries of positive computed weight and the largest weight on which the
+// two disagree.
+template <bool RIGID, int G, bool TAPE = false, bool DBG = false, class WP>
 __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
                                              GatherLDS<G>& lds, int64_t first, const HRLane& st) {
+  static_assert(!(TAPE && DBG), "the debug instance records no tape");
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool live = first + (int64_t)threadIdx.x < a.n;  // idle lanes shadow the last particle
@@ -388,11 +437,21 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
   // weight and, among equal weights, the smallest index
   uint64_t key = 0ull;
   WallCull wc = all_walls();
+  DebugWalk dw{nullptr, 0, 0u, 0u, 0.0f};
+  if (DBG && live && a.dbg_ids != nullptr) {
+    dw.ids = a.dbg_ids + (first + (int64_t)threadIdx.x) * a.dbg_max_k;
+    dw.max_k = a.dbg_max_k;
+  }
   const TileSetup<G> ts = tile_setup<G>(gc, a.cell_start, x, y, z, lane, wid, lds);
   if (ts.nrows > lds.kRows || ts.total > (uint32_t)a.tile_max) {
     // spread-out wave: every lane walks its own stencil
-    const Sums s = gather<false, RIGID, TAPE>(gc, a.lr, a.cell_start, x, y, z, nullptr, 0);
+    const Sums s = gather<DBG, RIGID, TAPE>(gc, a.lr, a.cell_start, x, y, z, dw.ids, dw.max_k);
     S = s.S; Ux = s.Ux; Uy = s.Uy; Uz = s.Uz; M = s.M; arg = s.arg;
+    if (DBG) {
+      dw.count = s.count;
+      dw.count_w = s.count_w;
+      dw.wdis = s.wdis;
+    }
   } else {
     const float inv_h2 = gc.inv_h2;
     bool gran = !RIGID;
@@ -404,7 +463,6 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
       lo0 = fminf(lo0, ts.gb[g].lo[0]); lo1 = fminf(lo1, ts.gb[g].lo[1]); lo2 = fminf(lo2, ts.gb[g].lo[2]);
       hi0 = fmaxf(hi0, ts.gb[g].hi[0]); hi1 = fmaxf(hi1, ts.gb[g].hi[1]); hi2 = fmaxf(hi2, ts.gb[g].hi[2]);
     }
-    const float ext = fmaxf(hi0 - lo0, fmaxf(hi1 - lo1, hi2 - lo2));
     wc = wall_cull(gc, a.wall_mask, ts.bx0, ts.bx1, ts.by0, ts.by1, ts.bz0, ts.bz1);
     if (!RIGID) {
       // weights in the vector unit, sums on the matrix cores
@@ -418,6 +476,14 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
       // .w for the argmax, and lanes of component 3 use 1 instead.
       auto take = [&](float w, const float* lvf, uint32_t c) {
         float b = lvf[4 * c + comp];
+        if (DBG) {
+          b = comp == 3 ? 1.0f : b;
+          const uint32_t jb = __float_as_uint(lvf[4 * c + 3]);
+          if (jb != ~0u) {
+            const LRPoint& P = a.lr[jb];
+            dw.see(w, P.p.x, P.p.y, P.p.z, __float_as_uint(P.v.w), x, y, z, gc);
+          }
+        }
         if (TAPE) {
           b = comp == 3 ? 1.0f : b;
           const uint32_t id = __float_as_uint(lvf[4 * c + 3]);
@@ -428,46 +494,35 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
         }
         acc = mfma_entry(w, b, acc);
       };
-      if (ext * ext <= 4.0f * gc.h2) {
-        const DotStage ds{0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2), inv_h2,
-                          0.5f * (hi0 - lo0), 0.5f * (hi1 - lo1), 0.5f * (hi2 - lo2)};
-        const float px = x - ds.cx, py = y - ds.cy, pz = z - ds.cz;
-        const float A = fmaf(-fmaf(pz, pz, fmaf(py, py, px * px)), inv_h2, 1.0f);
-        const float k2 = 2.0f * inv_h2;
-        const float Px = k2 * px, Py = k2 * py, Pz = k2 * pz;
-        using Stage = std::conditional_t<TAPE, DotStage, WithOnes<DotStage>>;
-        tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
-          const float* lvf = reinterpret_cast<const float*>(lv);
-          auto step = [&](uint32_t c) {
-            const float4 Q = lp[c];
-            take(cube01(fmaf(Q.x, Px, fmaf(Q.y, Py, fmaf(Q.z, Pz, A + Q.w)))), lvf, c);
-          };
-          // eight entries per trip (one address update), then a last four
-          uint32_t c0 = 0;
-          for (; c0 + 8u <= nc; c0 += 8u) {
+      auto walk = [&](uint32_t nc, const float4* lp, const float4* lv) {
+        const float* lvf = reinterpret_cast<const float*>(lv);
+        auto step = [&](uint32_t c) {
+          const float4 Q = lp[c];
+          const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
+          const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          take(cube01(fmaf(-sq, inv_h2, 1.0f)), lvf, c);
+        };
+        // eight entries per trip (one address update), then a last four
+        uint32_t c0 = 0;
+        for (; c0 + 8u <= nc; c0 += 8u) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) step(c0 + (uint32_t)k);
-          }
-          if (c0 < nc) {
+          for (int k = 0; k < 8; ++k) step(c0 + (uint32_t)k);
+        }
+        if (c0 < nc) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) step(c0 + (uint32_t)k);
-          }
-        }, SortedTag(), Stage{ds});
+          for (int k = 0; k < 4; ++k) step(c0 + (uint32_t)k);
+        }
+      };
+      if (G == 1) {
+        const CentredCull cc{{}, 0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2),
+                             0.5f * (hi0 - lo0), 0.5f * (hi1 - lo1), 0.5f * (hi2 - lo2)};
+        using Stage = std::conditional_t<DBG, WithSortedIndex<CentredCull>,
+                                         std::conditional_t<TAPE, CentredCull, WithOnes<CentredCull>>>;
+        tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, walk, SortedTag(), Stage{cc});
       } else {
-        using Stage = std::conditional_t<TAPE, PlainStage, WithOnes<PlainStage>>;
-        tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
-          const float* lvf = reinterpret_cast<const float*>(lv);
-          for (uint32_t c0 = 0; c0 < nc; c0 += 4) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const uint32_t c = c0 + (uint32_t)k;
-              const float4 Q = lp[c];
-              const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
-              const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-              take(cube01(fmaf(-sq, inv_h2, 1.0f)), lvf, c);
-            }
-          }
-        }, SortedTag(), Stage{});
+        using Stage = std::conditional_t<DBG, WithSortedIndex<PlainStage>,
+                                         std::conditional_t<TAPE, PlainStage, WithOnes<PlainStage>>>;
+        tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, walk, SortedTag(), Stage{});
       }
       if (!TAPE) M = __int_as_float(Mb);
       quad_sums(acc, lane, Ux, Uy, Uz, S);
@@ -490,6 +545,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
           } else {
             M = fmaxf(M, w);
           }
+          if (DBG && Q.x < 1.0e38f) dw.see(w, Q.x, Q.y, Q.z, __float_as_uint(W.w), x, y, z, gc);
           if (RIGID) {
             const uint32_t bits = __float_as_uint(Q.w);
             // exact membership of a granular LR particle decides the rigid rule
@@ -511,6 +567,12 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
     bool A;
     const uint32_t o = threadIdx.x;
     finish(a, walls, first, o, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M, &A, wc);
+    if (DBG) {
+      const int64_t i = first + (int64_t)o;
+      if (a.dbg_count != nullptr) a.dbg_count[i] = dw.count;
+      if (a.dbg_count_w != nullptr) a.dbg_count_w[i] = dw.count_w;
+      if (a.dbg_wdis != nullptr) a.dbg_wdis[i] = dw.wdis;
+    }
     if (TAPE) {
       const int64_t m = a.n;
       float* const pt = a.tape + first;
@@ -526,11 +588,11 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
 
 // Seven waves per SIMD asked of the register allocator; with four lane groups
 // the LDS lists (35 KB per block) allow four.
-template <bool RIGID, int G, bool TAPE = false>
+template <bool RIGID, int G, bool TAPE = false, bool DBG = false>
 __global__ __launch_bounds__(kBlock, G == 4 ? 4 : 7) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
   __shared__ GatherLDS<G> lds;
   const int64_t first = (int64_t)blockIdx.x * kBlock;
-  advance_tile<RIGID, G, TAPE>(a, wt.w, lds, first, load_lane(a, first));
+  advance_tile<RIGID, G, TAPE, DBG>(a, wt.w, lds, first, load_lane(a, first));
 }
 
 // Batched step: block k takes entries k, k + grid, ... of the (scene, first
@@ -558,6 +620,8 @@ __global__ __launch_bounds__(kBlock, 7) void k_advance_batched(BatchAdvanceArgs 
     a.dbg_ids = nullptr;
     a.dbg_max_k = 0;
     a.dbg_branch = nullptr;
+    a.dbg_count_w = nullptr;
+    a.dbg_wdis = nullptr;
     a.wall_mask = nullptr;
     a.groups = 1;
     a.tile_max = b.tile_max;
@@ -570,11 +634,19 @@ __global__ __launch_bounds__(kBlock, 7) void k_advance_batched(BatchAdvanceArgs 
 
 }  // namespace
 
-hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool debug, hipStream_t st) {
+hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, int debug, hipStream_t st) {
   if (a.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((a.n + kBlock - 1) / kBlock);
-  if (debug)
+  if (debug == 1)
     hipLaunchKernelGGL(k_advance<true>, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  else if (debug == 2 && a.sc.has_rigid)
+    hipLaunchKernelGGL((k_advance_tiled<true, 1, false, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  else if (debug == 2 && a.groups == 4)
+    hipLaunchKernelGGL((k_advance_tiled<false, 4, false, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  else if (debug == 2 && a.groups == 2)
+    hipLaunchKernelGGL((k_advance_tiled<false, 2, false, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+  else if (debug == 2)
+    hipLaunchKernelGGL((k_advance_tiled<false, 1, false, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
   else if (a.tape != nullptr && a.sc.has_rigid)
     hipLaunchKernelGGL((k_advance_tiled<true, 1, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
   else if (a.tape != nullptr)

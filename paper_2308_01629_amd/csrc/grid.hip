@@ -44,13 +44,34 @@ __device__ __forceinline__ uint32_t claim_slot(uint32_t k, bool valid, uint32_t*
   return base + (uint32_t)(lane - start);
 }
 
-__global__ __launch_bounds__(kBlock) void k_keys_count(GridConst gc, const float* __restrict__ x,
+// An LR frame at the HR time level: frame a, or with a second frame b the
+// linear interpolation a + theta (b - a) in time, each operation rounded
+// separately (the boundary's float32 arithmetic; the key and the sorted copy
+// compute it identically).
+struct FramePair {
+  const float* x0;
+  const float* v0;
+  const float* x1;  // null: the frame is x0, v0 itself
+  const float* v1;
+  float theta;
+};
+__device__ __forceinline__ float frame_at(const float* a, const float* b, float theta, int64_t k) {
+  if (b == nullptr) return a[k];
+  const float a0 = a[k];
+  const float d = b[k] - a0;
+  const float p = theta * d;
+  return a0 + p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys_count(GridConst gc, FramePair f,
                                                        int64_t n, uint32_t* __restrict__ keys,
                                                        uint32_t* __restrict__ slot,
                                                        uint32_t* __restrict__ counts) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool valid = i < n;
-  const uint32_t k = valid ? cell_key(gc, x[i], x[n + i], x[2 * n + i]) : 0u;
+  const uint32_t k = valid ? cell_key(gc, frame_at(f.x0, f.x1, f.theta, i), frame_at(f.x0, f.x1, f.theta, n + i),
+                                      frame_at(f.x0, f.x1, f.theta, 2 * n + i))
+                           : 0u;
   const uint32_t sl = claim_slot(k, valid, counts);
   if (valid) {
     keys[i] = k;
@@ -196,8 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
 __global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ tmp,
                                                    const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ cell_start, int64_t n,
-                                                   const float* __restrict__ x,
-                                                   const float* __restrict__ v,
+                                                   FramePair f,
                                                    const uint8_t* __restrict__ rigid,
                                                    uint32_t* __restrict__ perm,
                                                    LRPoint* __restrict__ out) {
@@ -215,8 +235,10 @@ __global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ 
   perm[dst] = i;
   float flag = (rigid != nullptr && rigid[i] != 0) ? 1.0f : 0.0f;
   LRPoint o;
-  o.p = make_float4(x[i], x[n + i], x[2 * n + i], flag);
-  o.v = make_float4(v[i], v[n + i], v[2 * n + i], __uint_as_float(i));
+  o.p = make_float4(frame_at(f.x0, f.x1, f.theta, i), frame_at(f.x0, f.x1, f.theta, n + i),
+                    frame_at(f.x0, f.x1, f.theta, 2 * n + i), flag);
+  o.v = make_float4(frame_at(f.v0, f.v1, f.theta, i), frame_at(f.v0, f.v1, f.theta, n + i),
+                    frame_at(f.v0, f.v1, f.theta, 2 * n + i), __uint_as_float(i));
   out[dst] = o;
 }
 
@@ -558,11 +580,10 @@ hipError_t scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t
 
 }  // namespace
 
-hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float* lr_v,
-                             const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
-                             const GridScratch& s, hipStream_t st) {
+static hipError_t build_grid(const GridConst& gc, const FramePair& f, const uint8_t* lr_rigid, int64_t n_lr,
+                             int64_t n_cells, const GridScratch& s, hipStream_t st) {
   if (n_lr > 0) {
-    hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, gc, lr_x, n_lr,
+    hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, gc, f, n_lr,
                        s.keys, s.slot, s.counts);
   }
   int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);
@@ -581,9 +602,44 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
   }
   if (n_lr > 0) {
     hipLaunchKernelGGL(k_stable, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, s.tmp, s.keys,
-                       s.cell_start, n_lr, lr_x, lr_v, lr_rigid, s.perm, s.lr_sorted);
+                       s.cell_start, n_lr, f, lr_rigid, s.perm, s.lr_sorted);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float* lr_v,
+                             const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
+                             const GridScratch& s, hipStream_t st) {
+  return build_grid(gc, FramePair{lr_x, lr_v, nullptr, nullptr, 0.0f}, lr_rigid, n_lr, n_cells, s, st);
+}
+
+// The sorted LR copy as structure-of-arrays [3][n] (debug export).
+__global__ __launch_bounds__(kBlock) void k_unpack_sorted(const LRPoint* __restrict__ lr, int64_t n,
+                                                          float* __restrict__ x, float* __restrict__ v) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const LRPoint q = lr[j];
+  if (x != nullptr) {
+    x[j] = q.p.x;
+    x[n + j] = q.p.y;
+    x[2 * n + j] = q.p.z;
+  }
+  if (v != nullptr) {
+    v[j] = q.v.x;
+    v[n + j] = q.v.y;
+    v[2 * n + j] = q.v.z;
+  }
+}
+
+hipError_t launch_unpack_sorted(const LRPoint* lr, int64_t n, float* x, float* v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_unpack_sorted, dim3(blocks_for(n)), dim3(kBlock), 0, st, lr, n, x, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_grid_lerp(const GridConst& gc, const float* x0, const float* v0, const float* x1,
+                                  const float* v1, float theta, const uint8_t* lr_rigid, int64_t n_lr,
+                                  int64_t n_cells, const GridScratch& s, hipStream_t st) {
+  return build_grid(gc, FramePair{x0, v0, x1, v1, theta}, lr_rigid, n_lr, n_cells, s, st);
 }
 
 hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& s, hipStream_t st) {

@@ -24,6 +24,15 @@ struct GridScratch {
 hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float* lr_v,
                              const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
                              const GridScratch& s, hipStream_t st);
+// The same build of the LR state between two frames: x0 + theta (x1 - x0)
+// (and v alike), each float32 operation rounded separately, fused into the
+// keys and the sorted copy.
+hipError_t launch_build_grid_lerp(const GridConst& gc, const float* x0, const float* v0, const float* x1,
+                                  const float* v1, float theta, const uint8_t* lr_rigid, int64_t n_lr,
+                                  int64_t n_cells, const GridScratch& s, hipStream_t st);
+
+// The sorted LR copy as [3][n] positions and velocities (either may be null).
+hipError_t launch_unpack_sorted(const LRPoint* lr, int64_t n, float* x, float* v, hipStream_t st);
 
 // HR reorder by a space-filling key of fine cells (grid cells split into sub^3
 // sub-cells: Hilbert index, global Morton code, or cell then Morton order),
@@ -87,6 +96,8 @@ struct AdvanceArgs {
   uint32_t* dbg_ids;
   int64_t dbg_max_k;
   uint8_t* dbg_branch;
+  uint32_t* dbg_count_w;  // tiled debug: entries whose computed weight is > 0
+  float* dbg_wdis;        // tiled debug: largest weight where that test and membership disagree
   // [n_cells] per cell, bit k set when wall k can come within r_hr of the
   // cell's neighbourhood (cells c - reach - 1 .. c + reach + 1); null: every
   // wave tests every wall
@@ -95,7 +106,9 @@ struct AdvanceArgs {
   int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
   float* tape;   // [6][n] (S, Ux, Uy, Uz, M, argmax bits) or null
 };
-hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, bool debug, hipStream_t st);
+// debug: 0 the step kernel, 1 the per-lane walk with member exports, 2 the
+// step kernel's own template instance with member exports (same arithmetic)
+hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, int debug, hipStream_t st);
 
 // a9: batched step over many scenes in concatenated buffers.
 struct BatchScene {
@@ -148,6 +161,10 @@ hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& 
 
 // Host: validate one scene's parameters and compute its grid (runtime.hip).
 int check_scene_params(const upsample_params* p, upsample_grid_info* gi, std::string* why);
+// Host: the kernels' constants of a scene (runtime.hip).
+GridConst make_grid_const(const upsample_grid_info& gi);
+StepConst make_step_const(const upsample_params& p, bool has_rigid);
+WallTable make_wall_table(const float* walls, int n_walls);
 
 // a7: adjoint step.
 struct AdjointArgs {
@@ -173,8 +190,19 @@ struct AdjointArgs {
   int tiled;     // 1: wave-tiled kernel (non-rigid scenes), 0: one particle per lane
   int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
   const float* tape;  // forward record [6][n] (skips the recomputation of the sums) or null
+  // deterministic LR gradients (all null otherwise): per HR particle its
+  // adjoint coefficients [6][n] (dL/dU, dL/dS, dL/dM, argmax bits), and
+  // the HR particles sorted by the same cells
+  float* det_coef;
+  const uint32_t* hr_cell_start;  // set by launch_adjoint from hr_grid
+  const LRPoint* hr_sorted;
 };
-hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st);
+// With a.det_coef set (and hr_grid, scratch for max_hr particles over the
+// same cells): the HR pass writes the coefficients instead of adding LR
+// gradients, the HR grid is built into *hr_grid, and one wave per LR particle
+// sums its HR neighbours' terms in a fixed order (no atomics).
+hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st,
+                          const GridScratch* hr_grid = nullptr);
 
 // VALIDATE flag: sets *flag to 1 if any of the n floats is NaN or Inf.
 hipError_t launch_check_finite(const float* p, int64_t n, uint32_t* flag, hipStream_t st);

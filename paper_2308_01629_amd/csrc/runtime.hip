@@ -36,6 +36,9 @@ struct upsample_handle_s {
   int32_t* run_perm;
   uint32_t* finite_flag;
   float* g_sorted;      // [6][max_lr] adjoint LR gradients by sorted index, zero between calls
+  GridScratch hr_g;     // DETERMINISTIC_BWD: HR particles sorted by cell (max_hr)
+  float* det_coef;      // DETERMINISTIC_BWD: [6][max_hr] adjoint coefficients per HR particle
+  bool hr_g_dirty;      // a failed deterministic backward may have left hr_g.counts non-zero
   uint32_t* wall_mask;  // [n_cells] walls near each cell's neighbourhood, or null
   bool grid_valid;
   bool counts_dirty;     // an interrupted build may have left counts non-zero
@@ -141,7 +144,10 @@ int validate_params(const upsample_params* p, std::string* why) {
     *why = "capacities must be below 2^31";
     return UPSAMPLE_ERR_INVALID_ARG;
   }
-  if ((p->flags & ~UPSAMPLE_FLAG_VALIDATE) != 0u) { *why = "unknown flag bits"; return UPSAMPLE_ERR_INVALID_ARG; }
+  if ((p->flags & ~(UPSAMPLE_FLAG_VALIDATE | UPSAMPLE_FLAG_DETERMINISTIC_BWD)) != 0u) {
+    *why = "unknown flag bits";
+    return UPSAMPLE_ERR_INVALID_ARG;
+  }
   upsample_grid_info gi;
   return compute_grid(p, &gi, why);
 }
@@ -156,10 +162,16 @@ void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
                   h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.src, h->hs.x,
                   h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum,
-                  h->finite_flag, h->run_perm, h->wall_mask, h->g_sorted};
+                  h->finite_flag, h->run_perm, h->wall_mask, h->g_sorted, h->det_coef};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
   for (const GridScratch& g : h->run_g) {
+    void* rq[] = {g.keys, g.slot, g.tmp, g.perm, g.counts, g.local, g.chunk_sum, g.cell_start, g.lr_sorted};
+    for (void* q : rq)
+      if (q != nullptr) (void)hipFree(q);
+  }
+  {
+    const GridScratch& g = h->hr_g;
     void* rq[] = {g.keys, g.slot, g.tmp, g.perm, g.counts, g.local, g.chunk_sum, g.cell_start, g.lr_sorted};
     for (void* q : rq)
       if (q != nullptr) (void)hipFree(q);
@@ -214,38 +226,11 @@ std::vector<uint32_t> wall_masks(const upsample_handle h) {
   return m;
 }
 
-GridConst grid_const(const upsample_handle h) {
-  GridConst gc;
-  for (int a = 0; a < 3; ++a) {
-    gc.lo[a] = h->gi.lo[a];
-    gc.dims[a] = h->gi.dims[a];
-  }
-  gc.inv_cs = h->gi.inv_cell_size;
-  gc.cs = (float)h->gi.cell_size;
-  gc.reach = h->gi.reach;
-  gc.h2 = h->gi.h2;
-  gc.inv_h2 = h->gi.inv_h2;
-  return gc;
-}
+GridConst grid_const(const upsample_handle h) { return make_grid_const(h->gi); }
 
-StepConst step_const(const upsample_handle h) {
-  StepConst sc;
-  sc.c1 = h->p.c1;
-  sc.c2 = h->p.c2;
-  sc.dt = h->p.dt;
-  sc.r_hr = h->p.r_hr;
-  for (int a = 0; a < 3; ++a) sc.g[a] = h->p.g[a];
-  sc.n_walls = h->p.n_walls;
-  sc.has_rigid = h->has_rigid ? 1 : 0;
-  return sc;
-}
+StepConst step_const(const upsample_handle h) { return make_step_const(h->p, h->has_rigid); }
 
-WallTable wall_table(const upsample_handle h) {
-  WallTable wt;
-  std::memset(&wt, 0, sizeof(wt));
-  std::memcpy(wt.w, h->walls, sizeof(float) * UPSAMPLE_WALL_FLOATS * h->p.n_walls);
-  return wt;
-}
+WallTable wall_table(const upsample_handle h) { return make_wall_table(h->walls, h->p.n_walls); }
 
 int check_device(upsample_handle h) {
   int cur = -1;
@@ -279,6 +264,39 @@ int check_scene_params(const upsample_params* p, upsample_grid_info* gi, std::st
   const int rc = validate_params(p, why);
   if (rc != UPSAMPLE_OK) return rc;
   return compute_grid(p, gi, why);
+}
+
+GridConst make_grid_const(const upsample_grid_info& gi) {
+  GridConst gc;
+  for (int a = 0; a < 3; ++a) {
+    gc.lo[a] = gi.lo[a];
+    gc.dims[a] = gi.dims[a];
+  }
+  gc.inv_cs = gi.inv_cell_size;
+  gc.cs = (float)gi.cell_size;
+  gc.reach = gi.reach;
+  gc.h2 = gi.h2;
+  gc.inv_h2 = gi.inv_h2;
+  return gc;
+}
+
+StepConst make_step_const(const upsample_params& p, bool has_rigid) {
+  StepConst sc;
+  sc.c1 = p.c1;
+  sc.c2 = p.c2;
+  sc.dt = p.dt;
+  sc.r_hr = p.r_hr;
+  for (int a = 0; a < 3; ++a) sc.g[a] = p.g[a];
+  sc.n_walls = p.n_walls;
+  sc.has_rigid = has_rigid ? 1 : 0;
+  return sc;
+}
+
+WallTable make_wall_table(const float* walls, int n_walls) {
+  WallTable wt;
+  std::memset(&wt, 0, sizeof(wt));
+  if (n_walls > 0) std::memcpy(wt.w, walls, sizeof(float) * UPSAMPLE_WALL_FLOATS * n_walls);
+  return wt;
 }
 
 }  // namespace ups
@@ -405,6 +423,19 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   ALLOC(h->g_sorted, 6 * nl)
   const bool cull_walls = p->n_walls > 0 && h->n_cells <= kWallMaskMaxCells;
   if (cull_walls) ALLOC(h->wall_mask, h->n_cells)
+  const bool det = (p->flags & UPSAMPLE_FLAG_DETERMINISTIC_BWD) != 0u;
+  if (det) {
+    ALLOC(h->hr_g.keys, nh)
+    ALLOC(h->hr_g.slot, nh)
+    ALLOC(h->hr_g.tmp, nh)
+    ALLOC(h->hr_g.perm, nh)
+    ALLOC(h->hr_g.counts, h->n_cells)
+    ALLOC(h->hr_g.local, h->n_cells)
+    ALLOC(h->hr_g.chunk_sum, h->n_chunks + 1)
+    ALLOC(h->hr_g.cell_start, h->n_cells + 1)
+    ALLOC(h->hr_g.lr_sorted, nh)
+    ALLOC(h->det_coef, 6 * nh)
+  }
 #undef ALLOC
   if (e == hipSuccess && cull_walls) {
     const std::vector<uint32_t> m = wall_masks(h);
@@ -413,6 +444,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
   if (e == hipSuccess) e = hipMemset(h->g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells);
   if (e == hipSuccess) e = hipMemset(h->hs.counts, 0, sizeof(uint32_t) * (size_t)n_bins);
   if (e == hipSuccess && nl > 0) e = hipMemset(h->g_sorted, 0, sizeof(float) * (size_t)(6 * nl));
+  if (e == hipSuccess && det) e = hipMemset(h->hr_g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells);
   for (int k = 0; k < 2 * kTimingRing && e == hipSuccess; ++k) e = hipEventCreate(&h->ev[k]);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -514,10 +546,13 @@ static hipError_t timing_close(upsample_handle h, hipStream_t st) {
   return e;
 }
 
+// debug: 0 the step, 1 the per-lane debug walk, 2 the step kernel's debug
+// instance (count_w, wdis: its extra exports)
 static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
-                        float* hr_v_out, int64_t n_hr, void* stream, bool debug, uint32_t* count,
+                        float* hr_v_out, int64_t n_hr, void* stream, int debug, uint32_t* count,
                         uint32_t* ids, int64_t max_k, uint8_t* branch, float* tape = nullptr,
-                        const GridScratch* grid = nullptr) {
+                        const GridScratch* grid = nullptr, uint32_t* count_w = nullptr,
+                        float* wdis = nullptr) {
   if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
   if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
   if (n_hr > 0 && (hr_x == nullptr || hr_v == nullptr || hr_x_out == nullptr || hr_v_out == nullptr))
@@ -547,12 +582,14 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
   a.dbg_ids = ids;
   a.dbg_max_k = max_k;
   a.dbg_branch = branch;
+  a.dbg_count_w = count_w;
+  a.dbg_wdis = wdis;
   a.wall_mask = h->tune.wall_cull != 0 ? h->wall_mask : nullptr;
   a.groups = h->tune.gather_groups;
   a.tile_max = h->tune.tile_max;
   a.tape = tape;
   // timed on its own unless the caller (upsample_run) has a pair open
-  const bool timed = h->timing && !debug && n_hr > 0;
+  const bool timed = h->timing && debug == 0 && n_hr > 0;
   const bool own = timed && h->seg_n < 0;
   hipError_t e = own ? timing_open(h, st) : hipSuccess;
   if (e == hipSuccess) e = launch_advance(a, wall_table(h), debug, st);
@@ -565,7 +602,7 @@ static int advance_impl(upsample_handle h, const float* hr_x, const float* hr_v,
 int upsample_advance(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
                      float* hr_v_out, int64_t n_hr, void* stream) {
   if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
-  return advance_impl(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream, false, nullptr, nullptr, 0,
+  return advance_impl(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream, 0, nullptr, nullptr, 0,
                       nullptr);
 }
 
@@ -593,7 +630,7 @@ int upsample_step_taped(upsample_handle h, const float* lr_x, const float* lr_v,
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR or tape pointer is NULL");
   int rc = upsample_build_grid(h, lr_x, lr_v, lr_rigid, n_lr, stream);
   if (rc != UPSAMPLE_OK) return rc;
-  return advance_impl(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream, false, nullptr, nullptr, 0, nullptr,
+  return advance_impl(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream, 0, nullptr, nullptr, 0, nullptr,
                       tape);
 }
 
@@ -635,15 +672,23 @@ static int backward_impl(upsample_handle h, const float* lr_x, const float* lr_v
   a.tiled = h->tune.adjoint_tiled;
   a.tile_max = h->tune.adjoint_tile_max;
   a.tape = tape;
+  const bool det = (h->p.flags & UPSAMPLE_FLAG_DETERMINISTIC_BWD) != 0u;
+  a.det_coef = det ? h->det_coef : nullptr;
+  a.hr_cell_start = nullptr;
+  a.hr_sorted = nullptr;
   hipError_t e = hipSuccess;
   if (h->g_sorted_dirty && n_lr > 0)
     e = hipMemsetAsync(h->g_sorted, 0, sizeof(float) * (size_t)(6 * h->p.max_lr), st);
+  if (e == hipSuccess && det && h->hr_g_dirty)
+    e = hipMemsetAsync(h->hr_g.counts, 0, sizeof(uint32_t) * (size_t)h->n_cells, st);
   if (e == hipSuccess) {
     h->g_sorted_dirty = true;
-    e = launch_adjoint(a, wall_table(h), st);
+    h->hr_g_dirty = det;
+    e = launch_adjoint(a, wall_table(h), st, det ? &h->hr_g : nullptr);
   }
   if (e != hipSuccess) return hip_fail(h, e, "step_backward");
   h->g_sorted_dirty = false;
+  h->hr_g_dirty = false;
   return UPSAMPLE_OK;
 }
 
@@ -716,11 +761,68 @@ static int run_prepare(upsample_handle h, hipStream_t st) {
   return UPSAMPLE_OK;
 }
 
+// The LR state one step of a run uses: frame x0, v0, or with x1, v1 the
+// interpolation x0 + theta (x1 - x0) between two frames.
+struct RunFrame {
+  const float* x0;
+  const float* v0;
+  const float* x1;
+  const float* v1;
+  float theta;
+};
+
+static int run_impl(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                    int64_t n_lr, int32_t n_frames, const std::vector<RunFrame>& steps, float* hr_x, float* hr_v,
+                    int64_t n_hr, int32_t sort_every, int32_t* perm_io, void* stream);
+
 int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid, int64_t n_lr,
                  int32_t n_frames, float* hr_x, float* hr_v, int64_t n_hr, int32_t sort_every, int32_t* perm_io,
                  void* stream) {
   if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
   if (n_frames < 1) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_frames < 1");
+  if (n_lr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "negative count");
+  std::vector<RunFrame> steps((size_t)n_frames);
+  const size_t frame = 3 * (size_t)n_lr;
+  for (int32_t f = 0; f < n_frames; ++f)
+    steps[(size_t)f] = RunFrame{lr_x + frame * (size_t)f, lr_v + frame * (size_t)f, nullptr, nullptr, 0.0f};
+  return run_impl(h, lr_x, lr_v, lr_rigid, n_lr, n_frames, steps, hr_x, hr_v, n_hr, sort_every, perm_io, stream);
+}
+
+int upsample_run_multirate(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                           int64_t n_lr, int32_t n_frames, double t_lr0, double dt_lr, double t_hr0,
+                           int32_t n_steps, float* hr_x, float* hr_v, int64_t n_hr, int32_t sort_every,
+                           int32_t* perm_io, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_frames < 2) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_frames < 2");
+  if (n_steps < 1) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_steps < 1");
+  if (n_lr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "negative count");
+  if (!(std::isfinite(t_lr0) && std::isfinite(t_hr0) && std::isfinite(dt_lr) && dt_lr > 0.0))
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "t_lr0, t_hr0 must be finite and dt_lr > 0");
+  // the schedule, in double: step n ends at t_hr0 + (n + 1) dt and uses the
+  // LR state there, between frames k and k + 1
+  std::vector<RunFrame> steps((size_t)n_steps);
+  const size_t frame = 3 * (size_t)n_lr;
+  for (int32_t n = 0; n < n_steps; ++n) {
+    const double t = t_hr0 + (double)(n + 1) * (double)h->p.dt;
+    const double sf = (t - t_lr0) / dt_lr;
+    double k = std::floor(sf);
+    double th = sf - k;
+    if (k == (double)(n_frames - 1) && th == 0.0) {
+      k = (double)(n_frames - 2);
+      th = 1.0;
+    }
+    if (!(k >= 0.0 && k <= (double)(n_frames - 2)))
+      return fail(h, UPSAMPLE_ERR_INVALID_ARG, "an HR step ends outside the LR frames");
+    const size_t kk = (size_t)k;
+    steps[(size_t)n] = RunFrame{lr_x + frame * kk, lr_v + frame * kk, lr_x + frame * (kk + 1),
+                                lr_v + frame * (kk + 1), (float)th};
+  }
+  return run_impl(h, lr_x, lr_v, lr_rigid, n_lr, n_frames, steps, hr_x, hr_v, n_hr, sort_every, perm_io, stream);
+}
+
+static int run_impl(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
+                    int64_t n_lr, int32_t n_frames, const std::vector<RunFrame>& steps, float* hr_x, float* hr_v,
+                    int64_t n_hr, int32_t sort_every, int32_t* perm_io, void* stream) {
   if (sort_every < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "sort_every < 0");
   if (n_lr < 0 || n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "negative count");
   if (n_lr > h->p.max_lr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_lr exceeds max_lr");
@@ -753,8 +855,8 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
   GridScratch* buf[2 * kRunBatch];
   buf[0] = &h->g;
   for (int k = 1; k < 2 * kRunBatch; ++k) buf[k] = &h->run_g[k - 1];
-  const size_t frame = 3 * (size_t)n_lr;
-  const int n_batches = (n_frames + kRunBatch - 1) / kRunBatch;
+  const int n_steps = (int)steps.size();
+  const int n_batches = (n_steps + kRunBatch - 1) / kRunBatch;
   // the side stream starts after the caller's earlier work on the stream
   hipError_t e = hipEventRecord(h->entry, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->entry, 0);
@@ -763,9 +865,10 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
     hipError_t r = hipStreamWaitEvent(h->side, h->consumed[set], 0);  // batch t - 2 is done with the set
     for (int j = 0; j < kRunBatch && r == hipSuccess; ++j) {
       const int f = t * kRunBatch + j;
-      if (f >= n_frames) break;
-      r = launch_build_grid(gc, lr_x + frame * (size_t)f, lr_v + frame * (size_t)f, lr_rigid, n_lr, h->n_cells,
-                            *buf[set * kRunBatch + j], h->side);
+      if (f >= n_steps) break;
+      const RunFrame& fr = steps[(size_t)f];
+      r = launch_build_grid_lerp(gc, fr.x0, fr.v0, fr.x1, fr.v1, fr.theta, lr_rigid, n_lr, h->n_cells,
+                                 *buf[set * kRunBatch + j], h->side);
     }
     if (r == hipSuccess) r = hipEventRecord(h->built[set], h->side);
     return r;
@@ -781,7 +884,7 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
     h->grid_n_lr = n_lr;
     for (int j = 0; j < kRunBatch && e == hipSuccess; ++j) {
       const int f = t * kRunBatch + j;
-      if (f >= n_frames) break;
+      if (f >= n_steps) break;
       const float* in_x = hr_x;
       const float* in_v = hr_v;
       if (sort_every > 0 && f % sort_every == 0 && n_hr > 0) {
@@ -804,7 +907,7 @@ int upsample_run(upsample_handle h, const float* lr_x, const float* lr_v, const 
         e = timing_open(h, st);
         if (e != hipSuccess) break;
       }
-      rc = advance_impl(h, in_x, in_v, hr_x, hr_v, n_hr, stream, false, nullptr, nullptr, 0, nullptr, nullptr,
+      rc = advance_impl(h, in_x, in_v, hr_x, hr_v, n_hr, stream, 0, nullptr, nullptr, 0, nullptr, nullptr,
                         buf[last]);
       if (rc != UPSAMPLE_OK) {
         h->counts_dirty = h->run_dirty = true;
@@ -906,6 +1009,14 @@ int upsample_debug_grid(upsample_handle h, uint32_t* keys, uint32_t* perm, uint3
   return UPSAMPLE_OK;
 }
 
+int upsample_debug_lr_sorted(upsample_handle h, float* x_sorted, float* v_sorted, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (!h->grid_valid) return fail(h, UPSAMPLE_ERR_STATE, "no LR grid built on this handle");
+  hipError_t e = launch_unpack_sorted(h->g.lr_sorted, h->grid_n_lr, x_sorted, v_sorted, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(h, e, "debug_lr_sorted");
+  return UPSAMPLE_OK;
+}
+
 int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* hr_v, int64_t n_hr,
                              uint32_t* count, uint32_t* ids, int64_t max_k, uint8_t* branch,
                              void* stream) {
@@ -913,7 +1024,17 @@ int upsample_debug_neighbors(upsample_handle h, const float* hr_x, const float* 
   if (n_hr > 0 && ids != nullptr && max_k <= 0)
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "ids needs max_k > 0");
   // The debug walk writes the stepped state to the handle's HR sort scratch.
-  return advance_impl(h, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, stream, true, count, ids, max_k, branch);
+  return advance_impl(h, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, stream, 1, count, ids, max_k, branch);
+}
+
+int upsample_debug_step_members(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
+                                float* hr_v_out, int64_t n_hr, uint32_t* count, uint32_t* ids, int64_t max_k,
+                                uint32_t* count_w, float* w_disagree, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (n_hr > 0 && ids != nullptr && max_k <= 0)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "ids needs max_k > 0");
+  return advance_impl(h, hr_x, hr_v, hr_x_out, hr_v_out, n_hr, stream, 2, count, ids, max_k, nullptr, nullptr,
+                      nullptr, count_w, w_disagree);
 }
 
 int upsample_set_tuning(upsample_handle h, const upsample_tuning* t) {

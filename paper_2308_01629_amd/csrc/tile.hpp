@@ -227,21 +227,22 @@ struct PlainStage {
     return make_float4(P.x, P.y, P.z, __uint_as_float(bits));
   }
   __device__ __forceinline__ float4 pad() const { return make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.0f); }
-  __device__ __forceinline__ float4 vel(float4 V) const { return V; }
+  __device__ __forceinline__ float4 vel(float4 V, uint32_t /*bits*/) const { return V; }
+  __device__ __forceinline__ float4 pad_vel() const { return make_float4(0.f, 0.f, 0.f, 0.f); }
 };
 
 // Stream the candidates and hand the LDS lists to visit(nc, p_list, v_list)
 // in chunks; p_list / v_list point at this lane's group list.  tag(row, k, j,
 // flag) gives the 32 bits stored in the .w of the position entry.
 // stage(P, tag) gives the 16 bytes stored for a kept candidate (culling
-// always uses its absolute position), stage.vel(V) its velocity entry and
-// stage.pad() the padding entry (whose velocity entry is zero).
+// always uses its absolute position), stage.vel(V, tag) its velocity entry,
+// stage.pad() the padding entry and stage.pad_vel() the padding's velocity
+// entry (zero for the step kernels).
 // Round > 1 pads every chunk to a multiple of Round entries, so that the
 // visitor can unroll by Round with immediate LDS offsets.
-// A stage with kCentred stores entries relative to the wave box's centre
-// (cx, cy, cz) and half-extents (hx, hy, hz); with one group the cull then
-// works on q = X - c, |q| - half per axis, and stage.centred(q) forms the
-// entry from the same q.
+// A stage with kCentred carries the wave box's centre (cx, cy, cz) and
+// half-extents (hx, hy, hz); with one group the cull then works on
+// q = X - c, |q| - half per axis, and stage.centred(P, tag) forms the entry.
 template <int G, int Round = 1, class L, class Visit, class Tag = SortedTag, class Stage = PlainStage>
 __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridConst& gc,
                                            const LRPoint* __restrict__ lr, int lane, int wid,
@@ -253,7 +254,7 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
   const float cull2 = gc.h2 * 1.001f;
   const float4 far_p = stage.pad();
   uint32_t carried = 0u;  // the row holding the round's first candidate
-  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 pad_v = stage.pad_vel();
   uint32_t cnt[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) cnt[g] = 0u;
@@ -294,7 +295,7 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
       const float dy = __builtin_amdgcn_fmed3f(fabsf(qy) - stage.hy, 0.0f, 1.0f);
       const float dz = __builtin_amdgcn_fmed3f(fabsf(qz) - stage.hz, 0.0f, 1.0f);
       keep[0] = valid & (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= cull2);  // no branch
-      pj = stage.centred(qx, qy, qz);
+      pj = stage.centred(P, bits);
     } else {
 #pragma unroll
       for (int g = 0; g < G; ++g) keep[g] = valid && box_dist2(ts.gb[g], P.x, P.y, P.z) <= cull2;
@@ -308,7 +309,7 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
         const uint32_t pos = cnt[g] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         lds.p[wid][g][pos] = pj;
-        lds.v[wid][g][pos] = stage.vel(V);
+        lds.v[wid][g][pos] = stage.vel(V, bits);
       }
       cnt[g] += (uint32_t)__popcll(m);
       nmax = max(nmax, cnt[g]);
@@ -319,7 +320,7 @@ __device__ __forceinline__ void tile_visit(const TileSetup<G>& ts, const GridCon
     for (int g = 0; g < G; ++g) {
       for (uint32_t q = cnt[g] + (uint32_t)lane; q < npad; q += 64u) {
         lds.p[wid][g][q] = far_p;
-        lds.v[wid][g][q] = zero4;
+        lds.v[wid][g][q] = pad_v;
       }
     }
     wave_lds_sync();

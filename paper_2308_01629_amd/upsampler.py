@@ -47,7 +47,8 @@ def _tape(t: torch.Tensor, n: int) -> torch.Tensor:
 
 def make_params(r_lr: float, r_hr: float, dt: float, g: Sequence[float], domain_lo, domain_hi,
                 walls=None, max_lr: int = 0, max_hr: int = 0, c1: float = 512.0 / 729.0,
-                c2: float = 0.6, cell_factor: float = 0.0, validate: bool = False):
+                c2: float = 0.6, cell_factor: float = 0.0, validate: bool = False,
+                deterministic_bwd: bool = False):
     """Params struct plus the host wall buffer that must outlive the call using it."""
     p = Params()
     lib().upsample_default_params(ctypes.byref(p))
@@ -64,7 +65,7 @@ def make_params(r_lr: float, r_hr: float, dt: float, g: Sequence[float], domain_
         p.n_walls = wbuf.shape[0]
         p.walls = wbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
     p.max_lr, p.max_hr = int(max_lr), int(max_hr)
-    p.flags = _lib.FLAG_VALIDATE if validate else 0
+    p.flags = (_lib.FLAG_VALIDATE if validate else 0) | (_lib.FLAG_DETERMINISTIC_BWD if deterministic_bwd else 0)
     return p, wbuf
 
 
@@ -107,11 +108,11 @@ class Upsampler:
 
     def __init__(self, r_lr: float, r_hr: float, dt: float, g, domain_lo, domain_hi, walls=None,
                  max_lr: int = 0, max_hr: int = 0, c1: float = 512.0 / 729.0, c2: float = 0.6,
-                 cell_factor: float = 0.0, validate: bool = False):
+                 cell_factor: float = 0.0, validate: bool = False, deterministic_bwd: bool = False):
         self._L = lib()
         self.kw = dict(r_lr=r_lr, r_hr=r_hr, dt=dt, g=tuple(g), domain_lo=tuple(domain_lo),
                        domain_hi=tuple(domain_hi), walls=walls, max_lr=max_lr, max_hr=max_hr, c1=c1,
-                       c2=c2, cell_factor=cell_factor, validate=validate)
+                       c2=c2, cell_factor=cell_factor, validate=validate, deterministic_bwd=deterministic_bwd)
         p, _wbuf = make_params(**self.kw)
         h = ctypes.c_void_p()
         check(self._L.upsample_init(ctypes.byref(p), ctypes.byref(h)))
@@ -243,6 +244,27 @@ class Upsampler:
                                          _ptr(hr_v), n, int(sort_every), _ptr(perm), _stream()))
         return hr_x, hr_v
 
+    def run_multirate(self, lr_x, lr_v, hr_x, hr_v, n_steps: int, dt_lr: float, t_lr0: float = 0.0,
+                      t_hr0: float = 0.0, sort_every: int = 0, lr_rigid=None, perm=None):
+        """Advance hr_x / hr_v in place by ``n_steps`` HR steps against LR
+        frames lr_x, lr_v [T, 3, N_L] at times t_lr0 + k dt_lr
+        (upsample_run_multirate)."""
+        if not (lr_x.is_cuda and lr_x.dtype == torch.float32 and lr_x.dim() == 3 and lr_x.shape[1] == 3
+                and lr_x.is_contiguous() and lr_v.shape == lr_x.shape and lr_v.is_contiguous()
+                and lr_v.dtype == torch.float32):
+            raise ValueError("lr_x, lr_v must be contiguous float32 device tensors [T, 3, N_L]")
+        T, nl = lr_x.shape[0], lr_x.shape[2]
+        _u8(lr_rigid, nl, "lr_rigid")
+        n = _soa(hr_x, "hr_x").shape[1]
+        _soa(hr_v, "hr_v")
+        if perm is not None and not (perm.dtype == torch.int32 and perm.shape == (n,) and perm.is_contiguous()):
+            raise ValueError("perm must be a contiguous int32 tensor of length N")
+        self._check(self._L.upsample_run_multirate(self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl, T,
+                                                   float(t_lr0), float(dt_lr), float(t_hr0), int(n_steps),
+                                                   _ptr(hr_x), _ptr(hr_v), n, int(sort_every), _ptr(perm),
+                                                   _stream()))
+        return hr_x, hr_v
+
     def sort_hr(self, hr_x, hr_v, with_perm: bool = True, out_x=None, out_v=None):
         """Reorders the HR state by the sub-cell key of the handle's tuning
         (Hilbert by default; upsample_sort_hr): in place by
@@ -280,6 +302,13 @@ class Upsampler:
         self._check(self._L.upsample_debug_grid(self._h, _ptr(keys), _ptr(perm), _ptr(cs), _stream()))
         return keys, perm, cs
 
+    def debug_lr_sorted(self, n_lr: int, device="cuda"):
+        """The last build's LR positions and velocities in sorted order [3, N_L]."""
+        x = torch.empty((3, n_lr), dtype=torch.float32, device=device)
+        v = torch.empty((3, n_lr), dtype=torch.float32, device=device)
+        self._check(self._L.upsample_debug_lr_sorted(self._h, _ptr(x), _ptr(v), _stream()))
+        return x, v
+
     def debug_neighbors(self, hr_x, hr_v, max_k: int = 64):
         n = _soa(hr_x, "hr_x").shape[1]
         _soa(hr_v, "hr_v")
@@ -289,6 +318,24 @@ class Upsampler:
         self._check(self._L.upsample_debug_neighbors(self._h, _ptr(hr_x), _ptr(hr_v), n, _ptr(count),
                                                      _ptr(ids), max_k, _ptr(branch), _stream()))
         return count, ids, branch
+
+    def debug_step_members(self, hr_x, hr_v, max_k: int = 64, out_x=None, out_v=None):
+        """The step kernel's own instance with member exports
+        (upsample_debug_step_members): returns (out_x, out_v, count, ids,
+        count_w, w_disagree)."""
+        n = _soa(hr_x, "hr_x").shape[1]
+        _soa(hr_v, "hr_v")
+        out_x = torch.empty_like(hr_x) if out_x is None else _soa(out_x, "out_x")
+        out_v = torch.empty_like(hr_v) if out_v is None else _soa(out_v, "out_v")
+        dev = hr_x.device
+        count = torch.empty(n, dtype=torch.int32, device=dev)
+        ids = torch.full((n, max_k), -1, dtype=torch.int32, device=dev) if max_k > 0 else None
+        count_w = torch.empty(n, dtype=torch.int32, device=dev)
+        wdis = torch.empty(n, dtype=torch.float32, device=dev)
+        self._check(self._L.upsample_debug_step_members(self._h, _ptr(hr_x), _ptr(hr_v), _ptr(out_x), _ptr(out_v),
+                                                        n, _ptr(count), _ptr(ids), max(max_k, 0), _ptr(count_w),
+                                                        _ptr(wdis), _stream()))
+        return out_x, out_v, count, ids, count_w, wdis
 
     # -- launch-shape knobs
     TUNING_KEYS = ("gather_groups", "sort_sub", "adjoint_tiled", "sort_mode", "tile_max", "adjoint_tile_max",

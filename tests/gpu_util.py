@@ -151,3 +151,43 @@ def assert_same_step(x_a, v_a, x_b, v_b, L):
     dx = (x_a - x_b).abs().max().item()
     dv = ((v_a - v_b).abs() / torch.clamp(v_b.abs(), min=1.0)).max().item()
     assert dx <= SAME_X * L and dv <= SAME_V, (dx, dv)
+
+
+def _decisions(o):
+    """The discrete decisions of an oracle step: alpha branch and wall pushes."""
+    return np.concatenate([o["A"][:, None], o["wall"]["pushed"]], axis=1)
+
+
+def band_along(frames, states, idx, prm, rigid=None, drift=None):
+    """Whether each particle idx met a decision threshold at some step of a
+    trajectory: states[t] = (x, v) [3, N] before frame t.  At step t a
+    particle counts when the oracle's step puts its alpha or wall decision
+    inside the band of either branch, or -- with ``drift`` (a function of t
+    giving a distance in metres) -- when moving its position by drift(t)
+    along any axis changes one of its decisions.  Two float32 runs that
+    group particles into other waves drift apart by rounding, by at most
+    their comparison tolerance so far; a particle whose decision is that
+    sensitive may take the other branch in one of them and from then on
+    follow another valid trajectory."""
+    hit = np.zeros(len(idx), bool)
+    for t, ((X, V), (x, v)) in enumerate(zip(frames, states)):
+        xs, vs = np.asarray(x)[:, idx].astype(np.float64), np.asarray(v)[:, idx].astype(np.float64)
+        o = O.step(X, V, rigid, xs, vs, prm, keep=True)
+        hit |= o["band"] | o["wall_band"].any(axis=1)
+        if drift is not None:
+            base = _decisions(o)
+            d = float(drift(t))
+            for a in range(3):
+                for sgn in (-1.0, 1.0):
+                    xp = xs.copy()
+                    xp[a] += sgn * d
+                    hit |= (_decisions(O.step(X, V, rigid, xp, vs, prm, keep=True)) != base).any(axis=1)
+    return hit
+
+
+# Weight of a list entry on which the kernel's test (computed weight > 0) and
+# the exact membership predicate disagree: such an entry sits where
+# 1 - s / h^2 is within the rounding of the kernel's weight argument, at most
+# 16 float32 units of its largest term (about 1e-6), so its weight is below
+# (1e-6)^3 = 1e-18; ten times that is allowed.
+W_DISAGREE_MAX = 1e-17

@@ -9,7 +9,7 @@ from oracle import upsample_oracle as O
 from workloads import configs
 from workloads.generators import build_scene
 
-from gpu_util import TOL_V, TOL_X, dev, host, log
+from gpu_util import TOL_V, TOL_X, band_along, dev, host, log
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -160,18 +160,31 @@ def test_rollout_reorder_is_transparent(U):
         (xT * w).sum().backward()
         torch.cuda.synchronize()
         res[(reorder, re)] = (xT.detach(), vT.detach(), host(LVg.grad), host(x0g.grad))
+    # the trajectory in the original order, state by state, for the band check
+    states = [(host(x0), host(v0))]
+    xs, vs = x0, v0
+    for t in range(T):
+        xs, vs = up.step(LX[t], LV[t], None, xs, vs)
+        states.append((host(xs), host(vs)))
+    torch.cuda.synchronize()
     base = res[(False, 0)]
+    assert torch.equal(base[0], xs) and torch.equal(base[1], vs)
     for key in ((True, 0), (True, 2)):
         r = res[key]
         ddx = (base[0] - r[0]).abs().amax(dim=0)
         ddv = ((base[1] - r[1]).abs() / torch.clamp(base[1].abs(), min=1.0)).amax(dim=0)
-        off = ((ddx > TOL_X * sc.box_length * T) | (ddv > TOL_V * T)).sum().item()
+        off_idx = host(torch.nonzero((ddx > TOL_X * sc.box_length * T) | (ddv > TOL_V * T)).flatten())
+        off = int(off_idx.size)
         e_v = rel(r[2], base[2].astype(np.float64))
         e_0 = rel(r[3], base[3].astype(np.float64))
         log(f"reorder rollout {key}: median |dx| {torch.median(ddx).item():.2e} rel |dv| "
             f"{torch.median(ddv).item():.2e}, {off} beyond; rel dV {e_v:.2e} dx0 {e_0:.2e}")
-        # other waves round differently: a particle on an alpha threshold may
-        # take the other branch and follow another valid trajectory
+        # other waves round differently: a particle on an alpha or wall
+        # threshold may take the other branch and follow another valid
+        # trajectory; every particle that differs must have met a band
+        banded = band_along(frames, states[:-1], off_idx, sc.params(),
+                            drift=lambda t: TOL_X * sc.box_length * (t + 1))
+        assert banded.all(), (key, int((~banded).sum()), off)
         assert off <= max(5, 1e-4 * sc.n_hr), (key, off)
         assert e_v < 1e-3 and e_0 < 1e-3
 
@@ -237,3 +250,65 @@ def test_adjoint_scratch_cleared_between_calls(U):
     for a, b in zip(first, again):
         assert rel(b, a) < 1e-5, rel(b, a)
     assert np.abs(first[2]).sum() > 0 and np.abs(first[3]).sum() > 0
+
+
+@pytest.mark.parametrize("case", ["plain", "rigid", "diff"])
+def test_deterministic_backward(U, case):
+    """UPSAMPLE_FLAG_DETERMINISTIC_BWD: repeated backward calls (recomputing
+    and taped) give the same bits, the HR gradients equal the per-lane
+    adjoint's bit for bit, LR gradients are added to what the caller passes,
+    and everything matches the oracle's reference gradient."""
+    rig = None
+    if case == "rigid":
+        sc = build_scene("heap", 1500, 30001, seed=[21, 3], rigid_floor=True)
+        X, V = sc.lr_frame(1)
+        rig = sc.lr_rigid
+    elif case == "plain":
+        sc = configs.plain()
+        X, V = sc.lr_frame(2)
+    else:
+        sc = configs.diff()
+        X, V = sc.lr_frame(3)
+    kw = dict(max_lr=X.shape[1])
+    up = U.from_scene(sc, deterministic_bwd=True, **kw)
+    ref = U.from_scene(sc, **kw)
+    ref.set_tuning(adjoint_tiled=0)
+    rng = np.random.default_rng(21)
+    hx = dev(sc.hr_x0, torch)
+    hv = dev(rng.normal(0, 0.5, sc.hr_x0.shape).astype(np.float32), torch)
+    if case == "diff":
+        up.sort_hr(hx, hv, with_perm=False)
+    idx = None if sc.n_hr <= 65536 else np.sort(rng.choice(sc.n_hr, 8192, replace=False))
+    gxo = np.zeros(sc.hr_x0.shape, np.float32)
+    gvo = np.zeros(sc.hr_x0.shape, np.float32)
+    sel = slice(None) if idx is None else idx
+    gxo[:, sel] = rng.normal(size=gxo[:, sel].shape)
+    gvo[:, sel] = rng.normal(size=gvo[:, sel].shape)
+    Xd, Vd = dev(X, torch), dev(V, torch)
+    rd = None if rig is None else dev(rig, torch)
+    g = (dev(gxo, torch), dev(gvo, torch))
+    runs = [up.step_backward(Xd, Vd, rd, hx, hv, *g) for _ in range(3)]
+    base = ref.step_backward(Xd, Vd, rd, hx, hv, *g)
+    tape = torch.empty((6, sc.n_hr), dtype=torch.float32, device="cuda")
+    up.step(Xd, Vd, rd, hx, hv, tape=tape)
+    taped = [up.step_backward(Xd, Vd, rd, hx, hv, *g, tape=tape) for _ in range(2)]
+    ones = (torch.ones_like(Xd), torch.ones_like(Vd))
+    added = up.step_backward(Xd, Vd, rd, hx, hv, *g, g_lr_x=ones[0].clone(), g_lr_v=ones[1].clone())
+    torch.cuda.synchronize()
+    for r in runs[1:]:
+        for p_, q_ in zip(runs[0], r):
+            assert torch.equal(p_, q_), "deterministic backward differs between calls"
+    for p_, q_ in zip(taped[0], taped[1]):
+        assert torch.equal(p_, q_), "deterministic taped backward differs between calls"
+    assert torch.equal(runs[0][0], base[0]) and torch.equal(runs[0][1], base[1])
+    assert torch.equal(added[2], 1.0 + runs[0][2]) and torch.equal(added[3], 1.0 + runs[0][3])
+    for p_, q_ in zip(taped[0], runs[0]):
+        assert rel(host(p_), host(q_).astype(np.float64)) < 1e-5
+    for p_, q_ in zip(base[2:], runs[0][2:]):
+        assert rel(host(q_), host(p_).astype(np.float64)) < 1e-5
+    b = O.step_backward(X, V, rig, host(hx)[:, sel], host(hv)[:, sel], sc.params(), gxo[:, sel], gvo[:, sel])
+    errs = {"g_lr_v": rel(host(runs[0][3]), b["g_lr_v"]), "g_lr_x": rel(host(runs[0][2]), b["g_lr_x"]),
+            "gx": rel(host(runs[0][0])[:, sel], b["gx"]), "gv": rel(host(runs[0][1])[:, sel], b["gv"])}
+    for k, e in errs.items():
+        assert e < 1e-4, (k, e, errs)
+    log(f"deterministic backward {case}: bitwise repeatable, {errs}")

@@ -13,7 +13,7 @@ from oracle import upsample_oracle as O
 from workloads import configs
 from workloads.generators import build_scene
 
-from gpu_util import assert_same_step, compare_step, dev, host, log, morton_sort_keys
+from gpu_util import assert_same_step, band_along, compare_step, dev, host, log, morton_sort_keys
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -90,6 +90,25 @@ def test_plain_ten_steps_parity(U):
         ox, ov = o["x"], o["v"]
         log(f"plain step {t}: {s}, excluded so far {int(excluded.sum())}")
     assert excluded.sum() <= 1e-3 * sc.n_hr
+
+
+def test_plain_per_step_reseeded(U):
+    """Every HR particle, every step of the plain workload, at the per-step
+    tolerance (no scaling with the step count): each step is compared with
+    the oracle's step of the GPU's own state before it, so the bound holds
+    step by step along the GPU trajectory."""
+    sc = configs.plain()
+    up = U.from_scene(sc)
+    prm = sc.params()
+    x = dev(sc.hr_x0, torch)
+    v = dev(sc.hr_v0, torch)
+    for t in range(1, 11):
+        X, V = sc.lr_frame(t)
+        hx, hv = host(x).copy(), host(v).copy()
+        x, v = up.step(dev(X, torch), dev(V, torch), None, x, v)
+        torch.cuda.synchronize()
+        s = compare_step(host(x), host(v), X, V, None, hx, hv, prm, sc.box_length, n_steps=1)
+        log(f"plain re-seeded step {t}: {s}")
 
 
 def _sample(n, k, seed):
@@ -372,12 +391,18 @@ def test_run_matches_step_loop_and_oracle(U, sort_every):
     hx, hv = dev(sc.hr_x0, torch), dev(hv0, torch)
     n = sc.n_hr
     ref = U.from_scene(sc)
+    # the loop's states in the original particle order, before each frame
+    loop_states = []
     rx, rv = hx.clone(), hv.clone()
     rperm = torch.arange(n, device="cuda", dtype=torch.int64)
     for t in range(T):
         if sort_every and t % sort_every == 0:
             p = ref.sort_hr(rx, rv).long()
             rperm = rperm[p]
+        sx, sv = torch.empty_like(rx), torch.empty_like(rv)
+        sx[:, rperm] = rx
+        sv[:, rperm] = rv
+        loop_states.append((host(sx), host(sv)))
         rx, rv = ref.step(LX[t], LV[t], None, rx, rv, out_x=rx, out_v=rv)
     up = U.from_scene(sc)
     x, v = hx.clone(), hv.clone()
@@ -397,25 +422,37 @@ def test_run_matches_step_loop_and_oracle(U, sort_every):
     assert torch.equal(torch.sort(perm.long()).values, torch.arange(n, device="cuda"))
     ddx = (ox - qx).abs().amax(dim=0)
     ddv = ((ov - qv).abs() / torch.clamp(qv.abs(), min=1.0)).amax(dim=0)
-    off = ((ddx > 2e-7 * sc.box_length * T) | (ddv > 3e-6 * T)).sum().item()
+    off_idx = host(torch.nonzero((ddx > 2e-7 * sc.box_length * T) | (ddv > 3e-6 * T)).flatten())
+    off = int(off_idx.size)
     dx, dv = torch.median(ddx).item(), torch.median(ddv).item()
     # the reorders group particles into other waves, whose rounding differs;
-    # a particle sitting on an alpha threshold may then take the other branch
+    # a particle sitting on an alpha or wall threshold may then take the other
+    # branch: every such particle must have met a decision band on the way
+    banded = band_along(frames, loop_states, off_idx, sc.params(),
+                        drift=lambda t: 2e-7 * sc.box_length * (t + 1))
+    assert banded.all(), f"{int((~banded).sum())} of {off} particles differ without meeting a band"
     assert off <= max(5, 1e-4 * n), off
     # HR particles are independent given the frames: the oracle follows a sample
     idx = np.sort(np.random.default_rng(14).choice(n, 2048, replace=False))
     xo, vo = sc.hr_x0[:, idx], hv0[:, idx]
+    ostates = []
     for t in range(T):
+        ostates.append((xo, vo))
         o = O.step(frames[t][0], frames[t][1], None, xo, vo, sc.params())
         xo, vo = o["x"], o["v"]
     ex = np.abs(host(ox)[:, idx] - xo).max(axis=0)
     ev = (np.abs(host(ov)[:, idx] - vo) / np.maximum(np.abs(vo), 1.0)).max(axis=0)
     bad = (ex > 1e-6 * sc.box_length * T) | (ev > 1e-5 * T)
+    met_band = np.zeros(idx.size, bool)
+    if bad.any():
+        met_band[bad] = band_along(frames, [(a[0], a[1]) for a in ostates], np.nonzero(bad)[0], sc.params(),
+                                   drift=lambda t: 1e-6 * sc.box_length * (t + 1))
     log(f"run sort_every={sort_every}: vs loop median |dx| {dx:.2e} |dv| {dv:.2e}, {off} beyond; vs oracle median |dx| "
         f"{np.median(ex):.2e} |dv| {np.median(ev):.2e}, {int(bad.sum())} of {idx.size} beyond")
     # an alpha or wall decision inside its band may flip once in T steps (the
     # step-wise tests accept either branch); such particles then follow
-    # another, equally valid, trajectory
+    # another, equally valid, trajectory, and only those may differ
+    assert not (bad & ~met_band).any(), f"{int((bad & ~met_band).sum())} particles off without a band"
     assert bad.sum() <= max(3, 0.005 * idx.size)
     # the handle's grid is the last frame's
     spec = O.grid_spec(sc.r_lr, sc.domain_lo, sc.domain_hi)
