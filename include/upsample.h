@@ -425,6 +425,32 @@ int upsample_autotune(const upsample_params* p, const float* lr_x, const float* 
                       upsample_autotune_result* out);
 
 /*
+ * One step without a handle and without allocating: for callers that cannot
+ * call hipMalloc (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  It computes what upsample_step computes
+ * on a handle made from *p with the default tuning, bit for bit, from the
+ * same arguments (p: as for upsample_init; max_lr, max_hr are ignored).  The
+ * LR grid's scratch is a fixed device array inside the library, one per
+ * device it runs on (taken at the first call on a device, with that device
+ * current, and held until the process ends): it admits at most
+ * UPSAMPLE_NOALLOC_MAX_LR LR particles and a grid of at most
+ * UPSAMPLE_NOALLOC_MAX_CELLS cells (upsample_grid_info_for gives the count);
+ * larger inputs are rejected with UPSAMPLE_ERR_CAPACITY before any work is
+ * enqueued.  n_hr is not limited (the HR arrays are the caller's).  Every call
+ * on one device uses that device's array, so calls that overlap on one device
+ * (other streams, other threads) race and must be ordered by the caller.
+ * The flag UPSAMPLE_FLAG_VALIDATE is rejected (INVALID_ARG): it would
+ * synchronise.  Other errors: as upsample_step; a failure inside HIP is
+ * UPSAMPLE_ERR_HIP (no handle holds a message).
+ */
+#define UPSAMPLE_NOALLOC_MAX_LR    65536
+#define UPSAMPLE_NOALLOC_MAX_CELLS 262144
+int upsample_step_noalloc(const upsample_params* p,
+                          const float* lr_x, const float* lr_v, const uint8_t* lr_rigid, int64_t n_lr,
+                          const float* hr_x, const float* hr_v, float* hr_x_out, float* hr_v_out,
+                          int64_t n_hr, void* stream);
+
+/*
  * Batched step: many independent scenes (each the problem of Section 4 with
  * its own parameters) advanced together.
  *

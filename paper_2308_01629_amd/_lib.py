@@ -26,6 +26,8 @@ WALL_FLOATS = 12
 DEFAULT_CELL_FACTOR = 1.0001
 FLAG_VALIDATE = 1
 FLAG_DETERMINISTIC_BWD = 2
+NOALLOC_MAX_LR = 65536
+NOALLOC_MAX_CELLS = 262144
 BATCH_EAGER = 1
 
 
@@ -111,6 +113,7 @@ SIGNATURES = {
     "upsample_get_tuning": (_INT, [_P, ctypes.POINTER(Tuning)]),
     "upsample_timing_enable": (_INT, [_P, _INT]),
     "upsample_timing_read": (_INT, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "upsample_step_noalloc": (_INT, [ctypes.POINTER(Params), _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P]),
     "upsample_batch_init": (_INT, [ctypes.POINTER(SceneDesc), _I32, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "upsample_batch_step": (_INT, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "upsample_batch_destroy": (_INT, [_P]),

@@ -102,6 +102,21 @@ def autotune(params: dict, lr_x, lr_v, hr_x, hr_v, lr_rigid=None, cache_path: Op
             "tuning": {k: int(getattr(t, k)) for k in Upsampler.TUNING_KEYS}}
 
 
+def step_noalloc(params: dict, lr_x, lr_v, lr_rigid, hr_x, hr_v, out_x, out_v) -> None:
+    """upsample_step_noalloc: one step without a handle and without device
+    allocation in the library (the caller passes the output tensors).
+    ``params``: the keyword arguments of :func:`make_params`."""
+    p, _wbuf = make_params(**params)
+    nl = _soa(lr_x, "lr_x").shape[1]
+    _soa(lr_v, "lr_v")
+    _u8(lr_rigid, nl, "lr_rigid")
+    n = _soa(hr_x, "hr_x").shape[1]
+    for t, nm in ((hr_v, "hr_v"), (out_x, "out_x"), (out_v, "out_v")):
+        _soa(t, nm)
+    check(lib().upsample_step_noalloc(ctypes.byref(p), _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl, _ptr(hr_x),
+                                      _ptr(hr_v), _ptr(out_x), _ptr(out_v), n, _stream()))
+
+
 class Upsampler:
     """One handle of the library: a scene's parameters plus scratch for up to
     ``max_lr`` LR and ``max_hr`` HR particles."""
