@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched legs")
-    ap.add_argument("--only", choices=["drain", "column", "plain", "diff", "batched"], default=None,
+    ap.add_argument("--only", choices=["drain", "column", "plain", "multirate", "diff", "batched"], default=None,
                     help="run one leg only (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel 4 times (scale for the "
@@ -219,6 +219,26 @@ def drain_leg(args, torch, Upsampler, name="drain", steps=None, warmup=None, rep
             log(f"{name}: repeat {rep}: {times[-1] * 1e3 / steps:.4f} ms/step")
     elapsed = float(np.median(times))
     ms_step = elapsed * 1e3 / steps
+    default_ms = None
+    if tune is not None and name != "drain":
+        # the library defaults on the same steps, for the autotuner's gain
+        dflt = Upsampler.from_scene(sc)
+        if dflt.get_tuning() != up.get_tuning() or abs(gi["cell_size"] - dflt.grid_info()["cell_size"]) > 0:
+            dx0, dv0 = x_snap.clone(), v_snap.clone()
+            dflt.sort_hr(dx0, dv0, with_perm=False)
+            dflt.run(LX[warmup:warmup + steps], LV[warmup:warmup + steps], dx0, dv0, sort_every=args.sort_every)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            dx0.copy_(x_snap)
+            dv0.copy_(v_snap)
+            dflt.sort_hr(dx0, dv0, with_perm=False)
+            torch.cuda.synchronize()
+            e0.record()
+            dflt.run(LX[warmup:warmup + steps], LV[warmup:warmup + steps], dx0, dv0, sort_every=args.sort_every)
+            e1.record()
+            torch.cuda.synchronize()
+            default_ms = e0.elapsed_time(e1) / steps
+            log(f"{name}: library defaults {default_ms:.4f} ms/step against the tuned {ms_step:.4f}")
+        dflt.close()
     n_cells = gi["n_cells"]
     step_bytes = 48 * sc.n_hr + 89 * sc.n_lr + 8 * n_cells
     adv_s = adv_ms / 1e3 / max(launches, 1)
@@ -226,7 +246,7 @@ def drain_leg(args, torch, Upsampler, name="drain", steps=None, warmup=None, rep
     rf = roofline(adv_s, sc.n_hr, sc.n_lr, n_cells,
                   traffic=traffic_from_profiles() if is_drain else None,
                   profile_us=profile_record("advance_drain_trace.md", "timed_pass_avg_us") if is_drain else None)
-    res = {"value": sc.n_hr * steps / elapsed, "ms_per_step": ms_step,
+    res = {"value": sc.n_hr * steps / elapsed, "ms_per_step": ms_step, "default_ms_per_step": default_ms,
            "step_hbm_frac": step_bytes / (ms_step / 1e3) / HBM_PEAK,
            "config": {"workload": name, "n_lr": sc.n_lr, "n_hr": sc.n_hr, "r_lr": sc.r_lr,
                       "r_hr": sc.r_hr, "dt": sc.dt, "walls": int(sc.walls.shape[0]),
@@ -322,6 +342,17 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
     up.timing_enable(False)
     t_f = timed(fwd) / steps
     t_b = timed(bwd) / steps
+    # the same backward with deterministic LR gradients (no float atomics)
+    upd = Upsampler.from_scene(sc, deterministic_bwd=True)
+
+    def bwd_det():
+        for t in range(steps - 1, -1, -1):
+            upd.step_backward(LX[t], LV[t], None, xs[t], vs[t], gx, gv, g_lr_x=glx, g_lr_v=glv,
+                              gx_in=bx, gv_in=bv)
+
+    bwd_det()
+    t_bd = timed(bwd_det) / steps
+    upd.close()
     t_ft = timed(fwd_taped) / steps
     t_bt = timed(bwd_taped) / steps
     del tapes
@@ -342,13 +373,14 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
     up.close()
     log(f"diff: taped forward {t_ft * 1e3:.1f} us/step, taped backward {t_bt * 1e3:.1f} us/step, ratio "
         f"{t_bt / t_ft:.2f}; plain forward {t_f * 1e3:.1f}, recomputing backward {t_b * 1e3:.1f} (ratio "
-        f"{t_b / t_f:.2f}); rollout fwd {t_rf:.2f} ms, fwd+bwd {t_rfb:.2f} ms")
+        f"{t_b / t_f:.2f}), deterministic {t_bd * 1e3:.1f}; rollout fwd {t_rf:.2f} ms, fwd+bwd {t_rfb:.2f} ms")
     return {"workload": "diff", "n_lr": sc.n_lr, "n_hr": sc.n_hr,
             "ratio": t_b / t_f,
             "ratio_definition": "t(upsample_step_backward) / t(upsample_step) per step, each with its grid "
                                 "rebuild; the backward recomputes the forward sums",
             "forward_us_per_step": t_f * 1e3, "backward_recompute_us_per_step": t_b * 1e3,
             "ratio_taped": t_bt / t_ft,
+            "backward_deterministic_us_per_step": t_bd * 1e3, "ratio_deterministic": t_bd / t_f,
             "forward_taped_us_per_step": t_ft * 1e3, "backward_taped_us_per_step": t_bt * 1e3,
             "forward_gather_roofline": roofline(adv_ms / 1e3 / max(launches, 1), sc.n_hr, sc.n_lr, n_cells),
             "rollout_steps": steps, "checkpoint_every": every, "reorder_every": reorder_every,
@@ -469,6 +501,47 @@ def batched_leg(args, torch, Upsampler, steps=10, warmup=2):
             "graphs_captured": info["graphs_captured"], "kappa_autotuned": kappa, "kappa_used": kappa_used}
 
 
+def multirate_leg(args, torch, Upsampler, steps=60, warmup=10, dt_lr=0.005):
+    """The drain with LR frames at their own time step (Section 5.2: dt_LR =
+    0.005 s against dt_HR = 1/60 s): each HR step against the LR state at its
+    end, interpolated between the bracketing frames inside the grid build
+    (upsample_run_multirate), HR reorder every 10 steps."""
+    from workloads import configs
+    from workloads.generators import build_scene
+    base = configs.drain()
+    sc = build_scene("drain", base.n_lr, base.n_hr, seed=3, r_lr=base.r_lr, hr_radius_ratio=0.25, dt_lr=dt_lr)
+    n_frames = int((warmup + steps) * sc.dt / dt_lr) + 3
+    log(f"multirate: {sc.n_lr} LR frames every {dt_lr} s ({n_frames}), {sc.n_hr} HR, steps of {sc.dt:.5f} s")
+    frames = [sc.lr_frame(k) for k in range(n_frames)]
+    LX = torch.from_numpy(np.stack([f[0] for f in frames])).cuda()
+    LV = torch.from_numpy(np.stack([f[1] for f in frames])).cuda()
+    del frames
+    up = Upsampler.from_scene(sc)
+    hx = torch.from_numpy(sc.hr_x0).cuda()
+    hv = torch.from_numpy(sc.hr_v0).cuda()
+    up.sort_hr(hx, hv, with_perm=False)
+    up.run_multirate(LX, LV, hx, hv, n_steps=warmup, dt_lr=dt_lr, sort_every=args.sort_every)
+    t0 = warmup * float(sc.dt)
+    xs, vs = hx.clone(), hv.clone()
+    times = []
+    for _ in range(3):
+        hx.copy_(xs)
+        hv.copy_(vs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        up.run_multirate(LX, LV, hx, hv, n_steps=steps, dt_lr=dt_lr, t_hr0=t0, sort_every=args.sort_every)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    up.close()
+    el = float(np.median(times))
+    log(f"multirate: {el * 1e3 / steps:.4f} ms/step, {sc.n_hr * steps / el:.3e} HR updates/s")
+    return {"workload": "drain, LR frames at dt_LR", "dt_lr": dt_lr, "dt_hr": float(sc.dt), "steps": steps,
+            "lr_frames_per_hr_step": float(sc.dt) / dt_lr, "ms_per_step": el * 1e3 / steps,
+            "value": sc.n_hr * steps / el, "unit": "HR particle-updates/s"}
+
+
 def cpu_baseline(sc, frames, budget_s=12.0):
     """The oracle as it stands on a bounded sample of the drain workload: the
     full LR frame, a seeded sample of HR particles, one step."""
@@ -516,7 +589,10 @@ def main():
                           warmup=10 if name == "column" else 2, repeats=3)
             out[name] = {"value": w["value"], "unit": "HR particle-updates/s", "ms_per_step": w["ms_per_step"],
                          "steps": 100 if name == "column" else 10, "config": w["config"],
-                         "roofline": w["roofline"], "step_hbm_frac": w["step_hbm_frac"]}
+                         "roofline": w["roofline"], "step_hbm_frac": w["step_hbm_frac"],
+                         "library_defaults_ms_per_step": w["default_ms_per_step"]}
+    if args.only == "multirate" or (args.only is None and not args.no_extras):
+        out["multirate"] = multirate_leg(args, torch, Upsampler)
     if args.only == "diff" or (args.only is None and not args.no_extras):
         out["backward_forward"] = diff_leg(args, torch, Upsampler)
     if args.only == "batched" or (args.only is None and not args.no_extras):
