@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched legs")
-    ap.add_argument("--only", choices=["drain", "column", "plain", "multirate", "diff", "batched"], default=None,
+    ap.add_argument("--only", choices=["drain", "column", "plain", "multirate", "sampling", "diff", "batched"],
+                    default=None,
                     help="run one leg only (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel 4 times (scale for the "
@@ -542,6 +543,31 @@ def multirate_leg(args, torch, Upsampler, steps=60, warmup=10, dt_lr=0.005):
             "value": sc.n_hr * steps / el, "unit": "HR particle-updates/s"}
 
 
+def sampling_leg(torch, n_cand=16_000_000, reps=3):
+    """Randomized volume sampling (Section 4) of the drain's HR initial state
+    at its radius (r_LR / 4): 16M random candidates in the silo and hopper
+    below the LR fill's top, cells of side 2 r / sqrt(3)."""
+    from workloads import configs
+    from workloads.generators import volume_candidates
+    from paper_2308_01629_amd.upsampler import sample_volume
+    sc = configs.drain()
+    top = float(sc.lr_x0[1].max()) + sc.r_lr
+    cand, lo, hi = volume_candidates("drain", n_cand, [43, 1], top=top)
+    c = torch.from_numpy(cand).cuda()
+    out = sample_volume(c, sc.r_hr, lo, hi)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = sample_volume(c, sc.r_hr, lo, hi)
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    log(f"sampling: {n_cand} candidates -> {out.shape[1]} samples of radius {sc.r_hr:.5f} in {t * 1e3:.1f} ms")
+    return {"workload": "drain HR initial state", "r": sc.r_hr, "candidates": n_cand, "samples": int(out.shape[1]),
+            "ms": t * 1e3, "candidates_per_s": n_cand / t, "samples_per_s": out.shape[1] / t,
+            "note": "wall clock of the whole call, its temporary allocations included"}
+
+
 def cpu_baseline(sc, frames, budget_s=12.0):
     """The oracle as it stands on a bounded sample of the drain workload: the
     full LR frame, a seeded sample of HR particles, one step."""
@@ -593,6 +619,8 @@ def main():
                          "library_defaults_ms_per_step": w["default_ms_per_step"]}
     if args.only == "multirate" or (args.only is None and not args.no_extras):
         out["multirate"] = multirate_leg(args, torch, Upsampler)
+    if args.only == "sampling" or (args.only is None and not args.no_extras):
+        out["sampling"] = sampling_leg(torch)
     if args.only == "diff" or (args.only is None and not args.no_extras):
         out["backward_forward"] = diff_leg(args, torch, Upsampler)
     if args.only == "batched" or (args.only is None and not args.no_extras):

@@ -451,6 +451,31 @@ int upsample_step_noalloc(const upsample_params* p,
                           int64_t n_hr, void* stream);
 
 /*
+ * Randomized volume sampling of an initial particle state (Section 4, the
+ * sampling paragraph).  The box [lo, hi] (host float[3] each) is cut into
+ * cubic cells of side 2 r / sqrt(3), G_a = ceil((hi_a - lo_a) / side) per
+ * axis in double, so a cell's diagonal is 2 r; each candidate (device
+ * float32 [3][n_cand], random positions inside the hull, drawn by the caller)
+ * belongs to the cell clamp(floor(fl(fl(x - lo) fl32(1 / side))), 0, G - 1)
+ * per axis.  Each cell then takes the first of its candidates, in input
+ * order, whose squared distance to every position already taken is at least
+ * fl32(4 r^2) (squared distance rounded as in the membership predicate), so
+ * no two samples overlap as spheres of radius r.  The paper leaves the order
+ * of the cells open: here it is 27 colour phases, colour (cx mod 3) +
+ * 3 (cy mod 3) + 9 (cz mod 3), cell-key order inside a phase (cells of one
+ * colour cannot conflict, so a phase's cells choose in parallel).  The samples
+ * are written to out (device float32 [3][max_out]) in cell-key order, and
+ * *n_out (host) receives their number; when it exceeds max_out the first
+ * max_out are written and UPSAMPLE_ERR_CAPACITY is returned.  A set-up routine,
+ * not a step: it allocates temporary device memory (about 36 B per cell and
+ * 48 B per candidate) and synchronises the stream.  Errors: INVALID_ARG (bad
+ * r, box or pointers), GRID_TOO_LARGE (2^31 cells or more, or an axis of 2^20),
+ * CAPACITY, NO_DEVICE, OOM, HIP.
+ */
+int upsample_sample_volume(const float* cand, int64_t n_cand, float r, const float* lo, const float* hi,
+                           float* out, int64_t max_out, int64_t* n_out, void* stream);
+
+/*
  * Batched step: many independent scenes (each the problem of Section 4 with
  * its own parameters) advanced together.
  *

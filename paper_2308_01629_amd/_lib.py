@@ -114,6 +114,8 @@ SIGNATURES = {
     "upsample_timing_enable": (_INT, [_P, _INT]),
     "upsample_timing_read": (_INT, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "upsample_step_noalloc": (_INT, [ctypes.POINTER(Params), _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P]),
+    "upsample_sample_volume": (_INT, [_P, _I64, ctypes.c_float, ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_float), _P, _I64, ctypes.POINTER(_I64), _P]),
     "upsample_batch_init": (_INT, [ctypes.POINTER(SceneDesc), _I32, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "upsample_batch_step": (_INT, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "upsample_batch_destroy": (_INT, [_P]),

@@ -636,6 +636,11 @@ hipError_t launch_unpack_sorted(const LRPoint* lr, int64_t n, float* x, float* v
   return hipGetLastError();
 }
 
+hipError_t launch_scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t* chunk_sum,
+                            hipStream_t st) {
+  return scan_bins(counts, n_bins, local, chunk_sum, st);
+}
+
 hipError_t launch_build_grid_lerp(const GridConst& gc, const float* x0, const float* v0, const float* x1,
                                   const float* v1, float theta, const uint8_t* lr_rigid, int64_t n_lr,
                                   int64_t n_cells, const GridScratch& s, hipStream_t st) {

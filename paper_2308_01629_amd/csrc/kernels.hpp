@@ -31,6 +31,11 @@ hipError_t launch_build_grid_lerp(const GridConst& gc, const float* x0, const fl
                                   const float* v1, float theta, const uint8_t* lr_rigid, int64_t n_lr,
                                   int64_t n_cells, const GridScratch& s, hipStream_t st);
 
+// Exclusive scan of n_bins counts (zeroed behind): local[b] + chunk_sum[b /
+// kScanChunk] is bin b's offset, chunk_sum[n_chunks] the total.
+hipError_t launch_scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t* chunk_sum,
+                            hipStream_t st);
+
 // The sorted LR copy as [3][n] positions and velocities (either may be null).
 hipError_t launch_unpack_sorted(const LRPoint* lr, int64_t n, float* x, float* v, hipStream_t st);
 

@@ -117,6 +117,22 @@ def step_noalloc(params: dict, lr_x, lr_v, lr_rigid, hr_x, hr_v, out_x, out_v) -
                                       _ptr(hr_v), _ptr(out_x), _ptr(out_v), n, _stream()))
 
 
+def sample_volume(cand: torch.Tensor, r: float, lo, hi, max_out: Optional[int] = None) -> torch.Tensor:
+    """upsample_sample_volume: one non-overlapping sample of radius r per cell
+    of side 2r/sqrt(3), chosen among the candidates [3, M] (device float32);
+    returns the samples [3, K] in cell-key order."""
+    _soa(cand, "cand")
+    m = cand.shape[1]
+    cap = m if max_out is None else int(max_out)
+    out = torch.empty((3, max(cap, 0)), dtype=torch.float32, device=cand.device)
+    lo_c = (ctypes.c_float * 3)(*[float(v) for v in lo])
+    hi_c = (ctypes.c_float * 3)(*[float(v) for v in hi])
+    n = ctypes.c_int64()
+    check(lib().upsample_sample_volume(_ptr(cand), m, float(r), lo_c, hi_c, _ptr(out), cap, ctypes.byref(n),
+                                       _stream()))
+    return out[:, :n.value].contiguous()
+
+
 class Upsampler:
     """One handle of the library: a scene's parameters plus scratch for up to
     ``max_lr`` LR and ``max_hr`` HR particles."""

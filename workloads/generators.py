@@ -235,6 +235,27 @@ def place_hr(geom: Geometry, lr: np.ndarray, r_lr: float, n: int,
     return P[np.argsort(key, kind="stable")]
 
 
+def volume_candidates(geometry: str, n: int, seed, top: Optional[float] = None) -> np.ndarray:
+    """n random candidate positions uniform inside a geometry's fill region
+    (below ``top`` if given), float32 [3, n]: the random input of the volume
+    sampling of initial states.  -> also the box (lo, hi) they lie in."""
+    geom = make_geometry(geometry, with_walls=False)
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    lo = geom.fill_lo.copy()
+    hi = geom.fill_hi.copy()
+    if top is not None:
+        hi[1] = min(hi[1], top)
+    chunks, have = [], 0
+    while have < n:
+        m = max(1024, int(1.3 * (n - have)) + 1024)
+        C = rng.uniform(lo, hi, size=(m, 3))
+        C = C[geom.inside(C, 0.0)]
+        chunks.append(C)
+        have += C.shape[0]
+    P = np.concatenate(chunks)[:n]
+    return np.ascontiguousarray(P.T, dtype=F32), lo.astype(F32), hi.astype(F32)
+
+
 # ---------------------------------------------------------------------------
 # LR trajectory stand-in.
 # ---------------------------------------------------------------------------
