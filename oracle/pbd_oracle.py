@@ -22,6 +22,11 @@ One step of dt (Algorithm 1), LR particles of radius r:
    at the same x~ (Jacobi), the displacements averaged and added to x~.
 4. v = (x~ - x) / dt, x = x~ (static particles keep x and v = 0).
 
+``predict``, ``stab_iteration``, ``solve_iteration`` and ``finish`` are these
+steps one at a time; ``step`` chains them.  ``force_act`` / ``force_static``
+fix a pair's contact or friction decision, so that a test can recompute a
+stage with the other decision of a pair that sits on a threshold.
+
 Contact of a pair (i, j), x_ij = x~_j - x~_i, d = |x_ij| < 2r (Section 3):
     dx_i = -w_i/(w_i + w_j) (2r - d) x_ij / d,   dx_j = +w_j/(w_i + w_j) (2r - d) x_ij / d
 with the scaled inverse masses.  Friction of the same pair (solver
@@ -55,12 +60,13 @@ Readings (listed with the others in the design notes):
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
-from typing import Optional, Tuple
+from dataclasses import dataclass
+from typing import Tuple
 
 import numpy as np
 from scipy.spatial import cKDTree
 
+F32 = np.float32
 F64 = np.float64
 GRANULAR = -1
 STATIC = -2
@@ -86,34 +92,53 @@ def scaled_inv_mass(x, inv_m, prm: PBDParams) -> np.ndarray:
     return np.asarray(inv_m, dtype=F64) * np.exp(np.asarray(x, dtype=F64)[1] - prm.ground_y)
 
 
-def contact_pairs(P, body, r) -> np.ndarray:
+def contact_pairs(P, body, r, f32: bool = False) -> np.ndarray:
     """Pairs (i < j) closer than 2r, without static-static and same-body
-    pairs; P [3, N]."""
-    P = np.asarray(P, dtype=F64)
+    pairs; P [3, N].  With f32=True the distance test is taken in float32 like
+    the GPU's (the float32 positions, d = fl(P_j - P_i) per axis, separately
+    rounded squares and sums, against fl32(4 r^2)), so that both sides decide
+    each pair identically."""
+    P = np.asarray(P, dtype=F32 if f32 else F64)
     if P.shape[1] < 2:
         return np.zeros((0, 2), dtype=np.int64)
-    pr = np.array(sorted(cKDTree(P.T).query_pairs(2.0 * r * (1 + 1e-9))), dtype=np.int64).reshape(-1, 2)
+    pr = np.array(sorted(cKDTree(P.T.astype(F64)).query_pairs(2.0 * float(r) * (1 + 1e-6))),
+                  dtype=np.int64).reshape(-1, 2)
     if pr.size == 0:
         return pr
     i, j = pr[:, 0], pr[:, 1]
-    d = np.linalg.norm(P[:, j] - P[:, i], axis=0)
+    if f32:
+        d = P[:, j] - P[:, i]
+        s = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+        close = s < F32(4.0 * F64(F32(r)) ** 2)
+    else:
+        close = np.linalg.norm(P[:, j] - P[:, i], axis=0) < 2.0 * r
     bi, bj = body[i], body[j]
-    keep = (d < 2.0 * r) & ~((bi == STATIC) & (bj == STATIC)) & ~((bi >= 0) & (bi == bj))
+    keep = close & ~((bi == STATIC) & (bj == STATIC)) & ~((bi >= 0) & (bi == bj))
     return pr[keep]
 
 
-def _contact(P, pairs, w, r):
-    """Per-pair contact displacements (dx_i, dx_j) [3, K] and the active mask."""
+def _forced(own, force):
+    """A decision per pair: the oracle's own, or the one ``force`` fixes
+    (int8 per pair: -1 own, 0 false, 1 true)."""
+    if force is None:
+        return own
+    force = np.asarray(force)
+    return np.where(force < 0, own, force > 0)
+
+
+def _contact(P, pairs, w, r, force_act=None):
+    """Per-pair contact displacements (dx_i, dx_j) [3, K], the active mask and
+    the signed distance margin d - 2r."""
     i, j = pairs[:, 0], pairs[:, 1]
     xij = P[:, j] - P[:, i]
     d = np.linalg.norm(xij, axis=0)
     wi, wj = w[i], w[j]
     ws = wi + wj
-    act = (d < 2.0 * r) & (d > 0.0) & (ws > 0.0)
+    act = _forced((d < 2.0 * r) & (d > 0.0) & (ws > 0.0), force_act) & (d > 0.0) & (ws > 0.0)
     s = np.where(act, (2.0 * r - d) / np.where(d > 0, d, 1.0), 0.0)
     mi = np.where(act, wi / np.where(ws > 0, ws, 1.0), 0.0)
     mj = np.where(act, wj / np.where(ws > 0, ws, 1.0), 0.0)
-    return -mi * s * xij, mj * s * xij, act, xij, mi, mj
+    return -mi * s * xij, mj * s * xij, act, xij, mi, mj, d - 2.0 * r
 
 
 def polar_rotation(C) -> np.ndarray:
@@ -126,9 +151,11 @@ def polar_rotation(C) -> np.ndarray:
     return R
 
 
-def shape_matching(P, body, rest):
-    """Shape-matching displacements [3, N] (zero for non-rigid particles)."""
+def shape_matching(P, body, rest, return_frames: bool = False):
+    """Shape-matching displacements [3, N] (zero for non-rigid particles);
+    with return_frames also each body's (c, R), bodies 0 .. B-1."""
     dx = np.zeros_like(P)
+    frames = {}
     for b in np.unique(body[body >= 0]):
         idx = np.nonzero(body == b)[0]
         c = P[:, idx].mean(axis=1)
@@ -136,7 +163,91 @@ def shape_matching(P, body, rest):
         C = (P[:, idx] - c[:, None]) @ o.T
         R = polar_rotation(C)
         dx[:, idx] = R @ o + c[:, None] - P[:, idx]
+        frames[int(b)] = (c, R)
+    if return_frames:
+        return dx, frames
     return dx
+
+
+def _average(N, pairs, di, dj, act, extra=None, extra_cnt=None):
+    """Each particle's summed displacements divided by its number of active
+    constraints (constraint averaging)."""
+    acc = np.zeros((3, N))
+    cnt = np.zeros(N)
+    np.add.at(acc.T, pairs[:, 0], di.T)
+    np.add.at(acc.T, pairs[:, 1], dj.T)
+    np.add.at(cnt, pairs[:, 0], act.astype(F64))
+    np.add.at(cnt, pairs[:, 1], act.astype(F64))
+    if extra is not None:
+        acc += extra
+        cnt += extra_cnt
+    return np.where(cnt > 0, acc / np.maximum(cnt, 1.0), 0.0)
+
+
+def predict(x, v, body, inv_m, prm: PBDParams):
+    """Step 1: velocities with gravity (zero for static particles), the
+    predicted positions x~ and the scaled inverse masses (0 for static)."""
+    x = np.asarray(x, dtype=F64)
+    v = np.asarray(v, dtype=F64).copy()
+    dyn = np.asarray(body) != STATIC
+    v[:, dyn] += F64(prm.dt) * np.asarray(prm.g, dtype=F64)[:, None]
+    v[:, ~dyn] = 0.0
+    xt = x + F64(prm.dt) * v
+    w = scaled_inv_mass(x, inv_m, prm)
+    w[~dyn] = 0.0
+    return v, xt, w
+
+
+def stab_iteration(x, xt, pairs, w, r, force_act=None):
+    """Step 2, one stabilization iteration: the averaged contact displacements
+    of the pairs at x, added to x and to x~.  Returns (x, x~, per-pair
+    distance margin d - 2r)."""
+    x = np.asarray(x, dtype=F64)
+    xt = np.asarray(xt, dtype=F64)
+    di, dj, act, _, _, _, margin = _contact(x, pairs, w, F64(r), force_act)
+    upd = _average(x.shape[1], pairs, di, dj, act)
+    return x + upd, xt + upd, margin
+
+
+def solve_iteration(xt, x0, pairs, w, body, rest, prm: PBDParams, force_act=None, force_static=None):
+    """Step 3, one solver iteration on x~ (Jacobi): contact and friction of
+    each pair as one constraint, one shape-matching constraint per rigid
+    particle, averaged.  Returns (x~, info) with the per-pair distance margin
+    d - 2r, the friction margin |Dt| - 2 r mu_s and the bodies' (c, R)."""
+    xt = np.asarray(xt, dtype=F64)
+    x0 = np.asarray(x0, dtype=F64)
+    body = np.asarray(body)
+    r = F64(prm.r)
+    di, dj, act, xij, mi, mj, margin = _contact(xt, pairs, w, r, force_act)
+    i, j = pairs[:, 0], pairs[:, 1]
+    Dx = (xt[:, i] + di - x0[:, i]) - (xt[:, j] + dj - x0[:, j])
+    n2 = np.sum(xij * xij, axis=0)
+    Dt = Dx - np.sum(Dx * xij, axis=0) / np.where(n2 > 0, n2, 1.0) * xij
+    lt = np.linalg.norm(Dt, axis=0)
+    static_f = _forced(lt < 2.0 * r * prm.mu_s, force_static)
+    scale = np.where(static_f, 1.0, np.minimum(2.0 * r * prm.mu_k / np.where(lt > 0, lt, 1.0), 1.0))
+    f = Dt * scale
+    di = di - mi * f
+    dj = dj + mj * f
+    di[:, ~act] = 0.0
+    dj[:, ~act] = 0.0
+    rigid = body >= 0
+    frames = {}
+    sm, sm_cnt = None, None
+    if rigid.any():
+        sm, frames = shape_matching(xt, body, np.asarray(rest, dtype=F64), return_frames=True)
+        sm_cnt = rigid.astype(F64)
+    upd = _average(xt.shape[1], pairs, di, dj, act, sm, sm_cnt)
+    info = {"act": act, "act_margin": margin, "fric_margin": lt - 2.0 * r * prm.mu_s, "frames": frames}
+    return xt + upd, info
+
+
+def finish(x, xt, body, dt):
+    """Step 4: v = (x~ - x) / dt, x = x~; static particles keep x, v = 0."""
+    x = np.asarray(x, dtype=F64)
+    xt = np.asarray(xt, dtype=F64)
+    dyn = np.asarray(body) != STATIC
+    return np.where(dyn, xt, x), np.where(dyn, (xt - x) / F64(dt), 0.0)
 
 
 def step(x, v, body, inv_m, rest, prm: PBDParams, return_info: bool = False):
@@ -144,71 +255,30 @@ def step(x, v, body, inv_m, rest, prm: PBDParams, return_info: bool = False):
     STATIC = -2, rigid body ids >= 0); inv_m: [N] (0 for static); rest: [3, N]
     rest offsets of rigid particles from their body's centre (ignored
     otherwise).  Returns float64 (x, v) after the step."""
-    x = np.asarray(x, dtype=F64).copy()
-    v = np.asarray(v, dtype=F64).copy()
+    x = np.asarray(x, dtype=F64)
     body = np.asarray(body)
-    rest = np.asarray(rest, dtype=F64)
-    g = np.asarray(prm.g, dtype=F64)
-    dyn = body != STATIC
-    r, dt = F64(prm.r), F64(prm.dt)
-    # 1. prediction and scaled masses
-    v[:, dyn] += dt * g[:, None]
-    v[:, ~dyn] = 0.0
-    xt = x + dt * v
-    w = scaled_inv_mass(x, inv_m, prm)
-    w[~dyn] = 0.0
-    N = x.shape[1]
+    r = F64(prm.r)
     info = {"stab_pairs": 0, "solve_pairs": 0, "min_margin": np.inf}
+    # 1. prediction and scaled masses
+    v, xt, w = predict(x, v, body, inv_m, prm)
     # 2. stabilization on the start positions, applied to x and x~
     sp = contact_pairs(x, body, r)
     info["stab_pairs"] = sp.shape[0]
     for _ in range(prm.stab_iters):
-        di, dj, act, _, _, _ = _contact(x, sp, w, r)
-        acc = np.zeros((3, N))
-        cnt = np.zeros(N)
-        np.add.at(acc.T, sp[:, 0], di.T)
-        np.add.at(acc.T, sp[:, 1], dj.T)
-        np.add.at(cnt, sp[:, 0], act.astype(F64))
-        np.add.at(cnt, sp[:, 1], act.astype(F64))
-        upd = np.where(cnt > 0, acc / np.maximum(cnt, 1.0), 0.0)
-        x += upd
-        xt += upd
+        x, xt, _ = stab_iteration(x, xt, sp, w, r)
     x0 = x.copy()
     # 3. solver iterations on x~: contact + friction per pair, shape matching
     pairs = contact_pairs(xt, body, r)
     info["solve_pairs"] = pairs.shape[0]
-    rigid = body >= 0
     for _ in range(prm.solve_iters):
-        di, dj, act, xij, mi, mj = _contact(xt, pairs, w, r)
-        i, j = pairs[:, 0], pairs[:, 1]
-        Dx = (xt[:, i] + di - x0[:, i]) - (xt[:, j] + dj - x0[:, j])
-        n2 = np.sum(xij * xij, axis=0)
-        Dt = Dx - np.sum(Dx * xij, axis=0) / np.where(n2 > 0, n2, 1.0) * xij
-        lt = np.linalg.norm(Dt, axis=0)
-        static_f = lt < 2.0 * r * prm.mu_s
-        scale = np.where(static_f, 1.0, np.minimum(2.0 * r * prm.mu_k / np.where(lt > 0, lt, 1.0), 1.0))
-        f = Dt * scale
-        di = di - mi * f
-        dj = dj + mj * f
-        di[:, ~act] = 0.0
-        dj[:, ~act] = 0.0
-        acc = np.zeros((3, N))
-        cnt = np.zeros(N)
-        np.add.at(acc.T, i, di.T)
-        np.add.at(acc.T, j, dj.T)
-        np.add.at(cnt, i, act.astype(F64))
-        np.add.at(cnt, j, act.astype(F64))
-        if rigid.any():
-            acc += shape_matching(xt, body, rest)
-            cnt += rigid.astype(F64)
+        xt_new, it = solve_iteration(xt, x0, pairs, w, body, rest, prm)
+        act = it["act"]
         if act.any():
-            dd = np.linalg.norm(xij[:, act], axis=0)
-            info["min_margin"] = min(info["min_margin"], float(np.min(np.abs(dd - 2.0 * r))),
-                                     float(np.min(np.abs(lt[act] - 2.0 * r * prm.mu_s))))
-        xt += np.where(cnt > 0, acc / np.maximum(cnt, 1.0), 0.0)
+            info["min_margin"] = min(info["min_margin"], float(np.min(np.abs(it["act_margin"][act]))),
+                                     float(np.min(np.abs(it["fric_margin"][act]))))
+        xt = xt_new
     # 4. velocities from the positions
-    vn = np.where(dyn, (xt - x) / dt, 0.0)
-    xn = np.where(dyn, xt, x)
+    xn, vn = finish(x, xt, body, prm.dt)
     if return_info:
         return xn, vn, info
     return xn, vn

@@ -5,7 +5,8 @@ constraint averaging, the static and kinetic friction branches, the centre of
 mass conserved by isolated pairs, the scaled mass of Algorithm 1, the
 polar-decomposition rotation, shape matching leaving a rigid motion
 unchanged and restoring a deformed body, and stabilization not changing
-velocities."""
+velocities; the contact pairs against all pairs tested one by one (float64
+and the float32 contract), and a forced decision taking the other branch."""
 import json
 import math
 import os
@@ -192,3 +193,58 @@ def test_stabilization_moves_x_and_prediction_together():
     xn, vn = _one(x, stab_iters=2)
     np.testing.assert_allclose(vn, 0.0, atol=1e-12)
     np.testing.assert_allclose(xn[0, 1] - xn[0, 0], 2 * r, atol=1e-15)
+
+
+def test_contact_pairs_against_brute_force():
+    # every pair tested one by one, in float64 and in the float32 contract
+    rng = np.random.default_rng(7)
+    r = 0.02
+    x = rng.uniform(0.0, 0.25, (3, 150))
+    body = rng.choice([P.GRANULAR, P.STATIC, 0, 1], 150)
+    x32 = x.astype(np.float32)
+    d2 = np.float32(4.0 * float(np.float32(r)) ** 2)
+    want64, want32 = set(), set()
+    for i in range(150):
+        for j in range(i + 1, 150):
+            if (body[i] == P.STATIC and body[j] == P.STATIC) or (body[i] >= 0 and body[i] == body[j]):
+                continue
+            if math.dist(x[:, i], x[:, j]) < 2 * r:
+                want64.add((i, j))
+            dx, dy, dz = (x32[a, j] - x32[a, i] for a in range(3))
+            if (dx * dx + dy * dy) + dz * dz < d2:
+                want32.add((i, j))
+    assert {tuple(p) for p in P.contact_pairs(x, body, r)} == want64 and want64
+    assert {tuple(p) for p in P.contact_pairs(x32, body, np.float32(r), f32=True)} == want32
+
+
+def test_forced_decisions_take_the_other_branch():
+    r, dt, mu_k = 0.02, 0.005, 0.3
+    # a tangential slide whose relative displacement lies between 2 r mu_k
+    # and 2 r mu_s: static friction by the oracle's own decision
+    x = np.array([[0.5, 0.5 + 2 * r - 0.01], [0.3, 0.3], [0.5, 0.5]])
+    v = np.array([[0.0, 0.0], [0.0, 0.0], [1.45, -1.45]])
+    prm = _prm()
+    body = np.full(2, P.GRANULAR)
+    _, xt, w = P.predict(x, v, body, np.ones(2), prm)
+    pairs = P.contact_pairs(xt, body, r)
+    rest = np.zeros_like(x)
+    own, info = P.solve_iteration(xt, x, pairs, w, body, rest, prm)
+    n = (xt[:, 1] - xt[:, 0]) / np.linalg.norm(xt[:, 1] - xt[:, 0])
+    Dx = (xt[:, 0] - x[:, 0]) - (xt[:, 1] - x[:, 1])
+    Dt = Dx - (Dx @ n) * n
+    lt = np.linalg.norm(Dt)
+    assert 2 * r * mu_k < lt < 2 * r * 0.35
+    assert info["act"][0] and abs(info["fric_margin"][0] - (lt - 2 * r * 0.35)) < 1e-15
+    # contact switched off: the pair is no constraint, x~ stays as predicted
+    off, _ = P.solve_iteration(xt, x, pairs, w, body, rest, prm, force_act=[0])
+    np.testing.assert_array_equal(off, xt)
+    # kinetic branch forced: the correction along Dt is shorter by
+    # (|Dt| - 2 r mu_k) / 2 (equal masses)
+    kin, _ = P.solve_iteration(xt, x, pairs, w, body, rest, prm, force_static=[0])
+    np.testing.assert_allclose(kin[:, 0] - own[:, 0], 0.5 * (lt - 2 * r * mu_k) * Dt / lt, atol=1e-15)
+    np.testing.assert_allclose(kin[:, 1] - own[:, 1], -0.5 * (lt - 2 * r * mu_k) * Dt / lt, atol=1e-15)
+    # the stabilization iteration honours a forced decision too
+    xs, xts, m = P.stab_iteration(x, xt, P.contact_pairs(x, body, r), w, r, force_act=[0])
+    np.testing.assert_array_equal(xs, x)
+    np.testing.assert_array_equal(xts, xt)
+    assert abs(m[0] + 0.01) < 1e-15
