@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -57,7 +58,8 @@ def parse():
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched legs")
-    ap.add_argument("--only", choices=["drain", "column", "plain", "multirate", "sampling", "diff", "batched"],
+    ap.add_argument("--only", choices=["drain", "column", "plain", "multirate", "sampling", "pbd", "pipeline", "diff",
+                                       "batched"],
                     default=None,
                     help="run one leg only (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -543,6 +545,107 @@ def multirate_leg(args, torch, Upsampler, steps=60, warmup=10, dt_lr=0.005):
             "value": sc.n_hr * steps / el, "unit": "HR particle-updates/s"}
 
 
+def pbd_leg(torch, steps=200, warmup=20, reps=3):
+    """The LR simulation step (Section 3, Algorithm 1: two stabilization and
+    five solver iterations): the column collapse (16,384 granular LR on 7,225
+    static floor samples) and the impact scene (a granular bed, two rigid
+    bodies), after a warm-up into motion."""
+    from workloads import lr_scenes
+    from paper_2308_01629_amd.lr_sim import LRSim
+    res = {}
+    for sc in (lr_scenes.column_collapse(), lr_scenes.impact()):
+        sim = LRSim(sc.body, sc.inv_m, sc.rest, sc.r, sc.domain_lo, sc.domain_hi, dt=sc.dt, g=sc.g,
+                    ground_y=sc.ground_y)
+        x = torch.from_numpy(sc.x).cuda()
+        v = torch.from_numpy(sc.v).cuda()
+        sim.step(x, v, warmup)
+        xs, vs = x.clone(), v.clone()
+        times = []
+        for _ in range(reps):
+            x.copy_(xs)
+            v.copy_(vs)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            sim.step(x, v, steps)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        over = sim.overflow()
+        sim.close()
+        el = float(np.median(times))
+        log(f"pbd {sc.name}: {sc.n} LR ({sc.n_bodies} rigid bodies), {el * 1e3 / steps:.4f} ms/step, "
+            f"{sc.n * steps / el:.3e} LR particle-steps/s")
+        res[sc.name] = {"n_lr": sc.n, "n_static": int((sc.body == lr_scenes.STATIC).sum()),
+                        "n_rigid_bodies": sc.n_bodies, "steps": steps, "ms_per_step": el * 1e3 / steps,
+                        "value": sc.n * steps / el, "unit": "LR particle-steps/s", "neighbour_overflow": over}
+    return res
+
+
+def pipeline_leg(args, torch, Upsampler, hr_steps=60, dt_lr=0.005, n_cand=8_000_000):
+    """The column collapse end to end on the GPU: HR initial state by volume
+    sampling inside the column (r_HR = 0.3 r_LR), LR frames by the LR step
+    at dt_LR = 0.005 s, HR steps of 1/60 s against the LR state interpolated
+    at each HR time level (the static floor samples flagged rigid).  Timed:
+    one simulated second, the LR steps and the HR steps."""
+    from workloads import lr_scenes
+    from workloads.generators import box_walls, volume_candidates
+    from paper_2308_01629_amd.lr_sim import LRSim
+    from paper_2308_01629_amd.upsampler import sample_volume
+    sc = lr_scenes.column_collapse()
+    r_hr = 0.3 * sc.r
+    top = float(sc.x[1, sc.body == lr_scenes.GRANULAR].max()) + sc.r
+    cand, lo, hi = volume_candidates("column", n_cand, [47, 2], top=top)
+    hx = sample_volume(torch.from_numpy(cand).cuda(), r_hr, lo, hi)
+    del cand
+    hv = torch.zeros_like(hx)
+    n_hr = hx.shape[1]
+    dt_hr = 1.0 / 60.0
+    n_lr_steps = int(math.ceil(hr_steps * dt_hr / dt_lr)) + 1
+    walls = np.stack(box_walls(np.zeros(3), np.array([2.0, 1.5, 2.0]))).astype(np.float32)
+    up = Upsampler(sc.r, r_hr, dt_hr, sc.g, sc.domain_lo, sc.domain_hi, walls=walls, max_lr=sc.n, max_hr=n_hr)
+    rigid = torch.from_numpy(sc.lr_rigid).cuda()
+    sim = LRSim(sc.body, sc.inv_m, sc.rest, sc.r, sc.domain_lo, sc.domain_hi, dt=dt_lr, g=sc.g,
+                ground_y=sc.ground_y)
+    LX = torch.empty((n_lr_steps + 1, 3, sc.n), dtype=torch.float32, device="cuda")
+    LV = torch.empty_like(LX)
+    x0 = torch.from_numpy(sc.x).cuda()
+    v0 = torch.from_numpy(sc.v).cuda()
+    hx0, hv0 = hx.clone(), hv.clone()
+    up.sort_hr(hx0, hv0, with_perm=False)
+    t_lr, t_hr = [], []
+    for _ in range(3):
+        x, v = x0.clone(), v0.clone()
+        hx.copy_(hx0)
+        hv.copy_(hv0)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        e[0].record()
+        LX[0].copy_(x)
+        LV[0].copy_(v)
+        sim.step(x, v, n_lr_steps, frames=True, out=(LX[1:], LV[1:]))
+        e[1].record()
+        up.run_multirate(LX, LV, hx, hv, n_steps=hr_steps, dt_lr=dt_lr, sort_every=args.sort_every,
+                         lr_rigid=rigid)
+        e[2].record()
+        torch.cuda.synchronize()
+        t_lr.append(e[0].elapsed_time(e[1]) / 1e3)
+        t_hr.append(e[1].elapsed_time(e[2]) / 1e3)
+    over = sim.overflow()
+    finite = bool(torch.isfinite(hx).all().item())
+    sim.close()
+    up.close()
+    tl, th = float(np.median(t_lr)), float(np.median(t_hr))
+    log(f"pipeline: {sc.n} LR x {n_lr_steps} steps in {tl * 1e3:.1f} ms, {n_hr} HR x {hr_steps} steps in "
+        f"{th * 1e3:.1f} ms: one simulated second in {(tl + th) * 1e3:.1f} ms")
+    return {"workload": "column collapse, LR step + volume-sampled HR + multi-rate upsampling",
+            "n_lr": sc.n, "n_hr": int(n_hr), "lr_steps": n_lr_steps, "hr_steps": hr_steps, "dt_lr": dt_lr,
+            "dt_hr": dt_hr, "lr_ms_per_step": tl * 1e3 / n_lr_steps, "hr_ms_per_step": th * 1e3 / hr_steps,
+            "ms_per_simulated_second": (tl + th) * 1e3, "value": n_hr * hr_steps / (tl + th),
+            "unit": "HR particle-updates/s, LR simulation included", "neighbour_overflow": over,
+            "finite": finite}
+
+
 def sampling_leg(torch, n_cand=16_000_000, reps=3):
     """Randomized volume sampling (Section 4) of the drain's HR initial state
     at its radius (r_LR / 4): 16M random candidates in the silo and hopper
@@ -621,6 +724,10 @@ def main():
         out["multirate"] = multirate_leg(args, torch, Upsampler)
     if args.only == "sampling" or (args.only is None and not args.no_extras):
         out["sampling"] = sampling_leg(torch)
+    if args.only == "pbd" or (args.only is None and not args.no_extras):
+        out["lr_step"] = pbd_leg(torch)
+    if args.only == "pipeline" or (args.only is None and not args.no_extras):
+        out["pipeline"] = pipeline_leg(args, torch, Upsampler)
     if args.only == "diff" or (args.only is None and not args.no_extras):
         out["backward_forward"] = diff_leg(args, torch, Upsampler)
     if args.only == "batched" or (args.only is None and not args.no_extras):

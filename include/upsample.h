@@ -526,6 +526,95 @@ const char* upsample_batch_last_error(upsample_batch b);
  * step kernel's grid (one per tile), out[4] graphs captured so far */
 int upsample_batch_info(upsample_batch b, int64_t* out);
 
+/*
+ * The LR simulation step (Section 3, Algorithm 1): position-based dynamics of
+ * LR particles of radius r with contact and friction constraints, constraint
+ * averaging (each particle's displacements of an iteration summed and divided
+ * by its number of active constraints, all evaluated at the positions the
+ * iteration starts from), stabilization iterations, masses scaled by
+ * exp(-h) (h the height above ground_y), and shape matching of rigid bodies.
+ *
+ * Particles are typed by body[i]: UPSAMPLE_PBD_GRANULAR (-1), UPSAMPLE_PBD_STATIC
+ * (-2: boundary samples that never move, inverse mass 0), or a rigid body id
+ * 0 .. B-1 (dense).  One step of dt:
+ *   1. dynamic particles v += dt g; x~ = x + dt v; w* = w exp(y - ground_y);
+ *   2. contact pairs of x (closer than 2r, no static-static and no same-body
+ *      pairs); stab_iters times: each overlapping pair (i, j) gives i the
+ *      displacement -w*_i/(w*_i + w*_j) (2r - d) x_ij/d, x_ij = x_j - x_i;
+ *      the averages are added to x and to x~;
+ *   3. contact pairs of x~; solve_iters times: each overlapping pair gives
+ *      the contact displacement plus friction on the tangential part Dt of
+ *      the relative displacement (x'_i - x0_i) - (x'_j - x0_j) (x' after the
+ *      contact displacement, x0 the stabilized start positions): the whole
+ *      of Dt if |Dt| < 2 r mu_s, else Dt min(2 r mu_k / |Dt|, 1), shared in
+ *      the inverse-mass ratio; each rigid particle gets R o_i + c - x~_i with
+ *      c the mean of its body's x~ and R the rotation of the polar
+ *      decomposition of sum (x~_i - c) o_i^T (o_i the rest offsets);
+ *   4. v = (x~ - x0) / dt, x = x~ (static particles keep x, v = 0).
+ * Pairs are found on a uniform grid of cells 2r (1.0001) wide over
+ * [domain_lo, domain_hi] (particles outside are clamped into the border
+ * cells: correct, only slower); the pair predicate is the float32 squared
+ * distance (each operation rounded) against fl32(4 r^2).  Each particle keeps
+ * at most max_neighbors pairs per phase; a longer list sets a sticky overflow
+ * flag read by upsample_pbd_status (the extra pairs are dropped).
+ */
+#define UPSAMPLE_PBD_GRANULAR (-1)
+#define UPSAMPLE_PBD_STATIC   (-2)
+
+typedef struct {
+  float r;                 /* LR particle radius (m), > 0 */
+  float dt;                /* LR time step (s), > 0 (Section 5.2: 0.005) */
+  float g[3];              /* gravity (m/s^2) */
+  float mu_s, mu_k;        /* static / kinetic friction (Section 5.2: 0.35, 0.3) */
+  float ground_y;          /* height origin of the mass scaling */
+  int32_t stab_iters;      /* stabilization iterations (Algorithm 1: 2) */
+  int32_t solve_iters;     /* solver iterations (Algorithm 1: 5) */
+  int32_t mass_scaling;    /* 1: w* = w exp(y - ground_y); 0: w */
+  float domain_lo[3];      /* the pair grid's box */
+  float domain_hi[3];
+  int32_t max_neighbors;   /* pairs kept per particle and phase, 1 .. 1024 */
+} upsample_pbd_params;
+
+typedef struct upsample_pbd_s* upsample_pbd;
+
+/* The defaults above, r = 0.02, domain [0, 1]^3, max_neighbors 32. */
+int upsample_pbd_default_params(upsample_pbd_params* p);
+/* body (int32 [n]), inv_mass (float32 [n], >= 0; ignored for static) and
+ * rest (float32 [3][n], rest offsets o_i of rigid particles from their body's
+ * centre of mass, equal masses within a body; ignored for others) are HOST
+ * arrays, copied.  The handle owns device scratch of about (120 + 4 K) B per
+ * particle plus 12 B per grid cell.  Errors: INVALID_ARG (bad parameters,
+ * body ids below -2 or not dense, negative or non-finite inverse masses),
+ * GRID_TOO_LARGE, NO_DEVICE, OOM, HIP. */
+int upsample_pbd_init(const upsample_pbd_params* p, int64_t n, const int32_t* body, const float* inv_mass,
+                      const float* rest, upsample_pbd* out);
+/* Advances the device state x, v (float32 [3][n] each, in place) by n_steps
+ * steps on the stream.  frames_x / frames_v (device float32 [n_steps][3][n],
+ * both or neither) receive the state after each step.  Enqueues work only;
+ * no synchronisation.  Errors: INVALID_ARG, HIP (the handle's last_error
+ * says which call). */
+int upsample_pbd_step(upsample_pbd h, float* x, float* v, int32_t n_steps, float* frames_x, float* frames_v,
+                      void* stream);
+/* Synchronises the stream; *overflow (host) = 1 if some particle had more
+ * than max_neighbors pairs in a phase since init. */
+int upsample_pbd_status(upsample_pbd h, int64_t* overflow, void* stream);
+/* out[0] n, out[1] rigid bodies, out[2] max_neighbors, out[3] grid cells,
+ * out[4] the trace length in floats of upsample_pbd_debug_step. */
+int upsample_pbd_info(upsample_pbd h, int64_t* out);
+/* One step, as upsample_pbd_step, that also records every stage (float32,
+ * device): w* [n]; v and x~ after step 1 [3][n] each; per stabilization
+ * iteration x and x~ [3][n] each; per solver iteration the bodies' c and R
+ * (12 floats per body: c, then R row-major) and x~ [3][n]; the final x and v
+ * [3][n] each.  trace_len must equal out[4] of upsample_pbd_info.  pair_cnt
+ * (device uint32 [2][n]) and pair_ids (device uint32 [2][n][max_neighbors])
+ * receive the pair lists of the stabilization (0) and solver (1) phases:
+ * particle i's partners are pair_ids[phase][i][0 .. pair_cnt[phase][i]).
+ * Synchronises the stream.  A debug entry point. */
+int upsample_pbd_debug_step(upsample_pbd h, float* x, float* v, float* trace, int64_t trace_len,
+                            uint32_t* pair_cnt, uint32_t* pair_ids, void* stream);
+int upsample_pbd_destroy(upsample_pbd h);  /* waits for the device; NULL is a no-op */
+const char* upsample_pbd_last_error(upsample_pbd h);
+
 #ifdef __cplusplus
 }
 #endif

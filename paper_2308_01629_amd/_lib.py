@@ -29,6 +29,8 @@ FLAG_DETERMINISTIC_BWD = 2
 NOALLOC_MAX_LR = 65536
 NOALLOC_MAX_CELLS = 262144
 BATCH_EAGER = 1
+PBD_GRANULAR = -1
+PBD_STATIC = -2
 
 
 class UpsampleError(RuntimeError):
@@ -45,6 +47,16 @@ class Params(ctypes.Structure):
         ("cell_factor", ctypes.c_float), ("n_walls", ctypes.c_int32),
         ("walls", ctypes.POINTER(ctypes.c_float)),
         ("max_lr", ctypes.c_int64), ("max_hr", ctypes.c_int64), ("flags", ctypes.c_uint32),
+    ]
+
+
+class PbdParams(ctypes.Structure):
+    _fields_ = [
+        ("r", ctypes.c_float), ("dt", ctypes.c_float), ("g", ctypes.c_float * 3),
+        ("mu_s", ctypes.c_float), ("mu_k", ctypes.c_float), ("ground_y", ctypes.c_float),
+        ("stab_iters", ctypes.c_int32), ("solve_iters", ctypes.c_int32), ("mass_scaling", ctypes.c_int32),
+        ("domain_lo", ctypes.c_float * 3), ("domain_hi", ctypes.c_float * 3),
+        ("max_neighbors", ctypes.c_int32),
     ]
 
 
@@ -116,6 +128,14 @@ SIGNATURES = {
     "upsample_step_noalloc": (_INT, [ctypes.POINTER(Params), _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P]),
     "upsample_sample_volume": (_INT, [_P, _I64, ctypes.c_float, ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_float), _P, _I64, ctypes.POINTER(_I64), _P]),
+    "upsample_pbd_default_params": (_INT, [ctypes.POINTER(PbdParams)]),
+    "upsample_pbd_init": (_INT, [ctypes.POINTER(PbdParams), _I64, _P, _P, _P, ctypes.POINTER(_P)]),
+    "upsample_pbd_step": (_INT, [_P, _P, _P, _I32, _P, _P, _P]),
+    "upsample_pbd_status": (_INT, [_P, ctypes.POINTER(_I64), _P]),
+    "upsample_pbd_info": (_INT, [_P, ctypes.POINTER(_I64)]),
+    "upsample_pbd_debug_step": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P]),
+    "upsample_pbd_destroy": (_INT, [_P]),
+    "upsample_pbd_last_error": (ctypes.c_char_p, [_P]),
     "upsample_batch_init": (_INT, [ctypes.POINTER(SceneDesc), _I32, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "upsample_batch_step": (_INT, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "upsample_batch_destroy": (_INT, [_P]),

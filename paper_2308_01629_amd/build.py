@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libupsample.so")
-SOURCES = ["grid.hip", "advance.hip", "adjoint.hip", "batched.hip", "autotune.hip", "runtime.hip", "noalloc.hip", "sampling.hip"]
+SOURCES = ["grid.hip", "advance.hip", "adjoint.hip", "batched.hip", "autotune.hip", "runtime.hip", "noalloc.hip", "sampling.hip", "pbd.hip"]
 ARCH = os.environ.get("UPSAMPLE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

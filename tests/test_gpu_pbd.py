@@ -1,0 +1,304 @@
+"""GPU parity of the LR simulation step (upsample_pbd_*; Section 3,
+Algorithm 1) against oracle/pbd_oracle.py.
+
+Stage by stage: ``upsample_pbd_debug_step`` records every stage of one step
+(prediction, the pair lists of both phases, each stabilization iteration, each
+solver iteration with the rigid bodies' centres and rotations, the velocity
+update), and each stage is recomputed by the oracle in float64 from the GPU's
+own float32 input to that stage.
+
+* The pair lists are bit-exact against the oracle's float32 pair predicate.
+* Positions agree within 8 float32 units in the last place of the scene's
+  largest coordinate (a float32 position is known to half a unit; a solver
+  displacement carries a few units from the positions it is formed from).
+* A contact decision (d < 2r) or friction decision (|Dt| < 2 r mu_s) within
+  its rounding band may go either way: a particle off the tolerance passes
+  only if recomputing the stage with the other decision of some in-band pairs
+  next to it matches (the oracle's forced decisions).
+* The velocity update: x bit-exact, v within 4 units of its own magnitude
+  plus the position tolerance over dt.
+
+Scenes (workloads/lr_scenes.py): the column-collapse workload at full size
+(16,384 granular LR on 7,225 static floor samples) and reduced, and an impact
+scene with two rigid bodies, at fresh and moving states.  Plus the frames of a
+multi-step call against single steps, the free fall of a rigid body in closed
+form, invariants over a long run, and edge cases."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import pbd_oracle as P
+from workloads import lr_scenes as S
+
+from gpu_util import dev, host, log
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def LRSim():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_01629_amd.lr_sim import LRSim as cls
+    return cls
+
+
+def _scene(name):
+    return {"column": lambda: S.column_collapse(), "column_small": lambda: S.column_collapse(0.1),
+            "impact": lambda: S.impact(), "impact_small": lambda: S.impact(True)}[name]()
+
+
+def _prm(sc, **kw):
+    """The oracle's parameters: the float32 values the library computes with."""
+    f = lambda a: float(F32(a))
+    base = dict(r=f(sc.r), dt=f(sc.dt), g=tuple(f(a) for a in sc.g), mu_s=f(0.35), mu_k=f(0.3),
+                ground_y=f(sc.ground_y))
+    base.update(kw)
+    return P.PBDParams(**base)
+
+
+def _sim(cls, sc, **kw):
+    return cls(sc.body, sc.inv_m, sc.rest, sc.r, sc.domain_lo, sc.domain_hi, dt=sc.dt, g=sc.g,
+               ground_y=sc.ground_y, **kw)
+
+
+def _f64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+def _check_pairs(cnt, ids, Pos, body, r, what):
+    """The GPU's per-particle lists equal the oracle's float32 pairs; returns
+    the oracle's pairs (i < j)."""
+    n = Pos.shape[1]
+    pairs = P.contact_pairs(np.asarray(Pos, F32), body, F32(r), f32=True)
+    K = ids.shape[1]
+    assert cnt.max(initial=0) <= K
+    owner = np.repeat(np.arange(n, dtype=np.int64), cnt.astype(np.int64))
+    got = owner * n + ids[np.arange(K)[None, :] < cnt[:, None]].astype(np.int64)
+    want = np.concatenate([pairs[:, 0] * n + pairs[:, 1], pairs[:, 1] * n + pairs[:, 0]])
+    got.sort()
+    want.sort()
+    assert got.shape == want.shape and np.array_equal(got, want), \
+        f"{what}: {got.size} GPU pair entries against {want.size}"
+    return pairs
+
+
+def _resolve(what, gpu, run, pairs, tol, band_act, band_fric, n):
+    """Compares a stage's GPU output [3, n] with the oracle's; particles off
+    the tolerance must be explained by in-band decisions of adjacent pairs.
+    run(force_act, force_static) -> (ref [3, n], act, act_margin, fric_margin).
+    Returns the number of particles explained that way."""
+    ref, act, am, fm = run(None, None)
+    err = np.abs(_f64(gpu) - ref).max(axis=0)
+    bad = np.nonzero(err > tol)[0]
+    if bad.size == 0:
+        return 0
+    assert bad.size <= max(8, n // 500), f"{what}: {bad.size} particles off (max {err.max():.3g} > {tol:.3g})"
+    inc = {}
+    for k, (i, j) in enumerate(pairs):
+        inc.setdefault(int(i), []).append(k)
+        inc.setdefault(int(j), []).append(k)
+    done = set()
+    for p in bad.tolist():
+        if p in done:
+            continue
+        cand = [(k, "act") for k in inc.get(p, []) if abs(am[k]) <= band_act]
+        if fm is not None:
+            cand += [(k, "fric") for k in inc.get(p, []) if act[k] and abs(fm[k]) <= band_fric]
+        assert cand, (f"{what}: particle {p} off by {err[p]:.3g} (tol {tol:.3g}) with no contact or "
+                      f"friction decision in band")
+        ok = False
+        for size in range(1, min(len(cand), 4) + 1):
+            for sub in itertools.combinations(cand, size):
+                fa = np.full(len(pairs), -1, np.int8)
+                fs = np.full(len(pairs), -1, np.int8)
+                for k, kind in sub:
+                    if kind == "act":
+                        fa[k] = 0 if am[k] < 0 else 1
+                    else:
+                        fs[k] = 0 if fm[k] < 0 else 1
+                ref2 = run(fa, fs)[0]
+                touched = {p} | {int(q) for k, _ in sub for q in pairs[k]}
+                idx = np.array(sorted(touched))
+                if np.abs(_f64(gpu)[:, idx] - ref2[:, idx]).max() <= tol:
+                    ok = True
+                    done |= touched
+                    break
+            if ok:
+                break
+        assert ok, f"{what}: particle {p} off by {err[p]:.3g}; no in-band decision explains it"
+    return len(done)
+
+
+def check_debug_step(cls, sc, warm_steps, **sim_kw):
+    """Runs warm_steps on the GPU, then one recorded step; checks every stage."""
+    sim = _sim(cls, sc, **sim_kw)
+    prm = _prm(sc, stab_iters=sim.params.stab_iters, solve_iters=sim.params.solve_iters,
+               mass_scaling=bool(sim.params.mass_scaling))
+    x = dev(sc.x, torch)
+    v = dev(sc.v, torch)
+    if warm_steps:
+        sim.step(x, v, warm_steps)
+    x_in, v_in = host(x), host(v)
+    tr = sim.debug_step(x, v)
+    n, r = sc.n, prm.r
+    body = sc.body
+    scale = float(np.abs(x_in).max())
+    tol = 8 * float(np.spacing(F32(max(scale, 0.5))))
+    band_act = 1e-6 * 2 * r
+    band_fric = 2 * tol
+    # 1. prediction
+    v1, xt1, w = P.predict(_f64(x_in), _f64(v_in), body, sc.inv_m, prm)
+    assert np.all(np.abs(tr["w"] - w) <= 4e-7 * np.abs(w) + 1e-30), "scaled inverse masses"
+    assert np.all(np.abs(tr["v_pred"] - v1) <= 4 * np.spacing(np.abs(v1).astype(F32)) + 1e-12), "predicted v"
+    assert np.all(np.abs(tr["xt_pred"] - xt1) <= tol), "predicted x~"
+    w_g = _f64(tr["w"])
+    # 2. stabilization
+    sp = _check_pairs(*tr["pairs"][0], x_in, body, r, "stabilization pairs")
+    xs, xts = x_in, tr["xt_pred"]
+    flips = 0
+    for k, (xg, xtg) in enumerate(tr["stab"]):
+        def run(fa, fs, xs=xs, xts=xts):
+            a, b, m = P.stab_iteration(_f64(xs), _f64(xts), sp, w_g, r, force_act=fa)
+            return np.concatenate([a, b]), None, m, None
+        flips += _resolve(f"stabilization {k}", np.concatenate([xg, xtg]), run, sp, tol, band_act, band_fric, n)
+        xs, xts = xg, xtg
+    x0 = xs
+    # 3. solver
+    pairs = _check_pairs(*tr["pairs"][1], xts, body, r, "solver pairs")
+    cur = xts
+    n_act = 0
+    for k, (frames, xtg) in enumerate(tr["solve"]):
+        def run(fa, fs, cur=cur):
+            out, info = P.solve_iteration(_f64(cur), _f64(x0), pairs, w_g, body, sc.rest, prm, force_act=fa,
+                                          force_static=fs)
+            return out, info["act"], info["act_margin"], info["fric_margin"]
+        _, info = P.solve_iteration(_f64(cur), _f64(x0), pairs, w_g, body, sc.rest, prm)
+        n_act += int(info["act"].sum())
+        for b, (c, R) in info["frames"].items():
+            assert np.abs(frames[b, :3] - c).max() <= tol, f"body {b} centre, iteration {k}"
+            assert np.abs(frames[b, 3:].reshape(3, 3) - R).max() <= 2e-6, f"body {b} rotation, iteration {k}"
+        flips += _resolve(f"solver {k}", xtg, run, pairs, tol, band_act, band_fric, n)
+        cur = xtg
+    # 4. velocities
+    xn, vn = P.finish(_f64(x0), _f64(cur), body, prm.dt)
+    assert np.array_equal(_f64(tr["x"]), xn), "final x"
+    vt = 4 * np.spacing(np.abs(vn).astype(F32)) + float(np.spacing(F32(scale))) / prm.dt
+    assert np.all(np.abs(tr["v"] - vn) <= vt), "final v"
+    assert np.array_equal(host(x), tr["x"]) and np.array_equal(host(v), tr["v"])
+    assert not sim.overflow()
+    log(f"pbd {sc.name} after {warm_steps} steps: n {n}, {len(sp)} / {len(pairs)} pairs, "
+        f"{n_act} active contacts over {len(tr['solve'])} iterations, {flips} particles on a decision band, "
+        f"tolerance {tol:.2e} m")
+    sim.close()
+    return flips
+
+
+@pytest.mark.parametrize("name,warm", [("impact_small", 0), ("impact_small", 14), ("column_small", 25),
+                                       ("impact", 20), ("column", 30)])
+def test_stages_against_oracle(LRSim, name, warm):
+    check_debug_step(LRSim, _scene(name), warm)
+
+
+@pytest.mark.parametrize("kw", [dict(stab_iters=0), dict(solve_iters=0), dict(mass_scaling=False),
+                                dict(stab_iters=1, solve_iters=3)])
+def test_stage_variants(LRSim, kw):
+    check_debug_step(LRSim, _scene("impact_small"), 10, **kw)
+
+
+def test_frames_equal_single_steps(LRSim):
+    sc = _scene("impact_small")
+    sim = _sim(LRSim, sc)
+    xa, va = dev(sc.x, torch), dev(sc.v, torch)
+    fx, fv = sim.step(xa, va, 6, frames=True)
+    xb, vb = dev(sc.x, torch), dev(sc.v, torch)
+    for s in range(6):
+        if s % 2:
+            sim.step(xb, vb, 1)
+        else:
+            sim.debug_step(xb, vb)
+        assert np.array_equal(host(xb), host(fx[s])) and np.array_equal(host(vb), host(fv[s])), f"step {s}"
+    assert np.array_equal(host(xa), host(xb)) and np.array_equal(host(va), host(vb))
+    sim.close()
+
+
+def test_free_fall_and_invariants(LRSim):
+    """The cube of the impact scene falls freely until it meets the sand: its
+    centre follows the closed form; static samples never move; rigid bodies
+    stay rigid to a small fraction of r over 120 steps."""
+    sc = _scene("impact_small")
+    sim = _sim(LRSim, sc)
+    x, v = dev(sc.x, torch), dev(sc.v, torch)
+    fx, fv = sim.step(x, v, 120, frames=True)
+    fx, fv = host(fx), host(fv)
+    cube = sc.body == 1
+    c0 = _f64(sc.x[:, cube]).mean(axis=1)
+    dt, g = float(F32(sc.dt)), np.array([0.0, float(F32(-9.81)), 0.0])
+    v0 = np.array([0.0, -1.0, 0.0])
+    gap = float(sc.x[1, cube].min() - sc.x[1, sc.body == S.GRANULAR].max())
+    free = 0
+    for k in range(1, 121):
+        t = k * dt
+        drop = -(v0[1] * t + g[1] * dt * dt * k * (k + 1) / 2)
+        if drop > gap - 2.2 * sc.r:
+            break
+        c = _f64(fx[k - 1][:, cube]).mean(axis=1)
+        np.testing.assert_allclose(c, c0 + v0 * t + g * dt * dt * k * (k + 1) / 2, atol=2e-6)
+        free += 1
+    assert free >= 2
+    stat = sc.body == S.STATIC
+    assert all(np.array_equal(fx[k][:, stat], sc.x[:, stat]) for k in range(120))
+    assert np.all(fv[:, :, stat] == 0.0)
+    assert np.isfinite(fx).all() and np.isfinite(fv).all()
+    worst = 0.0
+    for b in range(sc.n_bodies):
+        m = sc.body == b
+        for k in (30, 60, 119):
+            X = _f64(fx[k][:, m])
+            c = X.mean(axis=1, keepdims=True)
+            R = P.polar_rotation((X - c) @ _f64(sc.rest[:, m]).T)
+            worst = max(worst, float(np.abs(X - (R @ _f64(sc.rest[:, m]) + c)).max()))
+    assert worst < 0.25 * sc.r, f"rigid bodies deform by {worst / sc.r:.3f} r"
+    assert not sim.overflow()
+    log(f"pbd free fall: {free} steps in closed form; rigid residual {worst / sc.r:.4f} r over 120 steps")
+    sim.close()
+
+
+def test_overflow_flag_and_edges(LRSim):
+    sc = _scene("impact_small")
+    sim = _sim(LRSim, sc, max_neighbors=1)
+    x, v = dev(sc.x, torch), dev(sc.v, torch)
+    sim.step(x, v, 2)
+    assert sim.overflow()
+    assert np.isfinite(host(x)).all()
+    sim.close()
+    # an empty system and zero steps
+    e = LRSim(np.zeros(0, np.int32), np.zeros(0, np.float32), np.zeros((3, 0), np.float32), 0.01,
+              (0, 0, 0), (1, 1, 1))
+    z = torch.zeros((3, 0), dtype=torch.float32, device="cuda")
+    e.step(z, z.clone(), 3)
+    e.close()
+    sim = _sim(LRSim, sc)
+    x, v = dev(sc.x, torch), dev(sc.v, torch)
+    sim.step(x, v, 0)
+    assert np.array_equal(host(x), sc.x)
+    # one particle: free fall in closed form
+    one = LRSim(np.array([-1], np.int32), np.ones(1, np.float32), np.zeros((3, 1), np.float32), 0.01,
+                (0, 0, 0), (1, 1, 1))
+    x1 = dev(np.array([[0.5], [0.7], [0.5]], F32), torch)
+    v1 = dev(np.array([[0.1], [0.0], [-0.2]], F32), torch)
+    one.step(x1, v1, 5)
+    dt, g = float(F32(0.005)), float(F32(-9.81))
+    # v = (x~ - x) / dt carries each step's position rounding (half a unit of
+    # |x| < 1) into the next step, so after k steps x is off by up to
+    # k (k + 1) / 2 such roundings and v by k of them over dt
+    ulp = float(np.spacing(F32(1.0)))
+    np.testing.assert_allclose(host(x1)[:, 0], [0.5 + 5 * dt * 0.1, 0.7 + g * dt * dt * 15, 0.5 - 5 * dt * 0.2],
+                               atol=15 * ulp)
+    np.testing.assert_allclose(host(v1)[:, 0], [0.1, 5 * dt * g, -0.2], atol=2 * 5 * ulp / dt)
+    one.close()
+    sim.close()

@@ -1,0 +1,72 @@
+"""The upsampling driven by the GPU's own LR simulation (Section 3 feeding
+Section 4): HR initial state by volume sampling, LR frames from the LR step at
+dt_LR, HR steps of dt_HR against the interpolated LR state, with the static
+boundary samples and the moving rigid bodies flagged rigid (the rigid rule of
+Section 4 on bodies coupled to the sand by shape matching).  Each HR step is
+compared with the oracle's step of the GPU's own state before it, every
+particle, with the LR state the oracle interpolates from the GPU's frames."""
+import numpy as np
+import pytest
+
+from oracle import multirate_oracle as MR
+from workloads import lr_scenes as S
+from workloads.generators import box_candidates, box_walls
+
+from gpu_util import compare_step, dev, host, log
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DT_LR = 0.005
+DT_HR = 1.0 / 60.0
+
+
+@pytest.fixture(scope="module")
+def libs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_01629_amd.lr_sim import LRSim
+    from paper_2308_01629_amd.upsampler import Upsampler, sample_volume
+    return LRSim, Upsampler, sample_volume
+
+
+def test_impact_scene_upsampled_from_gpu_frames(libs):
+    LRSim, Upsampler, sample_volume = libs
+    sc = S.impact(True)
+    L = float(sc.x[0, sc.body == S.STATIC].max()) - sc.r
+    depth = float(sc.x[1, sc.body == S.GRANULAR].max())
+    r_hr = sc.r / 3
+    cand = box_candidates((0.0, 0.0, 0.0), (L, depth, L), 400_000, [61, 1])
+    hx = sample_volume(dev(cand, torch), r_hr, (0.0, 0.0, 0.0), (L, depth, L))
+    hv = torch.zeros_like(hx)
+    n_hr = hx.shape[1]
+    T = 4
+    n_lr = int(np.ceil(T * DT_HR / DT_LR)) + 1
+    sim = LRSim(sc.body, sc.inv_m, sc.rest, sc.r, sc.domain_lo, sc.domain_hi, dt=DT_LR, g=sc.g)
+    x, v = dev(sc.x, torch), dev(sc.v, torch)
+    fx, fv = sim.step(x, v, n_lr, frames=True)
+    LX = torch.cat([dev(sc.x, torch)[None], fx]).contiguous()
+    LV = torch.cat([dev(sc.v, torch)[None], fv]).contiguous()
+    frames = [(host(LX[k]), host(LV[k])) for k in range(n_lr + 1)]
+    walls = np.stack(box_walls(np.zeros(3), np.array([L, 1.0, L]))).astype(np.float32)
+    up = Upsampler(sc.r, r_hr, DT_HR, sc.g, sc.domain_lo, sc.domain_hi, walls=walls, max_lr=sc.n, max_hr=n_hr)
+    rigid_d = dev(sc.lr_rigid, torch)
+    prm = dict(r_lr=float(np.float32(sc.r)), r_hr=float(np.float32(r_hr)), dt=float(np.float32(DT_HR)),
+               g=np.asarray(sc.g, np.float32), c1=512.0 / 729.0, c2=0.6, domain_lo=sc.domain_lo,
+               domain_hi=sc.domain_hi, walls=walls)
+    rigid = sc.lr_rigid.astype(bool)
+    box = float(np.max(sc.domain_hi - sc.domain_lo))
+    moving = 0
+    for n in range(T):
+        x0, v0 = host(hx).copy(), host(hv).copy()
+        up.run_multirate(LX, LV, hx, hv, n_steps=1, dt_lr=DT_LR, t_hr0=n * DT_HR, lr_rigid=rigid_d)
+        torch.cuda.synchronize()
+        (k, th), = MR.hr_schedule(n * DT_HR, DT_HR, 1, 0.0, DT_LR, len(frames))
+        X, V = MR.lerp_frame_f32(*frames[k], *frames[k + 1], th)
+        s = compare_step(host(hx), host(hv), X, V, rigid, x0, v0, prm, box)
+        moving = max(moving, int((np.abs(V[:, sc.body >= 0]).max(axis=0) > 0.05).sum()))
+        log(f"pipeline impact step {n}: frames {k}, {k + 1}, theta {th:.4f}, {n_hr} HR: {s}")
+    assert moving > 0, "the rigid bodies should be moving"
+    assert not sim.overflow()
+    sim.close()
+    up.close()

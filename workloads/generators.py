@@ -256,6 +256,14 @@ def volume_candidates(geometry: str, n: int, seed, top: Optional[float] = None) 
     return np.ascontiguousarray(P.T, dtype=F32), lo.astype(F32), hi.astype(F32)
 
 
+def box_candidates(lo, hi, n: int, seed) -> np.ndarray:
+    """n random candidate positions uniform in the box [lo, hi], float32
+    [3, n]: the random input of the volume sampling for a box-shaped region."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    P = rng.uniform(np.asarray(lo, float), np.asarray(hi, float), size=(n, 3))
+    return np.ascontiguousarray(P.T, dtype=F32)
+
+
 # ---------------------------------------------------------------------------
 # LR trajectory stand-in.
 # ---------------------------------------------------------------------------
