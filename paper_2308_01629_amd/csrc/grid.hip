@@ -219,6 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ 
                                                    const uint32_t* __restrict__ cell_start, int64_t n,
                                                    FramePair f,
                                                    const uint8_t* __restrict__ rigid,
+                                                   const int32_t* __restrict__ tag,
                                                    uint32_t* __restrict__ perm,
                                                    LRPoint* __restrict__ out) {
   int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -233,7 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ 
   const uint32_t dst = b + rank;
   if (dst >= e) return;
   perm[dst] = i;
-  float flag = (rigid != nullptr && rigid[i] != 0) ? 1.0f : 0.0f;
+  // p.w: the rigid flag as 0 / 1, or the caller's int32 tag as bits
+  float flag = tag != nullptr ? __int_as_float(tag[i]) : ((rigid != nullptr && rigid[i] != 0) ? 1.0f : 0.0f);
   LRPoint o;
   o.p = make_float4(frame_at(f.x0, f.x1, f.theta, i), frame_at(f.x0, f.x1, f.theta, n + i),
                     frame_at(f.x0, f.x1, f.theta, 2 * n + i), flag);
@@ -581,7 +583,8 @@ hipError_t scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t
 }  // namespace
 
 static hipError_t build_grid(const GridConst& gc, const FramePair& f, const uint8_t* lr_rigid, int64_t n_lr,
-                             int64_t n_cells, const GridScratch& s, hipStream_t st) {
+                             int64_t n_cells, const GridScratch& s, hipStream_t st,
+                             const int32_t* tag = nullptr) {
   if (n_lr > 0) {
     hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, gc, f, n_lr,
                        s.keys, s.slot, s.counts);
@@ -602,7 +605,7 @@ static hipError_t build_grid(const GridConst& gc, const FramePair& f, const uint
   }
   if (n_lr > 0) {
     hipLaunchKernelGGL(k_stable, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, s.tmp, s.keys,
-                       s.cell_start, n_lr, f, lr_rigid, s.perm, s.lr_sorted);
+                       s.cell_start, n_lr, f, lr_rigid, tag, s.perm, s.lr_sorted);
   }
   return hipGetLastError();
 }
@@ -611,6 +614,11 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
                              const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
                              const GridScratch& s, hipStream_t st) {
   return build_grid(gc, FramePair{lr_x, lr_v, nullptr, nullptr, 0.0f}, lr_rigid, n_lr, n_cells, s, st);
+}
+
+hipError_t launch_build_grid_tagged(const GridConst& gc, const float* x, const int32_t* tag, int64_t n,
+                                    int64_t n_cells, const GridScratch& s, hipStream_t st) {
+  return build_grid(gc, FramePair{x, x, nullptr, nullptr, 0.0f}, nullptr, n, n_cells, s, st, tag);
 }
 
 // The sorted LR copy as structure-of-arrays [3][n] (debug export).

@@ -61,43 +61,99 @@ __global__ __launch_bounds__(kBlock) void k_pbd_predict(PbdConst pc, int64_t n, 
   w[i] = wi;
 }
 
+// Lanes per particle: the pair search gives each of the 9 stencil rows (dy,
+// dz in {-1, 0, 1}) its own lane; the iterations split a particle's pair
+// list over kIterLanes lanes and sum them by a fixed butterfly.  Small LR
+// systems (tens of thousands of particles) would otherwise leave the chip
+// with about one wave per CU and every wave waiting on memory.
+constexpr int kPairLanes = 16;
+constexpr int kIterLanes = 4;
+
 // Contact list of each particle: the other particles closer than 2r
 // (squared distance rounded as in the upsampling's membership predicate,
-// against fl32(4 r^2)), without static-static and same-body pairs, in grid
-// walk order.  A list longer than K sets *overflow.
+// against fl32(4 r^2)), without static-static and same-body pairs, ordered by
+// stencil row (dz, then dy) and sorted slot.  Groups of kPairLanes lanes take
+// the sorted slots in order (the sorted copy carries each particle's body id
+// in p.w and its index in v.w).  Each row lane reads its candidates four at
+// a time and keeps its first kRowStage matches in LDS; the group forms the
+// exclusive prefix of the lanes' counts and copies the staged ids to the
+// list.  A lane with more matches than it staged scans its row once more for
+// the rest.  A list longer than K sets *overflow and keeps its first K
+// entries.
+constexpr int kRowStage = 8;
+
 __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoint* __restrict__ sorted,
-                                                      const uint32_t* __restrict__ cell_start, int64_t n,
-                                                      const float* __restrict__ P, const int32_t* __restrict__ body,
-                                                      int K, uint32_t* __restrict__ cnt, uint32_t* __restrict__ ids,
+                                                      const uint32_t* __restrict__ cell_start, int64_t n, int K,
+                                                      uint32_t* __restrict__ cnt, uint32_t* __restrict__ ids,
                                                       uint32_t* overflow) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const float x = P[i], y = P[n + i], z = P[2 * n + i];
-  const int bi = body[i];
-  const int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
-  const int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
-  const int cz = cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2]);
-  const int R = gc.reach;
-  uint32_t c = 0;
-  for (int zz = max(cz - R, 0); zz <= min(cz + R, gc.dims[2] - 1); ++zz)
-    for (int yy = max(cy - R, 0); yy <= min(cy + R, gc.dims[1] - 1); ++yy) {
+  __shared__ uint32_t stage[kRowStage][kBlock];
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t t = g / kPairLanes;
+  const int lane = (int)(g % kPairLanes);
+  if (t >= n) return;  // the 16 lanes of a particle leave together
+  const LRPoint me = sorted[t];
+  const uint32_t i = __float_as_uint(me.v.w);
+  const int bi = __float_as_int(me.p.w);
+  const int cx = cell_coord(me.p.x, gc.lo[0], gc.inv_cs, gc.dims[0]);
+  const int cy = cell_coord(me.p.y, gc.lo[1], gc.inv_cs, gc.dims[1]);
+  const int cz = cell_coord(me.p.z, gc.lo[2], gc.inv_cs, gc.dims[2]);
+  uint32_t b = 0, e = 0;
+  if (lane < 9) {
+    const int yy = cy + lane % 3 - 1, zz = cz + lane / 3 - 1;
+    if (yy >= 0 && yy < gc.dims[1] && zz >= 0 && zz < gc.dims[2]) {
       const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
-      const uint32_t b = cell_start[row + (uint32_t)max(cx - R, 0)];
-      const uint32_t e = cell_start[row + (uint32_t)min(cx + R, gc.dims[0] - 1) + 1u];
-      for (uint32_t q = b; q < e; ++q) {
-        const LRPoint L = sorted[q];
-        const uint32_t j = __float_as_uint(L.v.w);
-        if (j == (uint32_t)i) continue;
-        const int bj = body[j];
-        if ((bi == kStatic && bj == kStatic) || (bi >= 0 && bi == bj)) continue;
-        if (sq_dist(L.p.x, L.p.y, L.p.z, x, y, z) < gc.h2) {
-          if ((int)c < K) ids[(int64_t)i * K + c] = j;
-          ++c;
-        }
-      }
+      b = cell_start[row + (uint32_t)max(cx - 1, 0)];
+      e = cell_start[row + (uint32_t)min(cx + 1, gc.dims[0] - 1) + 1u];
     }
-  if ((int)c > K) atomicOr(overflow, 1u);
-  cnt[i] = min(c, (uint32_t)K);
+  }
+  auto match = [&](const LRPoint& L) -> bool {
+    const uint32_t j = __float_as_uint(L.v.w);
+    const int bj = __float_as_int(L.p.w);
+    if (j == i || (bi == kStatic && bj == kStatic) || (bi >= 0 && bi == bj)) return false;
+    return sq_dist(L.p.x, L.p.y, L.p.z, me.p.x, me.p.y, me.p.z) < gc.h2;
+  };
+  uint32_t c = 0;
+  for (uint32_t q0 = b; q0 < e; q0 += 4) {
+    LRPoint L[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q0 + u < e) L[u] = sorted[q0 + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q0 + u < e && match(L[u])) {
+        if (c < (uint32_t)kRowStage) stage[c][threadIdx.x] = __float_as_uint(L[u].v.w);
+        ++c;
+      }
+  }
+  uint32_t incl = c;
+#pragma unroll
+  for (int d = 1; d < kPairLanes; d <<= 1) {
+    const uint32_t u = __shfl_up(incl, d, kPairLanes);
+    if (lane >= d) incl += u;
+  }
+  const uint32_t total = __shfl(incl, kPairLanes - 1, kPairLanes);
+  const uint32_t o0 = incl - c;
+  const uint32_t staged = min(c, (uint32_t)kRowStage);
+  for (uint32_t k = 0; k < staged && o0 + k < (uint32_t)K; ++k) ids[(int64_t)i * K + o0 + k] = stage[k][threadIdx.x];
+  if (c > (uint32_t)kRowStage) {  // rare: the matches beyond the staged ones
+    uint32_t seen = 0, o = o0 + (uint32_t)kRowStage;
+    for (uint32_t q = b; q < e && o < (uint32_t)K; ++q) {
+      const LRPoint L = sorted[q];
+      if (!match(L)) continue;
+      if (++seen > (uint32_t)kRowStage) ids[(int64_t)i * K + o++] = __float_as_uint(L.v.w);
+    }
+  }
+  if (lane == 0) {
+    cnt[i] = min(total, (uint32_t)K);
+    if (total > (uint32_t)K) atomicOr(overflow, 1u);
+  }
+}
+
+// Sum of a float over the kIterLanes lanes of a particle, in a fixed order.
+__device__ __forceinline__ float group_sum(float a) {
+#pragma unroll
+  for (int off = kIterLanes / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kIterLanes);
+  return a;
 }
 
 // Contact displacement of particle i in pair (i, j) at positions Pi, Pj
@@ -127,218 +183,336 @@ __device__ __forceinline__ void load3(const float* a, int64_t n, int64_t i, floa
 }
 
 // 2. One stabilization iteration on the start positions: the averaged
-// contact displacement goes to x (xs_out) and to x~ (in place).
+// contact displacement goes to x (xs_out) and to x~ (in place, by the
+// particle's first lane).
 __global__ __launch_bounds__(kBlock) void k_pbd_stab(PbdConst pc, int64_t n, const float* __restrict__ xs_in,
                                                      float* __restrict__ xs_out, float* __restrict__ xt,
                                                      const float* __restrict__ w, int K,
                                                      const uint32_t* __restrict__ cnt,
                                                      const uint32_t* __restrict__ ids) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = g / kIterLanes;
+  const int l = (int)(g % kIterLanes);
+  if (i >= n) return;  // the lanes of a particle leave together
   float Pi[3];
   load3(xs_in, n, i, Pi);
   const float wi = w[i];
   float acc[3] = {0.f, 0.f, 0.f};
-  int na = 0;
+  float na = 0.0f;
   const uint32_t c = cnt[i];
-  for (uint32_t k = 0; k < c; ++k) {
+  for (uint32_t k = (uint32_t)l; k < c; k += kIterLanes) {
     const int64_t j = ids[i * K + k];
     float Pj[3];
     load3(xs_in, n, j, Pj);
     const float wj = w[j];
-    PairGeo g;
-    if (!contact_geo(Pi, Pj, wi, wj, pc.r2, g)) continue;
+    PairGeo gg;
+    if (!contact_geo(Pi, Pj, wi, wj, pc.r2, gg)) continue;
     const float mi = wi / (wi + wj);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) acc[a] -= mi * g.s * g.xij[a];
-    ++na;
+    for (int a = 0; a < 3; ++a) acc[a] -= mi * gg.s * gg.xij[a];
+    na += 1.0f;
   }
 #pragma unroll
+  for (int a = 0; a < 3; ++a) acc[a] = group_sum(acc[a]);
+  na = group_sum(na);
+  if (l != 0) return;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float u = na > 0 ? acc[a] / (float)na : 0.0f;
+    const float u = na > 0.0f ? acc[a] / na : 0.0f;
     xs_out[a * n + i] = Pi[a] + u;
     xt[a * n + i] += u;
   }
 }
 
-// Shape matching, per rigid body (one block each): centre c = mean of the
-// body's x~, C = sum (x~ - c) o^T in double, and the rotation R of the polar
-// decomposition of C (from the eigenvectors of C^T C, cyclic Jacobi in
-// double): R = sum_k u_k v_k^T with u_k = C v_k / sigma_k for the two largest
-// singular values and u_3 = u_1 x u_2, v_3 signed so that det R = +1.
-// Writes (c, R) as 12 floats per body.
-__device__ void jacobi_eig3(double A[3][3], double V[3][3]) {
+// Shape matching, per rigid body (one wave each): c = the mean of the body's
+// x~ and C = sum (x~ - c) o^T, formed in double in one pass as
+// sum x~ o^T - c (sum o)^T (sum o, a constant of the body, is 0 up to the
+// rounding of the rest offsets), then the rotation R of the polar
+// decomposition of C: the eigenvectors v_k of C^T C by cyclic Jacobi in
+// double, u_k = C v_k / |C v_k| for the two largest eigenvalues,
+// u_3 = u_1 x u_2 and v_3 signed so that det R = +1, R = sum_k u_k v_k^T.
+// (When det C < 0 this takes the nearest rotation, like an SVD with the sign
+// of its smallest singular direction flipped.)  A well-conditioned C with
+// det C > 0, the usual case of a body near its rest shape, takes the scaled
+// Newton iteration for the polar factor instead (Higham 1986,
+// X <- (z X + X^-T / z) / 2, z = sqrt(|X^-1|_F / |X|_F)), which reaches the
+// same rotation with far fewer square roots and divisions.  Writes (c, R
+// row-major) as 12 floats per body.
+constexpr int kShapeThreads = 256;
+
+template <int P, int Q>
+__device__ __forceinline__ void jacobi_rot(double (&A)[3][3], double (&V)[3][3]) {
+  if (A[P][Q] == 0.0) return;
+  const double theta = (A[Q][Q] - A[P][P]) / (2.0 * A[P][Q]);
+  const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+  const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {  // A <- A J
+    const double akp = A[k][P], akq = A[k][Q];
+    A[k][P] = c * akp - s * akq;
+    A[k][Q] = s * akp + c * akq;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {  // A <- J^T A
+    const double apk = A[P][k], aqk = A[Q][k];
+    A[P][k] = c * apk - s * aqk;
+    A[Q][k] = s * apk + c * aqk;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {  // V <- V J
+    const double vkp = V[k][P], vkq = V[k][Q];
+    V[k][P] = c * vkp - s * vkq;
+    V[k][Q] = s * vkp + c * vkq;
+  }
+}
+
+// Orders eigenpairs (diagonal of A, columns of V) by decreasing eigenvalue.
+template <int P, int Q>
+__device__ __forceinline__ void eig_order(double (&A)[3][3], double (&V)[3][3]) {
+  if (A[Q][Q] > A[P][P]) {
+    const double t = A[P][P];
+    A[P][P] = A[Q][Q];
+    A[Q][Q] = t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double u = V[k][P];
+      V[k][P] = V[k][Q];
+      V[k][Q] = u;
+    }
+  }
+}
+
+__device__ void polar_rotation(const double (&M)[3][3], double (&R)[3][3]) {
+  double A[3][3], V[3][3];
+#pragma unroll
   for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) V[a][b] = a == b ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      A[a][c] = M[0][a] * M[0][c] + M[1][a] * M[1][c] + M[2][a] * M[2][c];
+      V[a][c] = a == c ? 1.0 : 0.0;
+    }
   const double scale = fabs(A[0][0]) + fabs(A[1][1]) + fabs(A[2][2]);
   for (int sweep = 0; sweep < 32; ++sweep) {
     const double off = fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
     if (!(off > 1e-30 * scale)) break;
-    for (int p = 0; p < 2; ++p)
-      for (int q = p + 1; q < 3; ++q) {
-        if (A[p][q] == 0.0) continue;
-        const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
-        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < 3; ++k) {  // A <- J^T A J
-          const double akp = A[k][p], akq = A[k][q];
-          A[k][p] = c * akp - s * akq;
-          A[k][q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < 3; ++k) {
-          const double apk = A[p][k], aqk = A[q][k];
-          A[p][k] = c * apk - s * aqk;
-          A[q][k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < 3; ++k) {
-          const double vkp = V[k][p], vkq = V[k][q];
-          V[k][p] = c * vkp - s * vkq;
-          V[k][q] = s * vkp + c * vkq;
-        }
-      }
+    jacobi_rot<0, 1>(A, V);
+    jacobi_rot<0, 2>(A, V);
+    jacobi_rot<1, 2>(A, V);
   }
-}
-
-__global__ __launch_bounds__(kBlock) void k_pbd_shape(int64_t n, const float* __restrict__ xt,
-                                                      const uint32_t* __restrict__ members,
-                                                      const uint32_t* __restrict__ body_ptr,
-                                                      const float* __restrict__ rest, float* __restrict__ cr) {
-  __shared__ double red[kBlock][9];
-  __shared__ double cen[3];
-  const int b = blockIdx.x;
-  const uint32_t p0 = body_ptr[b], p1 = body_ptr[b + 1];
-  const int t = threadIdx.x;
-  double s[3] = {0.0, 0.0, 0.0};
-  for (uint32_t q = p0 + t; q < p1; q += kBlock) {
-    const int64_t i = members[q];
-    for (int a = 0; a < 3; ++a) s[a] += (double)xt[a * n + i];
-  }
-  for (int a = 0; a < 3; ++a) red[t][a] = s[a];
-  __syncthreads();
-  for (int h = kBlock / 2; h > 0; h >>= 1) {
-    if (t < h)
-      for (int a = 0; a < 3; ++a) red[t][a] += red[t + h][a];
-    __syncthreads();
-  }
-  if (t == 0)
-    for (int a = 0; a < 3; ++a) cen[a] = red[0][a] / (double)(p1 - p0);
-  __syncthreads();
-  double C[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (uint32_t q = p0 + t; q < p1; q += kBlock) {
-    const int64_t i = members[q];
-    double dxa[3], o[3];
-    for (int a = 0; a < 3; ++a) {
-      dxa[a] = (double)xt[a * n + i] - cen[a];
-      o[a] = (double)rest[a * n + i];
-    }
-    for (int a = 0; a < 3; ++a)
-      for (int c = 0; c < 3; ++c) C[3 * a + c] += dxa[a] * o[c];
-  }
-  __syncthreads();
-  for (int k = 0; k < 9; ++k) red[t][k] = C[k];
-  __syncthreads();
-  for (int h = kBlock / 2; h > 0; h >>= 1) {
-    if (t < h)
-      for (int k = 0; k < 9; ++k) red[t][k] += red[t + h][k];
-    __syncthreads();
-  }
-  if (t != 0) return;
-  double M[3][3], A[3][3], V[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int c = 0; c < 3; ++c) M[a][c] = red[0][3 * a + c];
-  for (int a = 0; a < 3; ++a)
-    for (int c = 0; c < 3; ++c) {
-      double acc = 0.0;
-      for (int k = 0; k < 3; ++k) acc += M[k][a] * M[k][c];
-      A[a][c] = acc;
-    }
-  jacobi_eig3(A, V);
-  // order the eigenpairs by decreasing eigenvalue
-  int ord[3] = {0, 1, 2};
-  for (int x = 0; x < 2; ++x)
-    for (int y = x + 1; y < 3; ++y)
-      if (A[ord[y]][ord[y]] > A[ord[x]][ord[x]]) {
-        const int tmp = ord[x];
-        ord[x] = ord[y];
-        ord[y] = tmp;
-      }
-  double v[3][3], u[3][3];
-  for (int k = 0; k < 3; ++k)
-    for (int a = 0; a < 3; ++a) v[k][a] = V[a][ord[k]];
+  eig_order<0, 1>(A, V);
+  eig_order<0, 2>(A, V);
+  eig_order<1, 2>(A, V);
+  double u[3][3];
+#pragma unroll
   for (int k = 0; k < 2; ++k) {
     double nrm = 0.0;
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-      double acc = 0.0;
-      for (int c = 0; c < 3; ++c) acc += M[a][c] * v[k][c];
-      u[k][a] = acc;
-      nrm += acc * acc;
+      u[k][a] = M[a][0] * V[0][k] + M[a][1] * V[1][k] + M[a][2] * V[2][k];
+      nrm += u[k][a] * u[k][a];
     }
     nrm = sqrt(nrm);
+#pragma unroll
     for (int a = 0; a < 3; ++a) u[k][a] = nrm > 0.0 ? u[k][a] / nrm : (a == k ? 1.0 : 0.0);
   }
   u[2][0] = u[0][1] * u[1][2] - u[0][2] * u[1][1];
   u[2][1] = u[0][2] * u[1][0] - u[0][0] * u[1][2];
   u[2][2] = u[0][0] * u[1][1] - u[0][1] * u[1][0];
-  const double detv = v[0][0] * (v[1][1] * v[2][2] - v[1][2] * v[2][1]) -
-                      v[0][1] * (v[1][0] * v[2][2] - v[1][2] * v[2][0]) +
-                      v[0][2] * (v[1][0] * v[2][1] - v[1][1] * v[2][0]);
-  if (detv < 0.0)
-    for (int a = 0; a < 3; ++a) v[2][a] = -v[2][a];
-  float* o = cr + 12 * b;
-  for (int a = 0; a < 3; ++a) o[a] = (float)cen[a];
+  const double detv = V[0][0] * (V[1][1] * V[2][2] - V[2][1] * V[1][2]) -
+                      V[0][1] * (V[1][0] * V[2][2] - V[2][0] * V[1][2]) +
+                      V[0][2] * (V[1][0] * V[2][1] - V[2][0] * V[1][1]);
+  const double sg = detv < 0.0 ? -1.0 : 1.0;
+#pragma unroll
   for (int a = 0; a < 3; ++a)
-    for (int c = 0; c < 3; ++c) {
-      double acc = 0.0;
-      for (int k = 0; k < 3; ++k) acc += u[k][a] * v[k][c];
-      o[3 + 3 * a + c] = (float)acc;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R[a][c] = u[0][a] * V[c][0] + u[1][a] * V[c][1] + sg * u[2][a] * V[c][2];
+}
+
+// Polar rotation by the scaled Newton iteration; false if M is not proper and
+// well conditioned (the caller then takes the eigenvector path).
+__device__ bool polar_newton(const double (&M)[3][3], double (&R)[3][3]) {
+  double fro = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fro += M[a][c] * M[a][c];
+  fro = sqrt(fro / 3.0);
+  if (!(fro > 0.0)) return false;
+  const double ifro = 1.0 / fro;
+  double X[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) X[a][c] = M[a][c] * ifro;
+  for (int it = 0; it < 40; ++it) {
+    // cofactors: X^-T = cof(X) / det X
+    double C[3][3];
+    C[0][0] = X[1][1] * X[2][2] - X[1][2] * X[2][1];
+    C[0][1] = X[1][2] * X[2][0] - X[1][0] * X[2][2];
+    C[0][2] = X[1][0] * X[2][1] - X[1][1] * X[2][0];
+    C[1][0] = X[0][2] * X[2][1] - X[0][1] * X[2][2];
+    C[1][1] = X[0][0] * X[2][2] - X[0][2] * X[2][0];
+    C[1][2] = X[0][1] * X[2][0] - X[0][0] * X[2][1];
+    C[2][0] = X[0][1] * X[1][2] - X[0][2] * X[1][1];
+    C[2][1] = X[0][2] * X[1][0] - X[0][0] * X[1][2];
+    C[2][2] = X[0][0] * X[1][1] - X[0][1] * X[1][0];
+    const double det = X[0][0] * C[0][0] + X[0][1] * C[0][1] + X[0][2] * C[0][2];
+    if (it == 0 && !(det > 1e-6)) return false;  // improper or near-singular
+    const double id = 1.0 / det;
+    double nx = 0.0, ny = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C[a][c] *= id;
+        nx += X[a][c] * X[a][c];
+        ny += C[a][c] * C[a][c];
+      }
+    const double z = sqrt(sqrt(ny / nx));
+    const double hz = 0.5 * z, hiz = 0.5 / z;
+    double diff = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double xn = hz * X[a][c] + hiz * C[a][c];
+        diff += (xn - X[a][c]) * (xn - X[a][c]);
+        X[a][c] = xn;
+      }
+    if (diff < 1e-26) break;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R[a][c] = X[a][c];
+  return true;
+}
+
+__global__ __launch_bounds__(kShapeThreads) void k_pbd_shape(int64_t n, const float* __restrict__ xt,
+                                                             const uint32_t* __restrict__ members,
+                                                             const uint32_t* __restrict__ body_ptr,
+                                                             const float* __restrict__ rest,
+                                                             const double* __restrict__ osum,
+                                                             float* __restrict__ cr) {
+  __shared__ double part[kShapeThreads / 64][12];
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const uint32_t p0 = body_ptr[b], p1 = body_ptr[b + 1];
+  double s[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) s[k] = 0.0;
+  for (uint32_t q = p0 + (uint32_t)tid; q < p1; q += kShapeThreads) {
+    const int64_t i = members[q];
+    double xa[3], o[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      xa[a] = (double)xt[a * n + i];
+      o[a] = (double)rest[a * n + i];
     }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      s[a] += xa[a];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s[3 + 3 * a + c] += xa[a] * o[c];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] += __shfl_xor(s[k], off, 64);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) part[tid >> 6][k] = s[k];
+  __syncthreads();
+  if (tid != 0) return;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    double t = part[0][k];
+#pragma unroll
+    for (int w = 1; w < kShapeThreads / 64; ++w) t += part[w][k];
+    s[k] = t;
+  }
+  const double im = 1.0 / (double)(p1 - p0);
+  double cen[3], M[3][3], R[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) cen[a] = s[a] * im;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) M[a][c] = s[3 + 3 * a + c] - cen[a] * osum[3 * b + c];
+  if (!polar_newton(M, R)) polar_rotation(M, R);
+  float* o = cr + 12 * b;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) o[a] = (float)cen[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o[3 + 3 * a + c] = (float)R[a][c];
 }
 
 // 3. One solver iteration: contact and friction of each pair (one constraint)
-// plus the shape-matching displacement of rigid particles, averaged.
+// plus the shape-matching displacement of rigid particles, averaged.  With
+// FINISH (the last iteration, x0 not aliasing x) the particle's first lane
+// also does step 4: v = (x~ - x0) / dt, x = x~ (static particles keep x0,
+// v = 0), and copies the state into the frame buffers if given.
+struct FinishArgs {
+  float* x;
+  float* v;
+  float* fx;
+  float* fv;
+};
+
+template <bool FINISH>
 __global__ __launch_bounds__(kBlock) void k_pbd_solve(PbdConst pc, int64_t n, const float* __restrict__ xt_in,
                                                       float* __restrict__ xt_out, const float* __restrict__ x0,
                                                       const float* __restrict__ w, int K,
                                                       const uint32_t* __restrict__ cnt,
                                                       const uint32_t* __restrict__ ids,
                                                       const int32_t* __restrict__ body,
-                                                      const float* __restrict__ rest, const float* __restrict__ cr) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+                                                      const float* __restrict__ rest, const float* __restrict__ cr,
+                                                      FinishArgs fin) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = g / kIterLanes;
+  const int l = (int)(g % kIterLanes);
+  if (i >= n) return;  // the lanes of a particle leave together
   float Pi[3], X0i[3];
   load3(xt_in, n, i, Pi);
   load3(x0, n, i, X0i);
   const float wi = w[i];
   float acc[3] = {0.f, 0.f, 0.f};
-  int na = 0;
+  float na = 0.0f;
   const uint32_t c = cnt[i];
-  for (uint32_t k = 0; k < c; ++k) {
+  for (uint32_t k = (uint32_t)l; k < c; k += kIterLanes) {
     const int64_t j = ids[i * K + k];
     float Pj[3], X0j[3];
     load3(xt_in, n, j, Pj);
     const float wj = w[j];
-    PairGeo g;
-    if (!contact_geo(Pi, Pj, wi, wj, pc.r2, g)) continue;
     load3(x0, n, j, X0j);
+    PairGeo gg;
+    if (!contact_geo(Pi, Pj, wi, wj, pc.r2, gg)) continue;
     const float mi = wi / (wi + wj), mj = wj / (wi + wj);
     float Dx[3], ci[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      ci[a] = -mi * g.s * g.xij[a];
-      const float cj = mj * g.s * g.xij[a];
+      ci[a] = -mi * gg.s * gg.xij[a];
+      const float cj = mj * gg.s * gg.xij[a];
       Dx[a] = ((Pi[a] + ci[a]) - X0i[a]) - ((Pj[a] + cj) - X0j[a]);
     }
     // friction on the part of Dx perpendicular to x_ij
-    const float dn = fmaf(Dx[2], g.xij[2], fmaf(Dx[1], g.xij[1], Dx[0] * g.xij[0])) / g.d2;
+    const float dn = fmaf(Dx[2], gg.xij[2], fmaf(Dx[1], gg.xij[1], Dx[0] * gg.xij[0])) / gg.d2;
     float Dt[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Dt[a] = Dx[a] - dn * g.xij[a];
+    for (int a = 0; a < 3; ++a) Dt[a] = Dx[a] - dn * gg.xij[a];
     const float lt = sqrtf(fmaf(Dt[2], Dt[2], fmaf(Dt[1], Dt[1], Dt[0] * Dt[0])));
     const float scale = lt < pc.mu_s2r ? 1.0f : fminf(pc.mu_k2r / lt, 1.0f);
 #pragma unroll
     for (int a = 0; a < 3; ++a) acc[a] += ci[a] - mi * (Dt[a] * scale);
-    ++na;
+    na += 1.0f;
   }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) acc[a] = group_sum(acc[a]);
+  na = group_sum(na);
+  if (l != 0) return;
   const int bi = body[i];
   if (bi >= 0) {
     const float* q = cr + 12 * bi;
@@ -349,16 +523,30 @@ __global__ __launch_bounds__(kBlock) void k_pbd_solve(PbdConst pc, int64_t n, co
       const float ro = fmaf(q[3 + 3 * a + 2], o[2], fmaf(q[3 + 3 * a + 1], o[1], q[3 + 3 * a] * o[0]));
       acc[a] += (ro + q[a]) - Pi[a];
     }
-    ++na;
+    na += 1.0f;
   }
+  const bool stat = bi == kStatic;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) xt_out[a * n + i] = Pi[a] + (na > 0 ? acc[a] / (float)na : 0.0f);
+  for (int a = 0; a < 3; ++a) {
+    const float xn = Pi[a] + (na > 0.0f ? acc[a] / na : 0.0f);
+    xt_out[a * n + i] = xn;
+    if (FINISH) {
+      const float xf = stat ? X0i[a] : xn;
+      const float vf = stat ? 0.0f : (xf - X0i[a]) * pc.inv_dt;
+      fin.x[a * n + i] = xf;
+      fin.v[a * n + i] = vf;
+      if (fin.fx != nullptr) {
+        fin.fx[a * n + i] = xf;
+        fin.fv[a * n + i] = vf;
+      }
+    }
+  }
 }
 
-// 4. v = (x~ - x0) / dt, x = x~ (static particles keep x0, v = 0), x0 the
-// stabilized start positions; optionally the new state into a frame buffer.
-// x0 may alias x (not restrict-qualified): each thread reads its element
-// before writing it.
+// 4. (when not fused into the last solver iteration) v = (x~ - x0) / dt,
+// x = x~ (static particles keep x0, v = 0), x0 the stabilized start
+// positions; optionally the new state into a frame buffer.  x0 may alias x
+// (not restrict-qualified): each thread reads its element before writing it.
 __global__ __launch_bounds__(kBlock) void k_pbd_finish(PbdConst pc, int64_t n, const float* x0,
                                                        const float* __restrict__ xt,
                                                        const int32_t* __restrict__ body, float* x,
@@ -379,6 +567,11 @@ __global__ __launch_bounds__(kBlock) void k_pbd_finish(PbdConst pc, int64_t n, c
       fv[a * n + i] = vn;
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_u32(uint32_t* __restrict__ p, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < m) p[i] = 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy_f32(float* __restrict__ dst, const float* __restrict__ src,
@@ -405,8 +598,9 @@ struct upsample_pbd_s {
   float* rest;
   uint32_t* members;
   uint32_t* body_ptr;
+  double* osum;  // [n_bodies][3] sum of each body's rest offsets
   float* cr;
-  float *w, *xt, *xt2, *xs;
+  float *w, *xt, *xt2, *xs, *xs2;
   uint32_t *cnt, *ids, *overflow;
   std::string last_error;
 };
@@ -420,8 +614,8 @@ int pbd_fail(upsample_pbd h, int code, const std::string& m) {
 
 void pbd_free(upsample_pbd h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
-                  h->g.cell_start, h->g.lr_sorted, h->body, h->inv_m, h->rest, h->members, h->body_ptr, h->cr,
-                  h->w, h->xt, h->xt2, h->xs, h->cnt, h->ids, h->overflow};
+                  h->g.cell_start, h->g.lr_sorted, h->body, h->inv_m, h->rest, h->members, h->body_ptr, h->osum,
+                  h->cr, h->w, h->xt, h->xt2, h->xs, h->xs2, h->cnt, h->ids, h->overflow};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
 }
@@ -476,14 +670,18 @@ hipError_t copy_pairs(const upsample_pbd_s* h, const PbdTrace* tr, int phase, hi
   return e;
 }
 
-// One step (Algorithm 1).  The stabilization ping-pongs between x and h->xs,
-// the solver between h->xt and h->xt2.  With a trace, every stage is copied
-// out behind its kernel.
+// One step (Algorithm 1).  The stabilization reads x and then alternates
+// between h->xs and h->xs2, so the stabilized start positions x0 never alias
+// x when there is at least one iteration and the last solver iteration can
+// write the new state itself; the solver alternates between h->xt and
+// h->xt2.  With a trace, every stage is copied out behind its kernel.
 hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float* fv, const PbdTrace* tr,
                         hipStream_t st) {
   const int64_t n = h->n;
   const PbdConst pc = pbd_const(h->p);
   const unsigned nb = nblocks(n);
+  const unsigned nb_pairs = nblocks(n * kPairLanes);
+  const unsigned nb_iter = nblocks(n * kIterLanes);
   const int K = h->K;
   float* rec = tr != nullptr ? tr->base : nullptr;
   hipError_t e = hipSuccess;
@@ -498,37 +696,49 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
   record(v, 3 * n);
   record(h->xt, 3 * n);
   // 2. stabilization on the start positions
-  float* sa = x;
-  float* sb = h->xs;
-  if (e == hipSuccess) e = launch_build_grid(h->gc, sa, sa, nullptr, n, h->n_cells, h->g, st);
-  if (e == hipSuccess)
-    hipLaunchKernelGGL(k_pbd_pairs, dim3(nb), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start, n, sa,
-                       h->body, K, h->cnt, h->ids, h->overflow);
-  if (e == hipSuccess && tr != nullptr) e = copy_pairs(h, tr, 0, st);
-  for (int it = 0; it < h->p.stab_iters && e == hipSuccess; ++it) {
-    hipLaunchKernelGGL(k_pbd_stab, dim3(nb), dim3(kBlock), 0, st, pc, n, sa, sb, h->xt, h->w, K, h->cnt, h->ids);
+  const float* x0 = x;
+  if (h->p.stab_iters == 0 && tr != nullptr && e == hipSuccess) {
+    // no stabilization pairs: the trace's lists of that phase are empty
+    hipLaunchKernelGGL(k_zero_u32, dim3(nb), dim3(kBlock), 0, st, tr->pair_cnt, n);
     e = hipGetLastError();
-    float* t = sa;
-    sa = sb;
-    sb = t;
-    record(sa, 3 * n);
-    record(h->xt, 3 * n);
   }
-  const float* x0 = sa;  // stabilized start positions
+  if (h->p.stab_iters > 0) {
+    if (e == hipSuccess) e = launch_build_grid_tagged(h->gc, x, h->body, n, h->n_cells, h->g, st);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(k_pbd_pairs, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start,
+                         n, K, h->cnt, h->ids, h->overflow);
+    if (e == hipSuccess && tr != nullptr) e = copy_pairs(h, tr, 0, st);
+    float* out = h->xs;
+    for (int it = 0; it < h->p.stab_iters && e == hipSuccess; ++it) {
+      hipLaunchKernelGGL(k_pbd_stab, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, x0, out, h->xt, h->w, K, h->cnt,
+                         h->ids);
+      e = hipGetLastError();
+      x0 = out;
+      out = out == h->xs ? h->xs2 : h->xs;
+      record(x0, 3 * n);
+      record(h->xt, 3 * n);
+    }
+  }
   // 3. solver iterations on x~
   float* ta = h->xt;
   float* tb = h->xt2;
-  if (e == hipSuccess) e = launch_build_grid(h->gc, ta, ta, nullptr, n, h->n_cells, h->g, st);
+  if (e == hipSuccess) e = launch_build_grid_tagged(h->gc, ta, h->body, n, h->n_cells, h->g, st);
   if (e == hipSuccess)
-    hipLaunchKernelGGL(k_pbd_pairs, dim3(nb), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start, n, ta,
-                       h->body, K, h->cnt, h->ids, h->overflow);
+    hipLaunchKernelGGL(k_pbd_pairs, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start, n,
+                       K, h->cnt, h->ids, h->overflow);
   if (e == hipSuccess && tr != nullptr) e = copy_pairs(h, tr, 1, st);
+  const bool fuse = x0 != x && h->p.solve_iters > 0;
+  const FinishArgs fin{x, v, fx, fv};
   for (int it = 0; it < h->p.solve_iters && e == hipSuccess; ++it) {
     if (h->n_bodies > 0)
-      hipLaunchKernelGGL(k_pbd_shape, dim3((unsigned)h->n_bodies), dim3(kBlock), 0, st, n, ta, h->members,
-                         h->body_ptr, h->rest, h->cr);
-    hipLaunchKernelGGL(k_pbd_solve, dim3(nb), dim3(kBlock), 0, st, pc, n, ta, tb, x0, h->w, K, h->cnt, h->ids,
-                       h->body, h->rest, h->cr);
+      hipLaunchKernelGGL(k_pbd_shape, dim3((unsigned)h->n_bodies), dim3(kShapeThreads), 0, st, n, ta, h->members,
+                         h->body_ptr, h->rest, h->osum, h->cr);
+    if (fuse && it == h->p.solve_iters - 1)
+      hipLaunchKernelGGL(k_pbd_solve<true>, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, ta, tb, x0, h->w, K, h->cnt,
+                         h->ids, h->body, h->rest, h->cr, fin);
+    else
+      hipLaunchKernelGGL(k_pbd_solve<false>, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, ta, tb, x0, h->w, K,
+                         h->cnt, h->ids, h->body, h->rest, h->cr, fin);
     e = hipGetLastError();
     float* t = ta;
     ta = tb;
@@ -536,9 +746,8 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
     record(h->cr, 12 * (int64_t)h->n_bodies);
     record(ta, 3 * n);
   }
-  // 4. velocities; x0 may be x itself (an even number of stabilization
-  // iterations): each thread reads its own element before writing it
-  if (e == hipSuccess) {
+  // 4. velocities, unless the last solver iteration wrote them
+  if (e == hipSuccess && !fuse) {
     hipLaunchKernelGGL(k_pbd_finish, dim3(nb), dim3(kBlock), 0, st, pc, n, x0, ta, h->body, x, v, fx, fv);
     e = hipGetLastError();
   }
@@ -646,11 +855,13 @@ int upsample_pbd_init(const upsample_pbd_params* p, int64_t n, const int32_t* bo
   ALLOC(h->rest, 3 * n)
   ALLOC(h->members, (int64_t)members.size())
   ALLOC(h->body_ptr, n_bodies + 1)
+  ALLOC(h->osum, 3 * (int64_t)n_bodies)
   ALLOC(h->cr, 12 * (int64_t)n_bodies)
   ALLOC(h->w, n)
   ALLOC(h->xt, 3 * n)
   ALLOC(h->xt2, 3 * n)
   ALLOC(h->xs, 3 * n)
+  ALLOC(h->xs2, 3 * n)
   ALLOC(h->cnt, n)
   ALLOC(h->ids, n * (int64_t)h->K)
   ALLOC(h->overflow, 1)
@@ -661,6 +872,13 @@ int upsample_pbd_init(const upsample_pbd_params* p, int64_t n, const int32_t* bo
   if (e == hipSuccess && !members.empty())
     e = hipMemcpy(h->members, members.data(), sizeof(uint32_t) * members.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(h->body_ptr, ptr.data(), sizeof(uint32_t) * ptr.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_bodies > 0) {
+    std::vector<double> os((size_t)n_bodies * 3, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      if (body[i] >= 0)
+        for (int a = 0; a < 3; ++a) os[(size_t)body[i] * 3 + a] += (double)rest[a * n + i];
+    e = hipMemcpy(h->osum, os.data(), sizeof(double) * os.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMemset(h->g.counts, 0, sizeof(uint32_t) * (size_t)n_cells);
   if (e == hipSuccess) e = hipMemset(h->overflow, 0, sizeof(uint32_t));
   if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -158,7 +158,11 @@ def check_debug_step(cls, sc, warm_steps, **sim_kw):
     assert np.all(np.abs(tr["xt_pred"] - xt1) <= tol), "predicted x~"
     w_g = _f64(tr["w"])
     # 2. stabilization
-    sp = _check_pairs(*tr["pairs"][0], x_in, body, r, "stabilization pairs")
+    if prm.stab_iters:
+        sp = _check_pairs(*tr["pairs"][0], x_in, body, r, "stabilization pairs")
+    else:
+        assert not tr["pairs"][0][0].any()
+        sp = np.zeros((0, 2), np.int64)
     xs, xts = x_in, tr["xt_pred"]
     flips = 0
     for k, (xg, xtg) in enumerate(tr["stab"]):
