@@ -391,7 +391,7 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
             "rollout_forward_backward_ms": t_rfb, "rollout_backward_over_forward": (t_rfb - t_rf) / t_rf}
 
 
-def batched_leg(args, torch, Upsampler, steps=10, warmup=2):
+def batched_leg(args, torch, Upsampler, steps=10, warmup=2, aging_steps=40):
     """64 scenes (heap / column / drain, N_H log-uniform in [50k, 1M], N_L =
     N_H / 32): one graph replay of the batched step per step vs 64 plain
     upsample_step calls from Python, same inputs; the final states of both
@@ -491,6 +491,35 @@ def batched_leg(args, torch, Upsampler, steps=10, warmup=2):
     same = all(torch.equal(gx, x) and torch.equal(gv, v)
                for gx, gv, x, v in zip(b.split_hr(hx), b.split_hr(hv), xs, vs))
     info = b.info()
+    # a longer run (the frames replayed in a cycle): without a reorder the
+    # waves age as the particles move apart; upsample_batch_sort_hr every
+    # 10 steps keeps them compact
+    hx0, hv0 = hx.clone(), hv.clone()
+    aging = {}
+    for label, every in (("no_reorder", 0), ("reorder_every_10", 10)):
+        hx.copy_(hx0)
+        hv.copy_(hv0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(aging_steps):
+            if every and k % every == every - 1:
+                b.sort_hr(hx, hv, with_perm=False)
+            t = k % n_frames
+            lx.copy_(LXb[t])
+            lv.copy_(LVb[t])
+            b.step(lx, lv, hx, hv, out_x=hx, out_v=hv)
+        e1.record()
+        torch.cuda.synchronize()
+        aging[label] = e0.elapsed_time(e1) / aging_steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.sort_hr(hx, hv, with_perm=False)
+    e1.record()
+    torch.cuda.synchronize()
+    aging["reorder_ms"] = e0.elapsed_time(e1)
+    log(f"batched: {aging_steps}-step run {aging['no_reorder']:.3f} ms/step without reorder, "
+        f"{aging['reorder_every_10']:.3f} with a reorder every 10 steps (one reorder {aging['reorder_ms']:.3f} ms)")
     b.close()
     for up in plain:
         up.close()
@@ -501,7 +530,8 @@ def batched_leg(args, torch, Upsampler, steps=10, warmup=2):
             "speedup": t_p / t_b, "batched_hr_updates_per_s": b.total_hr / (t_b / 1e3),
             "plain_hr_updates_per_s": b.total_hr / (t_p / 1e3), "bit_identical": bool(same),
             "tiles": info["tiles"], "grid_blocks": info["grid_blocks"],
-            "graphs_captured": info["graphs_captured"], "kappa_autotuned": kappa, "kappa_used": kappa_used}
+            "graphs_captured": info["graphs_captured"], "kappa_autotuned": kappa, "kappa_used": kappa_used,
+            "long_run_ms_per_step": aging}
 
 
 def multirate_leg(args, torch, Upsampler, steps=60, warmup=10, dt_lr=0.005):

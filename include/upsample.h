@@ -520,6 +520,19 @@ int upsample_batch_init(const upsample_scene* scenes, int32_t n_scenes, uint32_t
 int upsample_batch_step(upsample_batch b, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
                         const float* hr_x, const float* hr_v, float* hr_x_out, float* hr_v_out,
                         void* stream);
+/* HR reorder of every scene of the batch (the upsample_sort_hr of Section 4's
+ * grid, per scene): each scene's HR columns [hr_offset, hr_offset + n_hr) of
+ * hr_x, hr_v (device float32 [3][total_hr]) are permuted in place into the
+ * order of the single-scene handle's default key (Hilbert order of the grid
+ * cells split in two per axis), so that each scene's new order is the one
+ * upsample_sort_hr gives its columns alone.  perm (device int32 [total_hr], or
+ * NULL) receives for each new column the column it came from.  Long batched
+ * runs call it every few steps to keep each wave's particles close together.
+ * The first call allocates the sort scratch (about 48 B per HR particle of the
+ * largest scene plus 8 B per key bin) and synchronises; later calls only
+ * enqueue.  Errors: INVALID_ARG, GRID_TOO_LARGE (a scene's grid is too fine
+ * for the key bins), OOM/HIP (last_error says which). */
+int upsample_batch_sort_hr(upsample_batch b, float* hr_x, float* hr_v, int32_t* perm, void* stream);
 int upsample_batch_destroy(upsample_batch b);  /* waits for the device; NULL is a no-op */
 const char* upsample_batch_last_error(upsample_batch b);
 /* out[0] total_lr, out[1] total_hr, out[2] HR tiles, out[3] blocks of the

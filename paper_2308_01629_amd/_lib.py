@@ -138,6 +138,7 @@ SIGNATURES = {
     "upsample_pbd_last_error": (ctypes.c_char_p, [_P]),
     "upsample_batch_init": (_INT, [ctypes.POINTER(SceneDesc), _I32, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "upsample_batch_step": (_INT, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "upsample_batch_sort_hr": (_INT, [_P, _P, _P, _P, _P]),
     "upsample_batch_destroy": (_INT, [_P]),
     "upsample_batch_last_error": (ctypes.c_char_p, [_P]),
     "upsample_batch_info": (_INT, [_P, ctypes.POINTER(_I64)]),

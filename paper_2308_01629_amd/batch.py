@@ -95,6 +95,15 @@ class Batch:
                                                 _ptr(hr_v), _ptr(ox), _ptr(ov), _stream()))
         return ox, ov
 
+    def sort_hr(self, hr_x, hr_v, with_perm: bool = True):
+        """Reorders every scene's HR columns in place (upsample_batch_sort_hr);
+        returns the old column of each new column (int32 [total_hr]) or None."""
+        if _soa(hr_x, "hr_x").shape[1] != self.total_hr or _soa(hr_v, "hr_v").shape[1] != self.total_hr:
+            raise ValueError(f"HR arrays must be [3, {self.total_hr}]")
+        perm = torch.empty(self.total_hr, dtype=torch.int32, device=hr_x.device) if with_perm else None
+        self._check(self._L.upsample_batch_sort_hr(self._b, _ptr(hr_x), _ptr(hr_v), _ptr(perm), _stream()))
+        return perm
+
     def info(self) -> dict:
         out = (ctypes.c_int64 * 5)()
         self._check(self._L.upsample_batch_info(self._b, out))

@@ -55,6 +55,12 @@ struct upsample_batch_s {
   int n_graphs;
   uint64_t clock;
   int64_t captured;
+  // HR reorder (upsample_batch_sort_hr): per-scene grid constants and sort
+  // key, and the sort scratch, allocated at the first reorder
+  std::vector<BatchScene> host_scenes;
+  std::vector<int> sort_sub, sort_mode;
+  HRSortScratch hsort;
+  bool hsort_ready;
   std::string last_error;
 };
 
@@ -82,7 +88,8 @@ void release(upsample_batch b) {
   b->n_graphs = 0;
   void* ptrs[] = {b->d_scenes, b->d_lr_blocks, b->d_tiles, b->d_walls, b->d_scene_of, b->g.keys, b->g.slot,
                   b->g.tmp, b->g.perm, b->g.counts, b->g.local, b->g.chunk_sum,
-                  b->g.cell_start, b->g.lr_sorted};
+                  b->g.cell_start, b->g.lr_sorted, b->hsort.keys, b->hsort.slot, b->hsort.src, b->hsort.x,
+                  b->hsort.v, b->hsort.perm, b->hsort.counts, b->hsort.local, b->hsort.chunk_sum};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
   if (b->cap != nullptr) (void)hipStreamDestroy(b->cap);
@@ -206,6 +213,21 @@ int upsample_batch_init(const upsample_scene* scenes, int32_t n_scenes, uint32_t
   b->n_cells = n_cells;
   b->n_lr_blocks = (int64_t)lr_blocks.size();
   b->n_tiles = (int64_t)tiles_by_scene.size();
+  b->host_scenes = hs;
+  // the HR reorder key of each scene: the single-scene handle's default
+  // (Hilbert keys over cells split in 2 per axis when their bins fit)
+  b->sort_sub.assign((size_t)n_scenes, 0);
+  b->sort_mode.assign((size_t)n_scenes, 0);
+  for (int32_t s = 0; s < n_scenes; ++s) {
+    const int* dims = hs[(size_t)s].gc.dims;
+    auto bins_for = [&](int sub) { return std::max(sort_bins(dims, sub, 0), sort_bins(dims, sub, 1)); };
+    int max_sub = 4;
+    while (max_sub > 1 && bins_for(max_sub) > ((int64_t)1 << 24)) max_sub /= 2;
+    if (bins_for(max_sub) > ((int64_t)1 << 24)) continue;  // sub 0: this scene cannot be reordered
+    const int sub = max_sub >= 2 ? 2 : 1;
+    b->sort_sub[(size_t)s] = sub;
+    b->sort_mode[(size_t)s] = sort_bins(dims, sub, 2) <= ((int64_t)1 << 24) ? 2 : 0;
+  }
   if (hipGetDevice(&b->device) != hipSuccess) {
     delete b;
     return UPSAMPLE_ERR_NO_DEVICE;
@@ -360,6 +382,57 @@ int upsample_batch_step(upsample_batch b, const float* lr_x, const float* lr_v, 
   if (e != hipSuccess) {
     b->counts_dirty = true;
     return bhip(b, e, "graph launch");
+  }
+  return UPSAMPLE_OK;
+}
+
+int upsample_batch_sort_hr(upsample_batch b, float* hr_x, float* hr_v, int32_t* perm, void* stream) {
+  if (b == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (b->total_hr == 0) return UPSAMPLE_OK;
+  if (hr_x == nullptr || hr_v == nullptr) return bfail(b, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
+  if (b->total_hr >= ((int64_t)1 << 31)) return bfail(b, UPSAMPLE_ERR_INVALID_ARG, "total_hr >= 2^31");
+  for (int32_t s = 0; s < b->n_scenes; ++s)
+    if (b->host_scenes[(size_t)s].n_hr > 0 && b->sort_sub[(size_t)s] == 0)
+      return bfail(b, UPSAMPLE_ERR_GRID_TOO_LARGE, "scene " + std::to_string(s) + ": grid too fine to reorder");
+  hipStream_t st = (hipStream_t)stream;
+  if (!b->hsort_ready) {
+    int64_t max_n = 0, bins = 1;
+    for (int32_t s = 0; s < b->n_scenes; ++s) {
+      const BatchScene& d = b->host_scenes[(size_t)s];
+      if (d.n_hr == 0) continue;
+      max_n = std::max<int64_t>(max_n, d.n_hr);
+      bins = std::max(bins, sort_bins(d.gc.dims, b->sort_sub[(size_t)s], b->sort_mode[(size_t)s]));
+    }
+    HRSortScratch& h = b->hsort;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) {
+      if (e == hipSuccess) e = r;
+    };
+    chk(dalloc(&h.keys, max_n));
+    chk(dalloc(&h.slot, max_n));
+    chk(dalloc(&h.src, max_n));
+    chk(dalloc(&h.x, 3 * max_n));
+    chk(dalloc(&h.v, 3 * max_n));
+    chk(dalloc(&h.perm, max_n));
+    chk(dalloc(&h.counts, bins));
+    chk(dalloc(&h.local, bins));
+    chk(dalloc(&h.chunk_sum, bins / kScanChunk + 2));
+    if (e != hipSuccess) return bhip(b, e, "batch_sort_hr allocation");
+    h.n_bins = bins;
+    h.max_sub = 2;
+    // the sort leaves its counts at zero behind it; they start at zero here
+    chk(hipMemset(h.counts, 0, sizeof(uint32_t) * (size_t)bins));
+    if (e != hipSuccess) return bhip(b, e, "batch_sort_hr");
+    b->hsort_ready = true;
+  }
+  for (int32_t s = 0; s < b->n_scenes; ++s) {
+    const BatchScene& d = b->host_scenes[(size_t)s];
+    if (d.n_hr == 0) continue;
+    const int64_t off = d.hr_off;
+    hipError_t e = launch_sort_hr(d.gc, hr_x + off, hr_v + off, hr_x + off, hr_v + off, d.n_hr,
+                                  b->sort_sub[(size_t)s], b->sort_mode[(size_t)s], b->hsort,
+                                  perm != nullptr ? perm + off : nullptr, st, b->total_hr, (int32_t)off);
+    if (e != hipSuccess) return bhip(b, e, "batch_sort_hr");
   }
   return UPSAMPLE_OK;
 }

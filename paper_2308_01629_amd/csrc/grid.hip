@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_hr_scatter(const uint32_t* __restric
                                                        const uint32_t* __restrict__ local,
                                                        const uint32_t* __restrict__ chunk_sum,
                                                        const float* __restrict__ x,
-                                                       const float* __restrict__ v,
+                                                       const float* __restrict__ v, int64_t ld,
                                                        float* __restrict__ xs, float* __restrict__ vs,
                                                        int32_t* __restrict__ perm) {
   __shared__ float stage[6][kHrSpan];
@@ -281,8 +281,8 @@ __global__ __launch_bounds__(kBlock) void k_hr_scatter(const uint32_t* __restric
     if (i < n) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        stage[a][l] = x[a * n + i];
-        stage[3 + a][l] = v[a * n + i];
+        stage[a][l] = x[a * ld + i];
+        stage[3 + a][l] = v[a * ld + i];
       }
     }
   }
@@ -308,16 +308,16 @@ __global__ __launch_bounds__(kBlock) void k_hr_scatter(const uint32_t* __restric
 __global__ __launch_bounds__(kBlock) void k_copy_back(const float* __restrict__ xs,
                                                       const float* __restrict__ vs,
                                                       const int32_t* __restrict__ perm, int64_t n,
-                                                      float* __restrict__ x, float* __restrict__ v,
-                                                      int32_t* __restrict__ perm_out) {
+                                                      float* __restrict__ x, float* __restrict__ v, int64_t ld,
+                                                      int32_t* __restrict__ perm_out, int32_t perm_base) {
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    x[a * n + i] = xs[a * n + i];
-    v[a * n + i] = vs[a * n + i];
+    x[a * ld + i] = xs[a * n + i];
+    v[a * ld + i] = vs[a * n + i];
   }
-  if (perm_out != nullptr) perm_out[i] = perm[i];
+  if (perm_out != nullptr) perm_out[i] = perm[i] + perm_base;
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_finite(const float* __restrict__ p, int64_t n,
@@ -414,7 +414,8 @@ static_assert(kHrTable % kBlock == 0, "HR key table entries per thread");
 constexpr uint32_t kNoKey = 0xffffffffu;
 
 __global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const float* __restrict__ x,
-                                                          int64_t n, int sub, int mode, int bx, int by, int bz,
+                                                          int64_t n, int64_t ld, int sub, int mode, int bx, int by,
+                                                          int bz,
                                                           uint32_t* __restrict__ keys,
                                                           uint32_t* __restrict__ slot,
                                                           uint32_t* __restrict__ src,
@@ -438,8 +439,8 @@ __global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const fl
     const bool valid = i < n;
     const int64_t ii = valid ? i : 0;
     const uint32_t fx = fine_coord(x[ii], gc.lo[0], gc.inv_cs, gc.dims[0], sub);
-    const uint32_t fy = fine_coord(x[n + ii], gc.lo[1], gc.inv_cs, gc.dims[1], sub);
-    const uint32_t fz = fine_coord(x[2 * n + ii], gc.lo[2], gc.inv_cs, gc.dims[2], sub);
+    const uint32_t fy = fine_coord(x[ld + ii], gc.lo[1], gc.inv_cs, gc.dims[1], sub);
+    const uint32_t fz = fine_coord(x[2 * ld + ii], gc.lo[2], gc.inv_cs, gc.dims[2], sub);
     uint32_t k;
     if (mode == 2) {
       k = hilbert3(fx, fy, fz, max(bx, max(by, bz)));
@@ -675,13 +676,16 @@ hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& 
 
 hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
                           float* out_v, int64_t n_hr, int sub, int mode, const HRSortScratch& s,
-                          int32_t* perm_out, hipStream_t st) {
+                          int32_t* perm_out, hipStream_t st, int64_t ld, int32_t perm_base) {
   if (n_hr == 0) return hipSuccess;
+  if (ld < 0) ld = n_hr;
+  // a strided state is sorted in place only (through the scratch copy)
+  if (ld != n_hr && (out_x != hr_x || out_v != hr_v)) return hipErrorInvalidValue;
   int bits[3];
   for (int a = 0; a < 3; ++a) bits[a] = sort_bits((int64_t)gc.dims[a] * sub);
   const int64_t n_bins = sort_bins(gc.dims, sub, mode);
   hipLaunchKernelGGL(k_hr_keys_count, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)),
-                     dim3(kBlock), 0, st, gc, hr_x, n_hr,
+                     dim3(kBlock), 0, st, gc, hr_x, n_hr, ld,
                      sub, mode, bits[0], bits[1], bits[2], s.keys, s.slot, s.src, s.counts);
   hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
   if (e != hipSuccess) return e;
@@ -690,11 +694,11 @@ hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* h
   int32_t* perm = perm_out == nullptr ? nullptr : (in_place ? s.perm : perm_out);
   hipLaunchKernelGGL(k_hr_scatter, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)), dim3(kBlock), 0, st,
                      s.keys, s.slot, s.src, n_hr,
-                     s.local, s.chunk_sum, hr_x, hr_v, in_place ? s.x : out_x, in_place ? s.v : out_v,
+                     s.local, s.chunk_sum, hr_x, hr_v, ld, in_place ? s.x : out_x, in_place ? s.v : out_v,
                      perm);
   if (in_place) {
     hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.x, s.v, s.perm,
-                       n_hr, out_x, out_v, perm_out);
+                       n_hr, out_x, out_v, ld, perm_out, perm_base);
   }
   return hipGetLastError();
 }

@@ -141,6 +141,7 @@ def test_batch_table_validated_before_device():
         assert init(ok) == _lib.ERR_CODES["UPSAMPLE_ERR_NO_DEVICE"]
     assert L.upsample_batch_step(None, None, None, None, None, None, None, None, None) == inv
     assert L.upsample_batch_info(None, None) == inv
+    assert L.upsample_batch_sort_hr(None, None, None, None, None) == inv
     assert L.upsample_batch_destroy(None) == 0
     assert L.upsample_batch_last_error(None).decode() == "null batch"
 

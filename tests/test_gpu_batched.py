@@ -1,8 +1,9 @@
 """GPU tests of the batched step (upsample_batch_*): per scene, bit-identical
 to upsample_step on a handle with the same parameters -- through the HIP
 graph (replayed several times, with eager work between replays) and eagerly --
-plus rigid scenes, empty scenes, graph re-capture for new buffers, and a
-sampled check of one scene against the oracle."""
+plus rigid scenes, empty scenes, graph re-capture for new buffers, the
+batched HR reorder against the per-scene one, and a sampled check of one
+scene against the oracle."""
 import numpy as np
 import pytest
 
@@ -127,3 +128,55 @@ def test_batched_empty_scenes_and_recapture(mods):
     # no LR particles: free fall, v' = v + dt g, x' = x + dt v'
     v_ff = hv0[1] + np.float32(base.dt) * np.asarray(base.g, np.float32)[:, None]
     np.testing.assert_allclose(host(b.split_hr(res[0][1])[1]), v_ff, rtol=1e-6, atol=1e-6)
+
+
+def test_batched_reorder_equals_plain_reorder(mods):
+    """upsample_batch_sort_hr sorts each scene's columns by the key
+    upsample_sort_hr uses for that scene alone: the sequence of keys is the
+    same and the permutation is one (particles of one fine cell may come in
+    another order: the counting sort places them by arrival, a valid order of
+    equal keys).  With the batch's permutation applied to the per-scene state,
+    the batched steps that follow stay bit-identical to the per-scene steps."""
+    from oracle import upsample_oracle as O
+    from gpu_util import morton_sort_keys
+    Batch, Upsampler = mods
+    scenes = _scenes()
+    b = Batch.from_scenes(scenes)
+    plain = [Upsampler.from_scene(s) for s in scenes]
+    hx0, hv0 = _hr_state(scenes, 3)
+    px = [dev(a, torch) for a in hx0]
+    pv = [dev(a, torch) for a in hv0]
+    bx, bv = dev(b.pack_hr(hx0), torch), dev(b.pack_hr(hv0), torch)
+    lx = torch.empty((3, b.total_lr), device="cuda")
+    lv = torch.empty_like(lx)
+    for t in range(1, 7):
+        frames = [s.lr_frame(t) for s in scenes]
+        lx.copy_(dev(b.pack_lr([f[0] for f in frames]), torch))
+        lv.copy_(dev(b.pack_lr([f[1] for f in frames]), torch))
+        b.step(lx, lv, bx, bv, out_x=bx, out_v=bv)
+        for s, up in enumerate(plain):
+            px[s], pv[s] = up.step(dev(frames[s][0], torch), dev(frames[s][1], torch), None, px[s], pv[s])
+        if t % 3 == 0:
+            torch.cuda.synchronize()
+            before = [host(x).copy() for x in px]
+            perm = b.sort_hr(bx, bv)
+            torch.cuda.synchronize()
+            for s, (off, n) in enumerate(zip(b.hr_offsets, b.n_hr)):
+                p = (perm[off:off + n] - off).long()
+                assert torch.equal(torch.sort(p)[0], torch.arange(n, device="cuda")), (t, s, "not a permutation")
+                # the single-scene reorder of the same columns: the same key sequence
+                up = plain[s]
+                cx, cv = px[s].clone(), pv[s].clone()
+                q = up.sort_hr(cx, cv).long()
+                spec = O.grid_spec(scenes[s].r_lr, scenes[s].domain_lo, scenes[s].domain_hi)
+                tun = up.get_tuning()
+                k_batch = morton_sort_keys(before[s][:, host(p)], spec, tun["sort_sub"], tun["sort_mode"])
+                k_plain = morton_sort_keys(before[s][:, host(q)], spec, tun["sort_sub"], tun["sort_mode"])
+                assert np.array_equal(k_batch, k_plain) and np.all(np.diff(k_batch) >= 0), (t, s, "keys")
+                # follow the batch's order in the per-scene state
+                px[s], pv[s] = px[s][:, p].contiguous(), pv[s][:, p].contiguous()
+        torch.cuda.synchronize()
+        for s, (gx, gv) in enumerate(zip(b.split_hr(bx), b.split_hr(bv))):
+            assert torch.equal(gx, px[s]) and torch.equal(gv, pv[s]), (t, s, scenes[s].name)
+    log(f"batched reorder: {len(scenes)} scenes, two reorders: per-scene key order, steps bit-identical")
+    b.close()
