@@ -306,3 +306,39 @@ def test_overflow_flag_and_edges(LRSim):
     np.testing.assert_allclose(host(v1)[:, 0], [0.1, 5 * dt * g, -0.2], atol=2 * 5 * ulp / dt)
     one.close()
     sim.close()
+
+
+def test_shape_matching_fallback_bodies(LRSim):
+    """Bodies whose shape-matching matrix is not proper and well conditioned
+    take the eigenvector path instead of the Newton iteration: a flat plate
+    (one layer of particles: C has rank 2) and a body whose particles sit at
+    the mirror image of its rest shape (det C < 0, where the rotation is the
+    one with the smallest singular direction flipped).  Both, free of
+    contacts, are checked stage by stage against the oracle (centres,
+    rotations and positions of every solver iteration)."""
+    r = 0.01
+    sp = 2 * r
+    g = (np.arange(5) - 2.0) * sp
+    plate = np.stack(np.meshgrid(g, g, indexing="ij")).reshape(2, -1)
+    plate = np.stack([plate[0], np.zeros(plate.shape[1]), plate[1]])          # y = 0 plane
+    cube = np.stack(np.meshgrid(g[:4], g[:4], g[:3], indexing="ij")).reshape(3, -1)
+    cube = cube - cube.mean(axis=1, keepdims=True)
+    th = 0.4
+    R = np.array([[np.cos(th), -np.sin(th), 0.0], [np.sin(th), np.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    mirror = np.diag([-1.0, 1.0, 1.0])
+    x_plate = R @ plate + np.array([[0.3], [0.5], [0.3]])
+    x_cube = mirror @ (R @ cube) + np.array([[0.7], [0.5], [0.7]])
+    x = np.concatenate([x_plate, x_cube], axis=1)
+    rest = np.concatenate([plate - plate.mean(axis=1, keepdims=True), cube], axis=1)
+    body = np.concatenate([np.zeros(plate.shape[1], np.int32), np.ones(cube.shape[1], np.int32)])
+    v = np.zeros_like(x)
+    sc = S.LRScene("fallback", r, 0.005, (0.0, -9.81, 0.0), np.zeros(3, F32), np.ones(3, F32), 0.0,
+                   np.ascontiguousarray(x, F32), np.ascontiguousarray(v, F32), body, np.ones(body.size, F32),
+                   np.ascontiguousarray(rest, F32))
+    check_debug_step(LRSim, sc, 0)
+    # the mirrored body's rotation is proper: the oracle and the GPU agree on it
+    prm = _prm(sc)
+    _, xt, w = P.predict(_f64(sc.x), _f64(sc.v), body, sc.inv_m, prm)
+    _, frames = P.shape_matching(xt, body, _f64(sc.rest), return_frames=True)
+    for b, (c, Rb) in frames.items():
+        assert abs(np.linalg.det(Rb) - 1.0) < 1e-9, b

@@ -70,3 +70,49 @@ def test_impact_scene_upsampled_from_gpu_frames(libs):
     assert not sim.overflow()
     sim.close()
     up.close()
+
+
+def test_column_collapse_full_size_sampled(libs):
+    """The configuration the bench's pipeline leg times: the column collapse
+    (23,609 LR) by the LR step, about 370k HR volume-sampled in the column
+    (r_HR = 0.3 r_LR), HR steps of 1/60 s with a reorder; each step against
+    the oracle on 4,096 sampled HR particles from the GPU's own state."""
+    from workloads.generators import volume_candidates
+    LRSim, Upsampler, sample_volume = libs
+    sc = S.column_collapse()
+    r_hr = 0.3 * sc.r
+    top = float(sc.x[1, sc.body == S.GRANULAR].max()) + sc.r
+    cand, lo, hi = volume_candidates("column", 8_000_000, [47, 2], top=top)
+    hx = sample_volume(dev(cand, torch), r_hr, lo, hi)
+    del cand
+    hv = torch.zeros_like(hx)
+    n_hr = hx.shape[1]
+    T = 4
+    n_lr = int(np.ceil(T * DT_HR / DT_LR)) + 1
+    sim = LRSim(sc.body, sc.inv_m, sc.rest, sc.r, sc.domain_lo, sc.domain_hi, dt=DT_LR, g=sc.g)
+    x, v = dev(sc.x, torch), dev(sc.v, torch)
+    fx, fv = sim.step(x, v, n_lr, frames=True)
+    LX = torch.cat([dev(sc.x, torch)[None], fx]).contiguous()
+    LV = torch.cat([dev(sc.v, torch)[None], fv]).contiguous()
+    frames = [(host(LX[k]), host(LV[k])) for k in range(n_lr + 1)]
+    walls = np.stack(box_walls(np.zeros(3), np.array([2.0, 1.5, 2.0]))).astype(np.float32)
+    up = Upsampler(sc.r, r_hr, DT_HR, sc.g, sc.domain_lo, sc.domain_hi, walls=walls, max_lr=sc.n, max_hr=n_hr)
+    up.sort_hr(hx, hv, with_perm=False)
+    rigid_d = dev(sc.lr_rigid, torch)
+    prm = dict(r_lr=float(np.float32(sc.r)), r_hr=float(np.float32(r_hr)), dt=float(np.float32(DT_HR)),
+               g=np.asarray(sc.g, np.float32), c1=512.0 / 729.0, c2=0.6, domain_lo=sc.domain_lo,
+               domain_hi=sc.domain_hi, walls=walls)
+    rigid = sc.lr_rigid.astype(bool)
+    box = float(np.max(sc.domain_hi - sc.domain_lo))
+    idx = np.sort(np.random.default_rng(9).choice(n_hr, 4096, replace=False))
+    for n in range(T):
+        x0, v0 = host(hx).copy(), host(hv).copy()
+        up.run_multirate(LX, LV, hx, hv, n_steps=1, dt_lr=DT_LR, t_hr0=n * DT_HR, lr_rigid=rigid_d)
+        torch.cuda.synchronize()
+        (k, th), = MR.hr_schedule(n * DT_HR, DT_HR, 1, 0.0, DT_LR, len(frames))
+        X, V = MR.lerp_frame_f32(*frames[k], *frames[k + 1], th)
+        s = compare_step(host(hx), host(hv), X, V, rigid, x0, v0, prm, box, idx=idx)
+        log(f"pipeline column step {n}: frames {k}, {k + 1}, theta {th:.4f}, {n_hr} HR (4,096 sampled): {s}")
+    assert not sim.overflow()
+    sim.close()
+    up.close()
