@@ -528,9 +528,12 @@ int upsample_batch_step(upsample_batch b, const float* lr_x, const float* lr_v, 
  * upsample_sort_hr gives its columns alone.  perm (device int32 [total_hr], or
  * NULL) receives for each new column the column it came from.  Long batched
  * runs call it every few steps to keep each wave's particles close together.
- * The first call allocates the sort scratch (about 48 B per HR particle of the
- * largest scene plus 8 B per key bin) and synchronises; later calls only
- * enqueue.  Errors: INVALID_ARG, GRID_TOO_LARGE (a scene's grid is too fine
+ * Scenes that own consecutive column ranges in scene order are sorted by one
+ * counting sort over all of them (bins: the scenes' fine cells, ranked along
+ * the Hilbert curve); other layouts by one sort per scene.  The first call
+ * allocates the sort scratch (about 40 B per HR column plus 12 B per fine
+ * cell of all scenes), builds the rank tables and synchronises; later calls
+ * only enqueue.  Errors: INVALID_ARG, GRID_TOO_LARGE (a scene's grid is too fine
  * for the key bins), OOM/HIP (last_error says which). */
 int upsample_batch_sort_hr(upsample_batch b, float* hr_x, float* hr_v, int32_t* perm, void* stream);
 int upsample_batch_destroy(upsample_batch b);  /* waits for the device; NULL is a no-op */

@@ -22,16 +22,21 @@ class Batch:
     """A fixed set of scenes stepped together in one graph-captured launch
     sequence (``eager=True``: direct launches)."""
 
-    def __init__(self, params: Sequence[dict], n_lr: Sequence[int], n_hr: Sequence[int], eager: bool = False):
+    def __init__(self, params: Sequence[dict], n_lr: Sequence[int], n_hr: Sequence[int], eager: bool = False,
+                 hr_offsets: Optional[Sequence[int]] = None):
+        """``hr_offsets``: first HR column of each scene (default: the scenes
+        one after another, in order)."""
         if not (len(params) == len(n_lr) == len(n_hr)) or not params:
             raise ValueError("params, n_lr and n_hr must have the same non-zero length")
         self._L = lib()
         self.n_lr = [int(v) for v in n_lr]
         self.n_hr = [int(v) for v in n_hr]
         self.lr_offsets = [int(v) for v in np.concatenate([[0], np.cumsum(self.n_lr)[:-1]])]
-        self.hr_offsets = [int(v) for v in np.concatenate([[0], np.cumsum(self.n_hr)[:-1]])]
+        if hr_offsets is None:
+            hr_offsets = np.concatenate([[0], np.cumsum(self.n_hr)[:-1]])
+        self.hr_offsets = [int(v) for v in hr_offsets]
         self.total_lr = int(sum(self.n_lr))
-        self.total_hr = int(sum(self.n_hr))
+        self.total_hr = int(max(o + n for o, n in zip(self.hr_offsets, self.n_hr)))
         descs = (SceneDesc * len(params))()
         keep = []
         for s, kw in enumerate(params):
@@ -46,13 +51,14 @@ class Batch:
         del keep
 
     @classmethod
-    def from_scenes(cls, scenes, cell_factor=0.0, eager: bool = False) -> "Batch":
+    def from_scenes(cls, scenes, cell_factor=0.0, eager: bool = False, hr_offsets=None) -> "Batch":
         """``cell_factor``: one kappa for every scene or one per scene."""
         kap = list(cell_factor) if np.ndim(cell_factor) else [float(cell_factor)] * len(scenes)
         params = [dict(r_lr=sc.r_lr, r_hr=sc.r_hr, dt=sc.dt, g=tuple(sc.g), domain_lo=tuple(sc.domain_lo),
                        domain_hi=tuple(sc.domain_hi), walls=sc.walls, c1=sc.c1, c2=sc.c2,
                        cell_factor=k) for sc, k in zip(scenes, kap)]
-        return cls(params, [sc.n_lr for sc in scenes], [sc.n_hr for sc in scenes], eager=eager)
+        return cls(params, [sc.n_lr for sc in scenes], [sc.n_hr for sc in scenes], eager=eager,
+                   hr_offsets=hr_offsets)
 
     def _check(self, rc: int) -> None:
         check(rc, self._b, self._L.upsample_batch_last_error)
@@ -74,7 +80,11 @@ class Batch:
         return np.ascontiguousarray(np.concatenate([np.asarray(a, np.float32) for a in arrays], axis=1))
 
     def pack_hr(self, arrays: Sequence[np.ndarray]) -> np.ndarray:
-        return np.ascontiguousarray(np.concatenate([np.asarray(a, np.float32) for a in arrays], axis=1))
+        """Per-scene [3, n_hr[s]] arrays placed at their columns (gaps zero)."""
+        out = np.zeros((3, self.total_hr), np.float32)
+        for a, o, n in zip(arrays, self.hr_offsets, self.n_hr):
+            out[:, o:o + n] = np.asarray(a, np.float32)
+        return out
 
     def split_hr(self, t) -> List:
         """Per-scene column views of a [3, total_hr] array or tensor."""

@@ -61,6 +61,11 @@ struct upsample_batch_s {
   std::vector<int> sort_sub, sort_mode;
   HRSortScratch hsort;
   bool hsort_ready;
+  bool sort_one_pass;        // one counting sort over all scenes (see upsample_batch_sort_hr)
+  int64_t* d_sort_start;     // [n_scenes + 1] first column of each scene
+  HrRankScene* d_rank_scenes;
+  uint32_t* d_rank;          // Hilbert rank of each fine cell, per scene
+  int64_t rank_bins;
   std::string last_error;
 };
 
@@ -89,7 +94,8 @@ void release(upsample_batch b) {
   void* ptrs[] = {b->d_scenes, b->d_lr_blocks, b->d_tiles, b->d_walls, b->d_scene_of, b->g.keys, b->g.slot,
                   b->g.tmp, b->g.perm, b->g.counts, b->g.local, b->g.chunk_sum,
                   b->g.cell_start, b->g.lr_sorted, b->hsort.keys, b->hsort.slot, b->hsort.src, b->hsort.x,
-                  b->hsort.v, b->hsort.perm, b->hsort.counts, b->hsort.local, b->hsort.chunk_sum};
+                  b->hsort.v, b->hsort.perm, b->hsort.counts, b->hsort.local, b->hsort.chunk_sum,
+                  b->d_sort_start, b->d_rank_scenes, b->d_rank};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
   if (b->cap != nullptr) (void)hipStreamDestroy(b->cap);
@@ -386,6 +392,80 @@ int upsample_batch_step(upsample_batch b, const float* lr_x, const float* lr_v, 
   return UPSAMPLE_OK;
 }
 
+namespace {
+
+// First call of upsample_batch_sort_hr: the sort scratch, and when the scenes
+// own consecutive column ranges in scene order and all take Hilbert keys, the
+// per-scene Hilbert rank tables of the one-pass sort.
+hipError_t prepare_sort(upsample_batch b, hipStream_t st) {
+  const int32_t S = b->n_scenes;
+  bool one = true;
+  int64_t pos = 0, rank_bins = 0, max_cube = 1, max_n = 0, max_bins = 1;
+  std::vector<int64_t> start((size_t)S + 1, 0);
+  std::vector<HrRankScene> rs((size_t)S);
+  for (int32_t s = 0; s < S; ++s) {
+    const BatchScene& d = b->host_scenes[(size_t)s];
+    max_n = std::max<int64_t>(max_n, d.n_hr);
+    if (d.n_hr > 0)
+      max_bins = std::max(max_bins, sort_bins(d.gc.dims, b->sort_sub[(size_t)s], b->sort_mode[(size_t)s]));
+    one = one && d.hr_off == pos && b->sort_mode[(size_t)s] == 2;
+    pos += d.n_hr;
+    start[(size_t)s + 1] = pos;
+    HrRankScene& r = rs[(size_t)s];
+    r.gc = d.gc;
+    r.sub = b->sort_sub[(size_t)s];
+    int bits = 0;
+    for (int a = 0; a < 3; ++a) {
+      r.fdims[a] = d.gc.dims[a] * r.sub;
+      bits = std::max(bits, sort_bits(r.fdims[a]));
+    }
+    r.base = (uint32_t)rank_bins;
+    rank_bins += (int64_t)r.fdims[0] * r.fdims[1] * r.fdims[2];
+    max_cube = std::max<int64_t>(max_cube, (int64_t)1 << (3 * bits));
+    if (rank_bins >= ((int64_t)1 << 31)) one = false;
+  }
+  one = one && pos == b->total_hr;
+  b->sort_one_pass = one;
+  const int64_t n_sort = one ? b->total_hr : max_n;
+  const int64_t bins = one ? std::max(rank_bins, max_cube) : max_bins;
+  HRSortScratch& h = b->hsort;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  chk(dalloc(&h.keys, n_sort));
+  chk(dalloc(&h.slot, n_sort));
+  chk(dalloc(&h.src, n_sort));
+  chk(dalloc(&h.x, 3 * n_sort));
+  chk(dalloc(&h.v, 3 * n_sort));
+  chk(dalloc(&h.perm, n_sort));
+  chk(dalloc(&h.counts, bins));
+  chk(dalloc(&h.local, bins));
+  chk(dalloc(&h.chunk_sum, bins / kScanChunk + 2));
+  if (one) {
+    chk(dalloc(&b->d_sort_start, (int64_t)S + 1));
+    chk(dalloc(&b->d_rank_scenes, S));
+    chk(dalloc(&b->d_rank, rank_bins));
+  }
+  if (e != hipSuccess) return e;
+  h.n_bins = bins;
+  h.max_sub = 2;
+  b->rank_bins = rank_bins;
+  // the sort leaves its counts at zero behind it; they start at zero here
+  chk(hipMemset(h.counts, 0, sizeof(uint32_t) * (size_t)bins));
+  if (one) {
+    chk(hipMemcpy(b->d_sort_start, start.data(), sizeof(int64_t) * start.size(), hipMemcpyHostToDevice));
+    chk(hipMemcpy(b->d_rank_scenes, rs.data(), sizeof(HrRankScene) * rs.size(), hipMemcpyHostToDevice));
+    for (int32_t s = 0; s < S && e == hipSuccess; ++s)
+      chk(launch_hilbert_ranks(rs[(size_t)s].fdims, b->d_rank + rs[(size_t)s].base, h.counts, h.local, h.chunk_sum,
+                               st));
+    chk(hipStreamSynchronize(st));
+  }
+  return e;
+}
+
+}  // namespace
+
 int upsample_batch_sort_hr(upsample_batch b, float* hr_x, float* hr_v, int32_t* perm, void* stream) {
   if (b == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
   if (b->total_hr == 0) return UPSAMPLE_OK;
@@ -396,34 +476,17 @@ int upsample_batch_sort_hr(upsample_batch b, float* hr_x, float* hr_v, int32_t* 
       return bfail(b, UPSAMPLE_ERR_GRID_TOO_LARGE, "scene " + std::to_string(s) + ": grid too fine to reorder");
   hipStream_t st = (hipStream_t)stream;
   if (!b->hsort_ready) {
-    int64_t max_n = 0, bins = 1;
-    for (int32_t s = 0; s < b->n_scenes; ++s) {
-      const BatchScene& d = b->host_scenes[(size_t)s];
-      if (d.n_hr == 0) continue;
-      max_n = std::max<int64_t>(max_n, d.n_hr);
-      bins = std::max(bins, sort_bins(d.gc.dims, b->sort_sub[(size_t)s], b->sort_mode[(size_t)s]));
-    }
-    HRSortScratch& h = b->hsort;
-    hipError_t e = hipSuccess;
-    auto chk = [&](hipError_t r) {
-      if (e == hipSuccess) e = r;
-    };
-    chk(dalloc(&h.keys, max_n));
-    chk(dalloc(&h.slot, max_n));
-    chk(dalloc(&h.src, max_n));
-    chk(dalloc(&h.x, 3 * max_n));
-    chk(dalloc(&h.v, 3 * max_n));
-    chk(dalloc(&h.perm, max_n));
-    chk(dalloc(&h.counts, bins));
-    chk(dalloc(&h.local, bins));
-    chk(dalloc(&h.chunk_sum, bins / kScanChunk + 2));
-    if (e != hipSuccess) return bhip(b, e, "batch_sort_hr allocation");
-    h.n_bins = bins;
-    h.max_sub = 2;
-    // the sort leaves its counts at zero behind it; they start at zero here
-    chk(hipMemset(h.counts, 0, sizeof(uint32_t) * (size_t)bins));
-    if (e != hipSuccess) return bhip(b, e, "batch_sort_hr");
+    const hipError_t e = prepare_sort(b, st);
+    if (e != hipSuccess)
+      return e == hipErrorOutOfMemory ? bfail(b, UPSAMPLE_ERR_OOM, "batch_sort_hr: out of device memory")
+                                      : bhip(b, e, "batch_sort_hr set-up");
     b->hsort_ready = true;
+  }
+  if (b->sort_one_pass) {
+    const hipError_t e = launch_sort_hr_batched(hr_x, hr_v, b->total_hr, b->d_sort_start, b->n_scenes,
+                                                b->d_rank_scenes, b->d_rank, b->rank_bins, b->hsort, perm, st);
+    if (e != hipSuccess) return bhip(b, e, "batch_sort_hr");
+    return UPSAMPLE_OK;
   }
   for (int32_t s = 0; s < b->n_scenes; ++s) {
     const BatchScene& d = b->host_scenes[(size_t)s];

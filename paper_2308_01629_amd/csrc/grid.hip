@@ -12,6 +12,8 @@
 //                 writes perm[] and the LR copy in sorted order (32 B / particle)
 //
 // The same key / count / scan machinery reorders HR particles by cell.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace ups {
@@ -351,45 +353,6 @@ __device__ __forceinline__ uint32_t morton3(uint32_t fx, uint32_t fy, uint32_t f
   return key;
 }
 
-// Index of fine cell (x0, x1, x2) along a 3-D Hilbert curve over a cube of
-// 2^b cells per axis, by Skilling's transpose method ("Programming the Hilbert
-// curve", AIP Conf. Proc. 707, 2004): undo the excess work of each level from
-// the top bit down, Gray-encode, then interleave the bits with axis 0 most
-// significant.  Consecutive indices are face-neighbouring cells, so runs of
-// particles in this order fill compact boxes (no Z-order jumps).
-__device__ __forceinline__ uint32_t hilbert3(uint32_t x0, uint32_t x1, uint32_t x2, int b) {
-  for (int k = b - 1; k > 0; --k) {
-    const uint32_t q = 1u << k, p = q - 1u;
-    x0 = (x0 & q) ? (x0 ^ p) : x0;
-    {
-      const uint32_t t = (x0 ^ x1) & p;
-      const bool hit = (x1 & q) != 0u;
-      x0 = hit ? (x0 ^ p) : (x0 ^ t);
-      x1 = hit ? x1 : (x1 ^ t);
-    }
-    {
-      const uint32_t t = (x0 ^ x2) & p;
-      const bool hit = (x2 & q) != 0u;
-      x0 = hit ? (x0 ^ p) : (x0 ^ t);
-      x2 = hit ? x2 : (x2 ^ t);
-    }
-  }
-  x1 ^= x0;
-  x2 ^= x1;
-  uint32_t t = 0u;
-  for (int k = b - 1; k > 0; --k) {
-    const uint32_t q = 1u << k;
-    if (x2 & q) t ^= q - 1u;
-  }
-  x0 ^= t;
-  x1 ^= t;
-  x2 ^= t;
-  uint32_t key = 0u;
-  for (int k = b - 1; k >= 0; --k)
-    key = (key << 3) | (((x0 >> k) & 1u) << 2) | (((x1 >> k) & 1u) << 1) | ((x2 >> k) & 1u);
-  return key;
-}
-
 __device__ __forceinline__ uint32_t morton_sub(uint32_t a, uint32_t b, uint32_t c) {
   return (a & 1u) | ((b & 1u) << 1) | ((c & 1u) << 2) | ((a & 2u) << 2) | ((b & 2u) << 3) | ((c & 2u) << 4);
 }
@@ -413,9 +376,55 @@ static_assert(kHrTable >= 2 * kHrSpan, "HR key table must stay at most half full
 static_assert(kHrTable % kBlock == 0, "HR key table entries per thread");
 constexpr uint32_t kNoKey = 0xffffffffu;
 
-__global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const float* __restrict__ x,
-                                                          int64_t n, int64_t ld, int sub, int mode, int bx, int by,
-                                                          int bz,
+// The reorder key of HR particle i of one scene: mode 2 the Hilbert index of
+// its fine cell, mode 1 the Z-order code, mode 0 the grid cell then the
+// Z-order of its sub-cells.
+struct SceneHrKey {
+  GridConst gc;
+  const float* x;
+  int64_t ld;
+  int sub, mode, bx, by, bz;
+  __device__ __forceinline__ uint32_t operator()(int64_t i) const {
+    const uint32_t fx = fine_coord(x[i], gc.lo[0], gc.inv_cs, gc.dims[0], sub);
+    const uint32_t fy = fine_coord(x[ld + i], gc.lo[1], gc.inv_cs, gc.dims[1], sub);
+    const uint32_t fz = fine_coord(x[2 * ld + i], gc.lo[2], gc.inv_cs, gc.dims[2], sub);
+    if (mode == 2) return hilbert3(fx, fy, fz, max(bx, max(by, bz)));
+    if (mode == 1) return morton3(fx, fy, fz, bx, by, bz);
+    // sub is 1, 2 or 4: divide and take remainders by shifts
+    const uint32_t sh = (uint32_t)(__ffs(sub) - 1), m = (uint32_t)sub - 1u;
+    const uint32_t cell = (fx >> sh) + (uint32_t)gc.dims[0] * ((fy >> sh) + (uint32_t)gc.dims[1] * (fz >> sh));
+    return (cell << (3u * sh)) + morton_sub(fx & m, fy & m, fz & m);
+  }
+};
+
+// The key of column i of a batch whose scenes own consecutive column ranges
+// (start[s] .. start[s + 1]): the scene's first bin plus the Hilbert rank of
+// the particle's fine cell among all fine cells of that scene's grid, so the
+// bins of all scenes together number their fine cells, not padded cubes.
+struct BatchHrKey {
+  const float* x;
+  int64_t ld;
+  const int64_t* start;
+  int n_scenes;
+  const HrRankScene* sc;
+  const uint32_t* rank;
+  __device__ __forceinline__ uint32_t operator()(int64_t i) const {
+    int lo = 0, hi = n_scenes;  // the scene s with start[s] <= i < start[s + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (start[mid] <= i) lo = mid; else hi = mid;
+    }
+    const HrRankScene& d = sc[lo];
+    const uint32_t fx = fine_coord(x[i], d.gc.lo[0], d.gc.inv_cs, d.gc.dims[0], d.sub);
+    const uint32_t fy = fine_coord(x[ld + i], d.gc.lo[1], d.gc.inv_cs, d.gc.dims[1], d.sub);
+    const uint32_t fz = fine_coord(x[2 * ld + i], d.gc.lo[2], d.gc.inv_cs, d.gc.dims[2], d.sub);
+    const uint32_t f = fx + (uint32_t)d.fdims[0] * (fy + (uint32_t)d.fdims[1] * fz);
+    return d.base + rank[d.base + f];
+  }
+};
+
+template <class KeyFn>
+__global__ __launch_bounds__(kBlock) void k_hr_keys_count(KeyFn kf, int64_t n,
                                                           uint32_t* __restrict__ keys,
                                                           uint32_t* __restrict__ slot,
                                                           uint32_t* __restrict__ src,
@@ -438,20 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_hr_keys_count(GridConst gc, const fl
     const int64_t i = block0 + (int64_t)j * kBlock + threadIdx.x;
     const bool valid = i < n;
     const int64_t ii = valid ? i : 0;
-    const uint32_t fx = fine_coord(x[ii], gc.lo[0], gc.inv_cs, gc.dims[0], sub);
-    const uint32_t fy = fine_coord(x[ld + ii], gc.lo[1], gc.inv_cs, gc.dims[1], sub);
-    const uint32_t fz = fine_coord(x[2 * ld + ii], gc.lo[2], gc.inv_cs, gc.dims[2], sub);
-    uint32_t k;
-    if (mode == 2) {
-      k = hilbert3(fx, fy, fz, max(bx, max(by, bz)));
-    } else if (mode == 1) {
-      k = morton3(fx, fy, fz, bx, by, bz);
-    } else {
-      // sub is 1, 2 or 4: divide and take remainders by shifts
-      const uint32_t sh = (uint32_t)(__ffs(sub) - 1), m = (uint32_t)sub - 1u;
-      const uint32_t cell = (fx >> sh) + (uint32_t)gc.dims[0] * ((fy >> sh) + (uint32_t)gc.dims[1] * (fz >> sh));
-      k = (cell << (3u * sh)) + morton_sub(fx & m, fy & m, fz & m);
-    }
+    const uint32_t k = kf(ii);
     const uint32_t kk = valid ? k : kNoKey;
     const uint32_t prev = __shfl_up(kk, 1, 64);
     const bool head = (lane == 0) || (prev != kk);
@@ -684,9 +680,9 @@ hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* h
   int bits[3];
   for (int a = 0; a < 3; ++a) bits[a] = sort_bits((int64_t)gc.dims[a] * sub);
   const int64_t n_bins = sort_bins(gc.dims, sub, mode);
-  hipLaunchKernelGGL(k_hr_keys_count, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)),
-                     dim3(kBlock), 0, st, gc, hr_x, n_hr, ld,
-                     sub, mode, bits[0], bits[1], bits[2], s.keys, s.slot, s.src, s.counts);
+  const SceneHrKey kf{gc, hr_x, ld, sub, mode, bits[0], bits[1], bits[2]};
+  hipLaunchKernelGGL(k_hr_keys_count<SceneHrKey>, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)),
+                     dim3(kBlock), 0, st, kf, n_hr, s.keys, s.slot, s.src, s.counts);
   hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
   if (e != hipSuccess) return e;
   const bool in_place = out_x == hr_x || out_v == hr_v;
@@ -700,6 +696,58 @@ hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* h
     hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.x, s.v, s.perm,
                        n_hr, out_x, out_v, ld, perm_out, perm_base);
   }
+  return hipGetLastError();
+}
+
+// Hilbert ranks of one scene's fine cells: mark the Hilbert index of every
+// fine cell of the box in a cube of 2^(3 bits) bins, scan, and give each fine
+// cell the number of box cells before it along the curve.
+__global__ __launch_bounds__(kBlock) void k_rank_mark(int fx, int fy, int fz, int bits, uint32_t* __restrict__ cube) {
+  const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (f >= (int64_t)fx * fy * fz) return;
+  const uint32_t x = (uint32_t)(f % fx), y = (uint32_t)((f / fx) % fy), z = (uint32_t)(f / ((int64_t)fx * fy));
+  cube[hilbert3(x, y, z, bits)] = 1u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_fill(int fx, int fy, int fz, int bits,
+                                                      const uint32_t* __restrict__ local,
+                                                      const uint32_t* __restrict__ chunk_sum,
+                                                      uint32_t* __restrict__ rank) {
+  const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (f >= (int64_t)fx * fy * fz) return;
+  const uint32_t x = (uint32_t)(f % fx), y = (uint32_t)((f / fx) % fy), z = (uint32_t)(f / ((int64_t)fx * fy));
+  rank[f] = cell_offset(local, chunk_sum, hilbert3(x, y, z, bits));
+}
+
+hipError_t launch_hilbert_ranks(const int fdims[3], uint32_t* rank, uint32_t* cube, uint32_t* local,
+                                uint32_t* chunk_sum, hipStream_t st) {
+  int bits = 0;
+  for (int a = 0; a < 3; ++a) bits = std::max(bits, sort_bits(fdims[a]));
+  const int64_t F = (int64_t)fdims[0] * fdims[1] * fdims[2];
+  const int64_t n_cube = (int64_t)1 << (3 * bits);
+  if (F == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rank_mark, dim3(blocks_for(F)), dim3(kBlock), 0, st, fdims[0], fdims[1], fdims[2], bits, cube);
+  hipError_t e = scan_bins(cube, n_cube, local, chunk_sum, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rank_fill, dim3(blocks_for(F)), dim3(kBlock), 0, st, fdims[0], fdims[1], fdims[2], bits,
+                     local, chunk_sum, rank);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_hr_batched(float* hr_x, float* hr_v, int64_t n, const int64_t* start,
+                                  int n_scenes, const HrRankScene* sc, const uint32_t* rank, int64_t n_bins,
+                                  const HRSortScratch& s, int32_t* perm_out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const BatchHrKey kf{hr_x, n, start, n_scenes, sc, rank};
+  const unsigned nb = (unsigned)((n + kHrSpan - 1) / kHrSpan);
+  hipLaunchKernelGGL(k_hr_keys_count<BatchHrKey>, dim3(nb), dim3(kBlock), 0, st, kf, n, s.keys, s.slot, s.src,
+                     s.counts);
+  hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hr_scatter, dim3(nb), dim3(kBlock), 0, st, s.keys, s.slot, s.src, n, s.local, s.chunk_sum,
+                     hr_x, hr_v, n, s.x, s.v, perm_out != nullptr ? s.perm : nullptr);
+  hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n)), dim3(kBlock), 0, st, s.x, s.v, s.perm, n,
+                     hr_x, hr_v, n, perm_out, 0);
   return hipGetLastError();
 }
 

@@ -72,6 +72,45 @@ inline int sort_bits(int64_t n) {
 // fine cells) 2^(bx + by + bz); mode 0 (grid cell, then Morton order of its
 // sub-cells) n_cells * sub^3; mode 2 (global Hilbert index of fine cells, on
 // a cube of 2^max(bx, by, bz) cells per axis) 2^(3 max(bx, by, bz)).
+// Index of fine cell (x0, x1, x2) along a 3-D Hilbert curve over a cube of
+// 2^b cells per axis, by Skilling's transpose method ("Programming the Hilbert
+// curve", AIP Conf. Proc. 707, 2004): undo the excess work of each level from
+// the top bit down, Gray-encode, then interleave the bits with axis 0 most
+// significant.  Consecutive indices are face-neighbouring cells, so runs of
+// particles in this order fill compact boxes (no Z-order jumps).
+__host__ __device__ inline uint32_t hilbert3(uint32_t x0, uint32_t x1, uint32_t x2, int b) {
+  for (int k = b - 1; k > 0; --k) {
+    const uint32_t q = 1u << k, p = q - 1u;
+    x0 = (x0 & q) ? (x0 ^ p) : x0;
+    {
+      const uint32_t t = (x0 ^ x1) & p;
+      const bool hit = (x1 & q) != 0u;
+      x0 = hit ? (x0 ^ p) : (x0 ^ t);
+      x1 = hit ? x1 : (x1 ^ t);
+    }
+    {
+      const uint32_t t = (x0 ^ x2) & p;
+      const bool hit = (x2 & q) != 0u;
+      x0 = hit ? (x0 ^ p) : (x0 ^ t);
+      x2 = hit ? x2 : (x2 ^ t);
+    }
+  }
+  x1 ^= x0;
+  x2 ^= x1;
+  uint32_t t = 0u;
+  for (int k = b - 1; k > 0; --k) {
+    const uint32_t q = 1u << k;
+    if (x2 & q) t ^= q - 1u;
+  }
+  x0 ^= t;
+  x1 ^= t;
+  x2 ^= t;
+  uint32_t key = 0u;
+  for (int k = b - 1; k >= 0; --k)
+    key = (key << 3) | (((x0 >> k) & 1u) << 2) | (((x1 >> k) & 1u) << 1) | ((x2 >> k) & 1u);
+  return key;
+}
+
 inline int64_t sort_bins(const int dims[3], int sub, int mode) {
   if (mode == 0) return (int64_t)dims[0] * dims[1] * dims[2] * sub * sub * sub;
   int b = 0, m = 0;
@@ -90,6 +129,27 @@ inline int64_t sort_bins(const int dims[3], int sub, int mode) {
 hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
                           float* out_v, int64_t n_hr, int sub, int mode, const HRSortScratch& s,
                           int32_t* perm_out, hipStream_t st, int64_t ld = -1, int32_t perm_base = 0);
+
+// One scene of a batched HR reorder: its grid, sub-cells per axis, fine grid
+// dims (dims * sub) and first bin (also its offset in the rank table).
+struct HrRankScene {
+  GridConst gc;
+  int sub;
+  int fdims[3];
+  uint32_t base;
+};
+// Hilbert rank of every fine cell of a grid of fdims fine cells (row-major,
+// x fastest) among all of them: rank (uint32 [fx fy fz]); cube, local (uint32
+// [2^(3 bits)], cube zero on entry and on exit) and chunk_sum are scratch.
+hipError_t launch_hilbert_ranks(const int fdims[3], uint32_t* rank, uint32_t* cube, uint32_t* local,
+                                uint32_t* chunk_sum, hipStream_t st);
+// Reorder of the columns [0, n) of a batch (scene s owns start[s] ..
+// start[s + 1]) in place: key = base + rank[base + fine cell] per scene, one
+// counting sort over n_bins bins for all scenes.  perm_out (or null) receives
+// the old column of each new column.
+hipError_t launch_sort_hr_batched(float* hr_x, float* hr_v, int64_t n, const int64_t* start,
+                                  int n_scenes, const HrRankScene* sc, const uint32_t* rank, int64_t n_bins,
+                                  const HRSortScratch& s, int32_t* perm_out, hipStream_t st);
 
 // a6: fused gather + blend + integrate + walls.
 struct AdvanceArgs {

@@ -130,18 +130,23 @@ def test_batched_empty_scenes_and_recapture(mods):
     np.testing.assert_allclose(host(b.split_hr(res[0][1])[1]), v_ff, rtol=1e-6, atol=1e-6)
 
 
-def test_batched_reorder_equals_plain_reorder(mods):
+@pytest.mark.parametrize("layout", ["in_order", "reversed"])
+def test_batched_reorder_equals_plain_reorder(mods, layout):
     """upsample_batch_sort_hr sorts each scene's columns by the key
-    upsample_sort_hr uses for that scene alone: the sequence of keys is the
-    same and the permutation is one (particles of one fine cell may come in
-    another order: the counting sort places them by arrival, a valid order of
-    equal keys).  With the batch's permutation applied to the per-scene state,
+    upsample_sort_hr uses for that scene alone (scenes in column order: one
+    counting sort over all scenes; reversed: one sort per scene).  The
+    sequence of keys is the same and the permutation is one (particles of one
+    fine cell may come in another order: the counting sort places them by
+    arrival, a valid order of equal keys).  With the batch's permutation applied to the per-scene state,
     the batched steps that follow stay bit-identical to the per-scene steps."""
     from oracle import upsample_oracle as O
     from gpu_util import morton_sort_keys
     Batch, Upsampler = mods
     scenes = _scenes()
-    b = Batch.from_scenes(scenes)
+    offsets = None
+    if layout == "reversed":   # scenes in reverse column order: the per-scene route
+        offsets = np.concatenate([[0], np.cumsum([s.n_hr for s in scenes[::-1]])[:-1]])[::-1]
+    b = Batch.from_scenes(scenes, hr_offsets=offsets)
     plain = [Upsampler.from_scene(s) for s in scenes]
     hx0, hv0 = _hr_state(scenes, 3)
     px = [dev(a, torch) for a in hx0]
@@ -178,5 +183,5 @@ def test_batched_reorder_equals_plain_reorder(mods):
         torch.cuda.synchronize()
         for s, (gx, gv) in enumerate(zip(b.split_hr(bx), b.split_hr(bv))):
             assert torch.equal(gx, px[s]) and torch.equal(gv, pv[s]), (t, s, scenes[s].name)
-    log(f"batched reorder: {len(scenes)} scenes, two reorders: per-scene key order, steps bit-identical")
+    log(f"batched reorder ({layout}): {len(scenes)} scenes, two reorders: per-scene key order, steps bit-identical")
     b.close()
