@@ -464,7 +464,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
       hi0 = fmaxf(hi0, ts.gb[g].hi[0]); hi1 = fmaxf(hi1, ts.gb[g].hi[1]); hi2 = fmaxf(hi2, ts.gb[g].hi[2]);
     }
     wc = wall_cull(gc, a.wall_mask, ts.bx0, ts.bx1, ts.by0, ts.by1, ts.bz0, ts.bz1);
-    if (!RIGID) {
+    {
       // weights in the vector unit, sums on the matrix cores
       v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
       const int comp = lane & 3;
@@ -499,14 +499,25 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
         auto step = [&](uint32_t c) {
           const float4 Q = lp[c];
           const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
-          const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          float sq;
+          if (RIGID) {
+            // each operation rounded separately: the exact membership
+            // predicate, of which a granular entry decides the rigid rule
+            // (padding entries are far: never members)
+            sq = (dx * dx + dy * dy) + dz * dz;
+            gran |= ((__float_as_uint(Q.w) & 0x80000000u) == 0u) & (sq < gc.h2);
+          } else {
+            sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          }
           take(cube01(fmaf(-sq, inv_h2, 1.0f)), lvf, c);
         };
-        // eight entries per trip (one address update), then a last four
+        // eight entries per trip (one address update), then a last four; four
+        // per trip with rigid particles, whose walk holds more per entry
+        constexpr uint32_t kTrip = RIGID ? 4u : 8u;
         uint32_t c0 = 0;
-        for (; c0 + 8u <= nc; c0 += 8u) {
+        for (; c0 + kTrip <= nc; c0 += kTrip) {
 #pragma unroll
-          for (int k = 0; k < 8; ++k) step(c0 + (uint32_t)k);
+          for (int k = 0; k < (int)kTrip; ++k) step(c0 + (uint32_t)k);
         }
         if (c0 < nc) {
 #pragma unroll
@@ -526,33 +537,6 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
       }
       if (!TAPE) M = __int_as_float(Mb);
       quad_sums(acc, lane, Ux, Uy, Uz, S);
-    } else {  // scenes with rigid LR particles: the membership test needs each pair
-      tile_visit<G>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
-        for (uint32_t c = 0; c < nc; ++c) {
-          const float4 Q = lp[c];
-          const float4 W = lv[c];
-          const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
-          const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-          const float u = fmaxf(fmaf(-sq, inv_h2, 1.0f), 0.0f);
-          const float w = u * u * u;
-          S += w;
-          Ux = fmaf(w, W.x, Ux);
-          Uy = fmaf(w, W.y, Uy);
-          Uz = fmaf(w, W.z, Uz);
-          if (TAPE) {
-            const uint64_t k = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~__float_as_uint(W.w));
-            key = k > key ? k : key;
-          } else {
-            M = fmaxf(M, w);
-          }
-          if (DBG && Q.x < 1.0e38f) dw.see(w, Q.x, Q.y, Q.z, __float_as_uint(W.w), x, y, z, gc);
-          if (RIGID) {
-            const uint32_t bits = __float_as_uint(Q.w);
-            // exact membership of a granular LR particle decides the rigid rule
-            if ((bits & 0x80000000u) == 0u && Q.x < 1.0e38f) gran |= sq_dist(Q.x, Q.y, Q.z, x, y, z) < gc.h2;
-          }
-        }
-      });
     }
     if (TAPE) {
       M = __uint_as_float((uint32_t)(key >> 32));
