@@ -58,8 +58,8 @@ def parse():
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched legs")
-    ap.add_argument("--only", choices=["drain", "column", "plain", "multirate", "sampling", "pbd", "pipeline", "diff",
-                                       "batched"],
+    ap.add_argument("--only", choices=["drain", "column", "plain", "multirate", "sampling", "pbd", "pipeline",
+                                       "pipeline_drain", "diff", "batched"],
                     default=None,
                     help="run one leg only (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -578,14 +578,15 @@ def multirate_leg(args, torch, Upsampler, steps=60, warmup=10, dt_lr=0.005):
 def pbd_leg(torch, steps=200, warmup=20, reps=3):
     """The LR simulation step (Section 3, Algorithm 1: two stabilization and
     five solver iterations): the column collapse (16,384 granular LR on 7,225
-    static floor samples) and the impact scene (a granular bed, two rigid
-    bodies), after a warm-up into motion."""
+    static floor samples), the impact scene (a granular bed, two rigid
+    bodies) and the drain (65,536 granular LR on 14,505 static samples of its
+    silo, hopper and plate), after a warm-up into motion."""
     from workloads import lr_scenes
     from paper_2308_01629_amd.lr_sim import LRSim
     res = {}
-    for sc in (lr_scenes.column_collapse(), lr_scenes.impact()):
+    for sc in (lr_scenes.column_collapse(), lr_scenes.impact(), lr_scenes.drain_flow()):
         sim = LRSim(sc.body, sc.inv_m, sc.rest, sc.r, sc.domain_lo, sc.domain_hi, dt=sc.dt, g=sc.g,
-                    ground_y=sc.ground_y)
+                    ground_y=sc.ground_y, max_neighbors=64 if sc.name == "drain_flow" else 32)
         x = torch.from_numpy(sc.x).cuda()
         v = torch.from_numpy(sc.v).cuda()
         sim.step(x, v, warmup)
@@ -612,31 +613,41 @@ def pbd_leg(torch, steps=200, warmup=20, reps=3):
     return res
 
 
-def pipeline_leg(args, torch, Upsampler, hr_steps=60, dt_lr=0.005, n_cand=8_000_000):
-    """The column collapse end to end on the GPU: HR initial state by volume
-    sampling inside the column (r_HR = 0.3 r_LR), LR frames by the LR step
-    at dt_LR = 0.005 s, HR steps of 1/60 s against the LR state interpolated
-    at each HR time level (the static floor samples flagged rigid).  Timed:
-    one simulated second, the LR steps and the HR steps."""
+def pipeline_leg(args, torch, Upsampler, scene="column", hr_steps=60):
+    """A scene end to end on the GPU: HR initial state by volume sampling
+    inside the LR fill, LR frames by the LR step at dt_LR = 0.005 s, HR steps
+    of 1/60 s against the LR state interpolated at each HR time level (the
+    static boundary samples flagged rigid).  Timed: one simulated second, the
+    LR steps and the HR steps.  column: the column collapse (r_HR = 0.3 r_LR,
+    8M candidates, box walls, dt_LR 0.005 s); drain: the drain running out
+    through its orifice (r_HR = r_LR / 4, 16M candidates, the drain's 11
+    walls, dt_LR 0.0025 s by the CFL condition, up to 64 pairs per
+    particle)."""
     from workloads import lr_scenes
-    from workloads.generators import box_walls, volume_candidates
+    from workloads.generators import box_walls, make_geometry, volume_candidates
     from paper_2308_01629_amd.lr_sim import LRSim
     from paper_2308_01629_amd.upsampler import sample_volume
-    sc = lr_scenes.column_collapse()
-    r_hr = 0.3 * sc.r
+    if scene == "column":
+        sc = lr_scenes.column_collapse()
+        r_hr, n_cand, seed, k_max = 0.3 * sc.r, 8_000_000, [47, 2], 32
+        walls = np.stack(box_walls(np.zeros(3), np.array([2.0, 1.5, 2.0]))).astype(np.float32)
+    else:
+        sc = lr_scenes.drain_flow()
+        r_hr, n_cand, seed, k_max = 0.25 * sc.r, 16_000_000, [43, 1], 64
+        walls = np.stack(make_geometry("drain").walls).astype(np.float32)
+    dt_lr = sc.dt
     top = float(sc.x[1, sc.body == lr_scenes.GRANULAR].max()) + sc.r
-    cand, lo, hi = volume_candidates("column", n_cand, [47, 2], top=top)
+    cand, lo, hi = volume_candidates(scene, n_cand, seed, top=top)
     hx = sample_volume(torch.from_numpy(cand).cuda(), r_hr, lo, hi)
     del cand
     hv = torch.zeros_like(hx)
     n_hr = hx.shape[1]
     dt_hr = 1.0 / 60.0
     n_lr_steps = int(math.ceil(hr_steps * dt_hr / dt_lr)) + 1
-    walls = np.stack(box_walls(np.zeros(3), np.array([2.0, 1.5, 2.0]))).astype(np.float32)
     up = Upsampler(sc.r, r_hr, dt_hr, sc.g, sc.domain_lo, sc.domain_hi, walls=walls, max_lr=sc.n, max_hr=n_hr)
     rigid = torch.from_numpy(sc.lr_rigid).cuda()
     sim = LRSim(sc.body, sc.inv_m, sc.rest, sc.r, sc.domain_lo, sc.domain_hi, dt=dt_lr, g=sc.g,
-                ground_y=sc.ground_y)
+                ground_y=sc.ground_y, max_neighbors=k_max)
     LX = torch.empty((n_lr_steps + 1, 3, sc.n), dtype=torch.float32, device="cuda")
     LV = torch.empty_like(LX)
     x0 = torch.from_numpy(sc.x).cuda()
@@ -666,9 +677,10 @@ def pipeline_leg(args, torch, Upsampler, hr_steps=60, dt_lr=0.005, n_cand=8_000_
     sim.close()
     up.close()
     tl, th = float(np.median(t_lr)), float(np.median(t_hr))
-    log(f"pipeline: {sc.n} LR x {n_lr_steps} steps in {tl * 1e3:.1f} ms, {n_hr} HR x {hr_steps} steps in "
+    log(f"pipeline {scene}: {sc.n} LR x {n_lr_steps} steps in {tl * 1e3:.1f} ms, {n_hr} HR x {hr_steps} steps in "
         f"{th * 1e3:.1f} ms: one simulated second in {(tl + th) * 1e3:.1f} ms")
-    return {"workload": "column collapse, LR step + volume-sampled HR + multi-rate upsampling",
+    what = {"column": "column collapse", "drain": "drain running out"}[scene]
+    return {"workload": f"{what}, LR step + volume-sampled HR + multi-rate upsampling",
             "n_lr": sc.n, "n_hr": int(n_hr), "lr_steps": n_lr_steps, "hr_steps": hr_steps, "dt_lr": dt_lr,
             "dt_hr": dt_hr, "lr_ms_per_step": tl * 1e3 / n_lr_steps, "hr_ms_per_step": th * 1e3 / hr_steps,
             "ms_per_simulated_second": (tl + th) * 1e3, "value": n_hr * hr_steps / (tl + th),
@@ -757,7 +769,9 @@ def main():
     if args.only == "pbd" or (args.only is None and not args.no_extras):
         out["lr_step"] = pbd_leg(torch)
     if args.only == "pipeline" or (args.only is None and not args.no_extras):
-        out["pipeline"] = pipeline_leg(args, torch, Upsampler)
+        out["pipeline"] = pipeline_leg(args, torch, Upsampler, "column")
+    if args.only == "pipeline_drain" or (args.only is None and not args.no_extras):
+        out["pipeline_drain"] = pipeline_leg(args, torch, Upsampler, "drain")
     if args.only == "diff" or (args.only is None and not args.no_extras):
         out["backward_forward"] = diff_leg(args, torch, Upsampler)
     if args.only == "batched" or (args.only is None and not args.no_extras):

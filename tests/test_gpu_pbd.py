@@ -19,8 +19,10 @@ own float32 input to that stage.
   plus the position tolerance over dt.
 
 Scenes (workloads/lr_scenes.py): the column-collapse workload at full size
-(16,384 granular LR on 7,225 static floor samples) and reduced, and an impact
-scene with two rigid bodies, at fresh and moving states.  Plus the frames of a
+(16,384 granular LR on 7,225 static floor samples) and reduced, an impact
+scene with two rigid bodies, and the drain (65,536 granular LR on 14,505
+static samples of its silo and hopper) running out through its orifice, at
+fresh and moving states.  Plus the frames of a
 multi-step call against single steps, the free fall of a rigid body in closed
 form, invariants over a long run, and edge cases."""
 import itertools
@@ -49,7 +51,8 @@ def LRSim():
 
 def _scene(name):
     return {"column": lambda: S.column_collapse(), "column_small": lambda: S.column_collapse(0.1),
-            "impact": lambda: S.impact(), "impact_small": lambda: S.impact(True)}[name]()
+            "impact": lambda: S.impact(), "impact_small": lambda: S.impact(True),
+            "drain": lambda: S.drain_flow()}[name]()
 
 
 def _prm(sc, **kw):
@@ -203,9 +206,9 @@ def check_debug_step(cls, sc, warm_steps, **sim_kw):
 
 
 @pytest.mark.parametrize("name,warm", [("impact_small", 0), ("impact_small", 14), ("column_small", 25),
-                                       ("impact", 20), ("column", 30)])
+                                       ("impact", 20), ("column", 30), ("drain", 40)])
 def test_stages_against_oracle(LRSim, name, warm):
-    check_debug_step(LRSim, _scene(name), warm)
+    check_debug_step(LRSim, _scene(name), warm, **({"max_neighbors": 64} if name == "drain" else {}))
 
 
 @pytest.mark.parametrize("kw", [dict(stab_iters=0), dict(solve_iters=0), dict(mass_scaling=False),

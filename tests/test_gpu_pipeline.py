@@ -116,3 +116,58 @@ def test_column_collapse_full_size_sampled(libs):
     assert not sim.overflow()
     sim.close()
     up.close()
+
+
+def test_drain_running_out_full_size_sampled(libs):
+    """The drain by the LR step (65,536 granular LR on the static samples of
+    its silo, hopper and plate, dt_LR = 0.0025 s by the CFL condition, up to
+    64 pairs per particle), about 2M HR volume-sampled in the silo
+    (r_HR = r_LR / 4) behind the drain's 11 analytic walls: 30 HR steps run
+    while the sand starts through the orifice, then three HR steps, each
+    against the oracle on 4,096 sampled HR particles from the GPU's own
+    state."""
+    from workloads.generators import make_geometry, volume_candidates
+    LRSim, Upsampler, sample_volume = libs
+    sc = S.drain_flow()
+    r_hr = 0.25 * sc.r
+    top = float(sc.x[1, sc.body == S.GRANULAR].max()) + sc.r
+    cand, lo, hi = volume_candidates("drain", 16_000_000, [43, 1], top=top)
+    hx = sample_volume(dev(cand, torch), r_hr, lo, hi)
+    del cand
+    hv = torch.zeros_like(hx)
+    n_hr = hx.shape[1]
+    T0, T = 30, 3
+    dt_lr = sc.dt   # the CFL-limited step of the drain
+    n_lr = int(np.ceil((T0 + T) * DT_HR / dt_lr)) + 1
+    sim = LRSim(sc.body, sc.inv_m, sc.rest, sc.r, sc.domain_lo, sc.domain_hi, dt=dt_lr, g=sc.g, max_neighbors=64)
+    x, v = dev(sc.x, torch), dev(sc.v, torch)
+    fx, fv = sim.step(x, v, n_lr, frames=True)
+    LX = torch.cat([dev(sc.x, torch)[None], fx]).contiguous()
+    LV = torch.cat([dev(sc.v, torch)[None], fv]).contiguous()
+    del fx, fv
+    walls = np.stack(make_geometry("drain").walls).astype(np.float32)
+    up = Upsampler(sc.r, r_hr, DT_HR, sc.g, sc.domain_lo, sc.domain_hi, walls=walls, max_lr=sc.n, max_hr=n_hr)
+    up.sort_hr(hx, hv, with_perm=False)
+    rigid_d = dev(sc.lr_rigid, torch)
+    up.run_multirate(LX, LV, hx, hv, n_steps=T0, dt_lr=dt_lr, sort_every=10, lr_rigid=rigid_d)
+    prm = dict(r_lr=float(np.float32(sc.r)), r_hr=float(np.float32(r_hr)), dt=float(np.float32(DT_HR)),
+               g=np.asarray(sc.g, np.float32), c1=512.0 / 729.0, c2=0.6, domain_lo=sc.domain_lo,
+               domain_hi=sc.domain_hi, walls=walls)
+    rigid = sc.lr_rigid.astype(bool)
+    box = float(np.max(sc.domain_hi - sc.domain_lo))
+    idx = np.sort(np.random.default_rng(10).choice(n_hr, 4096, replace=False))
+    below = int((host(LX[-1])[1, sc.body == S.GRANULAR] < 0.6).sum())
+    for n in range(T0, T0 + T):
+        x0, v0 = host(hx).copy(), host(hv).copy()
+        up.run_multirate(LX, LV, hx, hv, n_steps=1, dt_lr=dt_lr, t_hr0=n * DT_HR, lr_rigid=rigid_d)
+        torch.cuda.synchronize()
+        k_th = MR.hr_schedule(n * DT_HR, DT_HR, 1, 0.0, dt_lr, n_lr + 1)
+        (k, th), = k_th
+        X, V = MR.lerp_frame_f32(host(LX[k]), host(LV[k]), host(LX[k + 1]), host(LV[k + 1]), th)
+        s = compare_step(host(hx), host(hv), X, V, rigid, x0, v0, prm, box, idx=idx)
+        log(f"pipeline drain step {n}: frames {k}, {k + 1}, theta {th:.4f}, {n_hr} HR (4,096 sampled), "
+            f"{below} LR below the plate at the last frame: {s}")
+    assert below > 0, "the sand should be running out"
+    assert not sim.overflow()
+    sim.close()
+    up.close()

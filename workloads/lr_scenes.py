@@ -13,6 +13,10 @@ take these arrays as they are.
 * ``impact``: a granular bed in a box of static samples, hit by a rigid
   ellipsoid thrown into it while a rigid cube falls beside it (the shape of
   the paper's rigid-body scenes, with analytic shapes for its meshes).
+* ``drain_flow``: the drain workload's 65,536 granular LR (r = 0.0125) in
+  its silo, standing on static samples of the 60 degree hopper, of the
+  orifice plate's corners, of the silo walls and of a floor under the
+  orifice, so that the sand runs out through the orifice.
 """
 from __future__ import annotations
 
@@ -22,7 +26,7 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from .generators import fill_lattice, make_geometry
+from .generators import HOPPER_ANGLE, fill_lattice, make_geometry
 
 GRANULAR = -1
 STATIC = -2
@@ -132,3 +136,65 @@ def impact(small: bool = False, seed: int = 6, dt: float = 0.005) -> LRScene:
     return _assemble("impact_small" if small else "impact", r, dt, (0.0, -9.81, 0.0), lo, hi, 0.0,
                      [(boundary, None, STATIC, 0.0), (sand, None, GRANULAR, 1.0),
                       (E + e_c, (2.0, -2.5, 0.0), 0, 0.4), (C + c_c, (0.0, -1.0, 0.0), 1, 0.4)])
+
+
+def drain_flow(scale: float = 1.0, seed: int = 3, dt: float = 0.0025) -> LRScene:
+    """The drain workload's granular LR fill (65,536 * scale particles,
+    jittered lattice, at rest) on static samples of its boundary: the four
+    hopper planes from the orifice plate's throat up to the silo walls, the
+    plate's corners around the orifice (radius 0.1), the silo walls above
+    the hopper and below the plate, and a floor at y = 0.  Every static
+    sample sits r behind the surface it represents, at spacing 2r.  The time
+    step is the default 0.005 s limited by the CFL condition (Section 5.2):
+    sand falling the 0.6 m below the plate reaches about 3.4 m/s, so a step
+    of 0.0025 s moves it at most about r."""
+    r = 0.0125
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 13]))
+    geom = make_geometry("drain", with_walls=False)
+    y0, th, R = geom.params["plate_y"], geom.params["throat"], geom.params["orifice"]
+    sand = fill_lattice(geom, r, int(65536 * scale), rng)
+    sp = 2 * r
+    ta = math.tan(HOPPER_ANGLE)
+    s_, c_ = math.sin(HOPPER_ANGLE), math.cos(HOPPER_ANGLE)
+    y_top = y0 + (0.5 - th) * ta           # where the hopper meets the silo walls
+    top = float(sand[:, 1].max()) + 4 * r
+    parts = []
+    # hopper planes: along the slope from the throat edge, across within the
+    # frustum's half-width at that height; offset r along the outward normal
+    t_max = (y_top - y0) / s_
+    for ax in (0, 2):
+        other = 2 - ax
+        for sign in (1.0, -1.0):
+            for t in np.arange(0.0, t_max + 1e-9, sp):
+                y = y0 + s_ * t
+                hw = th + (y - y0) / ta
+                u = np.arange(0.5 - hw, 0.5 + hw + 1e-9, sp)
+                P = np.zeros((u.size, 3))
+                P[:, ax] = 0.5 + sign * (th + c_ * t) + sign * s_ * r
+                P[:, 1] = y - c_ * r
+                P[:, other] = u
+                parts.append(P)
+    # orifice plate: the corners of the throat square outside the hole
+    g = np.arange(0.5 - th, 0.5 + th + 1e-9, sp)
+    gx, gz = np.meshgrid(g, g, indexing="ij")
+    keep = np.hypot(gx - 0.5, gz - 0.5) >= R + r
+    parts.append(np.stack([gx[keep], np.full(keep.sum(), y0 - r), gz[keep]], axis=1))
+    # silo walls above the hopper and below the plate, and the floor
+    ys = np.concatenate([np.arange(-r, y0 + 1e-9, sp), np.arange(y_top - r, top + 1e-9, sp)])
+    w = np.arange(0.0, 1.0 + 1e-9, sp)
+    for ax in (0, 2):
+        other = 2 - ax
+        for pos in (-r, 1.0 + r):
+            A, Y = np.meshgrid(w, ys, indexing="ij")
+            P = np.zeros((A.size, 3))
+            P[:, ax] = pos
+            P[:, 1] = Y.ravel()
+            P[:, other] = A.ravel()
+            parts.append(P)
+    F = _lattice((0.0, -r, 0.0), (1.0, -r, 1.0), sp)
+    parts.append(F)
+    boundary = np.unique(np.round(np.concatenate(parts), 9), axis=0)
+    lo = (-4 * r, -4 * r, -4 * r)
+    hi = (1.0 + 4 * r, 2.4 + 4 * r, 1.0 + 4 * r)
+    return _assemble("drain_flow", r, dt, (0.0, -9.81, 0.0), lo, hi, 0.0,
+                     [(boundary, None, STATIC, 0.0), (sand, None, GRANULAR, 1.0)])
