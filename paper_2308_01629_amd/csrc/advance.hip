@@ -499,25 +499,34 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
         auto step = [&](uint32_t c) {
           const float4 Q = lp[c];
           const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
-          float sq;
-          if (RIGID) {
-            // each operation rounded separately: the exact membership
-            // predicate, of which a granular entry decides the rigid rule
-            // (padding entries are far: never members)
-            sq = (dx * dx + dy * dy) + dz * dz;
-            gran |= ((__float_as_uint(Q.w) & 0x80000000u) == 0u) & (sq < gc.h2);
-          } else {
-            sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-          }
+          const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
           take(cube01(fmaf(-sq, inv_h2, 1.0f)), lvf, c);
         };
-        // eight entries per trip (one address update), then a last four; four
-        // per trip with rigid particles, whose walk holds more per entry
-        constexpr uint32_t kTrip = RIGID ? 4u : 8u;
         uint32_t c0 = 0;
-        for (; c0 + kTrip <= nc; c0 += kTrip) {
+        if (RIGID) {
+          // With rigid particles a lane must learn whether a granular LR
+          // particle is its member: the squared distance rounded operation
+          // by operation (the exact predicate; padding entries are far)
+          // decides, and the weight is taken from it too.  Once every lane
+          // of the wave has met one, the rest of the list takes the plain
+          // walk.  Four entries per trip.
+          auto step_rigid = [&](uint32_t c) {
+            const float4 Q = lp[c];
+            const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
+            const float sq = (dx * dx + dy * dy) + dz * dz;
+            gran |= ((__float_as_uint(Q.w) & 0x80000000u) == 0u) & (sq < gc.h2);
+            take(cube01(fmaf(-sq, inv_h2, 1.0f)), lvf, c);
+          };
+          for (; c0 + 4u <= nc; c0 += 4u) {
+            if (__builtin_amdgcn_ballot_w64(!gran) == 0ull) break;
 #pragma unroll
-          for (int k = 0; k < (int)kTrip; ++k) step(c0 + (uint32_t)k);
+            for (int k = 0; k < 4; ++k) step_rigid(c0 + (uint32_t)k);
+          }
+        }
+        // eight entries per trip (one address update), then a last four
+        for (; c0 + 8u <= nc; c0 += 8u) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) step(c0 + (uint32_t)k);
         }
         if (c0 < nc) {
 #pragma unroll
