@@ -11,7 +11,12 @@
 // least two sides (2.31 r) apart and cannot conflict.  Within a phase every
 // cell chooses at once (one thread per cell), and the result is that of the
 // sequential pass over the cells in (colour, key) order.  A conflict can only
-// come from the 5 x 5 x 5 cells around a cell (2 r is 1.73 sides).
+// come from the 5 x 5 x 5 cells around a cell (2 r is 1.73 sides), and in
+// phase k only from those of the k colours before it: cells of later colours
+// are still empty, and the only cell of its own colour in the window is the
+// cell itself.  Each phase therefore tests the offsets of earlier colours
+// alone (none in the first phase, 62 on average), nearest first so that a
+// candidate that conflicts is rejected early.
 //
 // Candidates go through the LR grid build (keys, stable counting sort by
 // cell: a cell's candidates stay in input order), so the whole routine is
@@ -32,12 +37,19 @@ __global__ __launch_bounds__(kBlock) void k_zero_f4(float4* __restrict__ p, int6
   if (i < n) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// The offsets one phase tests: (dx + 2) | (dy + 2) << 3 | (dz + 2) << 6.
+struct PhaseOffsets {
+  int n;
+  uint32_t off[124];
+};
+
 // One colour phase: cells (a + 3 i, b + 3 j, c + 3 k).  A cell tries its
 // candidates in order and keeps the first whose separately rounded squared
-// distance to every sample of the 5 x 5 x 5 neighbourhood is >= d2 = fl(4 r^2).
+// distance to every sample of the listed neighbour cells is >= d2 = fl(4 r^2).
 __global__ __launch_bounds__(kBlock) void k_sample_phase(GridConst gc, const uint32_t* __restrict__ cell_start,
                                                          const LRPoint* __restrict__ cand, float4* __restrict__ smp,
-                                                         int a, int b, int c, int ni, int nj, int nk, float d2) {
+                                                         int a, int b, int c, int ni, int nj, int nk, float d2,
+                                                         PhaseOffsets po) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= (int64_t)ni * nj * nk) return;
   const int i = (int)(t % ni), j = (int)((t / ni) % nj), k = (int)(t / ((int64_t)ni * nj));
@@ -48,22 +60,14 @@ __global__ __launch_bounds__(kBlock) void k_sample_phase(GridConst gc, const uin
   for (uint32_t q = cell_start[key]; q < e; ++q) {
     const float4 P = cand[q].p;
     bool ok = true;
-    for (int dz = -2; dz <= 2 && ok; ++dz) {
-      const int z = cz + dz;
-      if (z < 0 || z >= Gz) continue;
-      for (int dy = -2; dy <= 2 && ok; ++dy) {
-        const int y = cy + dy;
-        if (y < 0 || y >= Gy) continue;
-        const uint32_t row = (uint32_t)Gx * ((uint32_t)y + (uint32_t)Gy * (uint32_t)z);
-        for (int dx = -2; dx <= 2; ++dx) {
-          const int x = cx + dx;
-          if (x < 0 || x >= Gx) continue;
-          const float4 S = smp[row + (uint32_t)x];
-          if (S.w != 0.0f && sq_dist(P.x, P.y, P.z, S.x, S.y, S.z) < d2) {
-            ok = false;
-            break;
-          }
-        }
+    for (int o = 0; o < po.n; ++o) {
+      const uint32_t w = po.off[o];
+      const int x = cx + (int)(w & 7u) - 2, y = cy + (int)((w >> 3) & 7u) - 2, z = cz + (int)(w >> 6) - 2;
+      if ((unsigned)x >= (unsigned)Gx || (unsigned)y >= (unsigned)Gy || (unsigned)z >= (unsigned)Gz) continue;
+      const float4 S = smp[(uint32_t)x + (uint32_t)Gx * ((uint32_t)y + (uint32_t)Gy * (uint32_t)z)];
+      if (S.w != 0.0f && sq_dist(P.x, P.y, P.z, S.x, S.y, S.z) < d2) {
+        ok = false;
+        break;
       }
     }
     if (ok) {
@@ -71,6 +75,22 @@ __global__ __launch_bounds__(kBlock) void k_sample_phase(GridConst gc, const uin
       return;
     }
   }
+}
+
+// The neighbour offsets of phase (a, b, c) whose cells have an earlier
+// colour, ordered by squared offset length.
+PhaseOffsets phase_offsets(int a, int b, int c) {
+  PhaseOffsets po{};
+  const int col = a + 3 * b + 9 * c;
+  for (int len = 1; len <= 12; ++len)
+    for (int dz = -2; dz <= 2; ++dz)
+      for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+          if (dx * dx + dy * dy + dz * dz != len) continue;
+          const int nc = (a + dx + 3) % 3 + 3 * ((b + dy + 3) % 3) + 9 * ((c + dz + 3) % 3);
+          if (nc < col) po.off[po.n++] = (uint32_t)(dx + 2) | (uint32_t)(dy + 2) << 3 | (uint32_t)(dz + 2) << 6;
+        }
+  return po;
 }
 
 __global__ __launch_bounds__(kBlock) void k_sample_flags(const float4* __restrict__ smp, int64_t n,
@@ -171,7 +191,7 @@ extern "C" int upsample_sample_volume(const float* cand, int64_t n_cand, float r
     const int64_t cnt = (int64_t)ni * nj * nk;
     if (cnt <= 0) continue;
     hipLaunchKernelGGL(k_sample_phase, dim3(blocks_of(cnt)), dim3(kBlock), 0, st, gc, g.cell_start, g.lr_sorted,
-                       smp, a, b, c, ni, nj, nk, gc.h2);
+                       smp, a, b, c, ni, nj, nk, gc.h2, phase_offsets(a, b, c));
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
