@@ -216,12 +216,51 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
   }
 }
 
+// The scatter of a build over positions alone that writes the sorted copy
+// itself: position, the caller's int32 tag (as bits) in p.w, the particle's
+// index in v.w.  Inside a cell the particles keep the order of their slot
+// claims, which varies from run to run; a caller of this build makes its
+// results independent of that order.
+template <bool SCAN_TOTALS>
+__global__ __launch_bounds__(kBlock) void k_scatter_points(const uint32_t* __restrict__ keys,
+                                                           const uint32_t* __restrict__ slot, int64_t n,
+                                                           const uint32_t* __restrict__ local,
+                                                           const uint32_t* __restrict__ chunk_sum,
+                                                           int64_t n_cells, int n_chunks,
+                                                           const float* __restrict__ x,
+                                                           const int32_t* __restrict__ tag,
+                                                           LRPoint* __restrict__ out,
+                                                           uint32_t* __restrict__ cell_start) {
+  __shared__ uint32_t offs[SCAN_TOTALS ? kBlock + 1 : 1];
+  const uint32_t* csum = chunk_sum;
+  if (SCAN_TOTALS) {
+    const uint32_t v = (int)threadIdx.x < n_chunks ? chunk_sum[threadIdx.x] : 0u;
+    uint32_t total;
+    const uint32_t e = block_exclusive_scan(v, &total);
+    offs[threadIdx.x] = e;
+    if (threadIdx.x == 0) offs[n_chunks] = total;
+    __syncthreads();
+    csum = offs;
+  }
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n_cells) cell_start[t] = cell_offset(local, csum, (uint32_t)t);
+  if (t == n_cells) cell_start[t] = csum[n_chunks];
+  if (t < n) {
+    const uint32_t pos = cell_offset(local, csum, keys[t]) + slot[t];
+    if (pos < (uint64_t)n) {  // always true when counts started at zero
+      LRPoint o;
+      o.p = make_float4(x[t], x[n + t], x[2 * n + t], __int_as_float(tag[t]));
+      o.v = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float((uint32_t)t));
+      out[pos] = o;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ tmp,
                                                    const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ cell_start, int64_t n,
                                                    FramePair f,
                                                    const uint8_t* __restrict__ rigid,
-                                                   const int32_t* __restrict__ tag,
                                                    uint32_t* __restrict__ perm,
                                                    LRPoint* __restrict__ out) {
   int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -236,8 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ 
   const uint32_t dst = b + rank;
   if (dst >= e) return;
   perm[dst] = i;
-  // p.w: the rigid flag as 0 / 1, or the caller's int32 tag as bits
-  float flag = tag != nullptr ? __int_as_float(tag[i]) : ((rigid != nullptr && rigid[i] != 0) ? 1.0f : 0.0f);
+  const float flag = (rigid != nullptr && rigid[i] != 0) ? 1.0f : 0.0f;
   LRPoint o;
   o.p = make_float4(frame_at(f.x0, f.x1, f.theta, i), frame_at(f.x0, f.x1, f.theta, n + i),
                     frame_at(f.x0, f.x1, f.theta, 2 * n + i), flag);
@@ -580,8 +618,7 @@ hipError_t scan_bins(uint32_t* counts, int64_t n_bins, uint32_t* local, uint32_t
 }  // namespace
 
 static hipError_t build_grid(const GridConst& gc, const FramePair& f, const uint8_t* lr_rigid, int64_t n_lr,
-                             int64_t n_cells, const GridScratch& s, hipStream_t st,
-                             const int32_t* tag = nullptr) {
+                             int64_t n_cells, const GridScratch& s, hipStream_t st) {
   if (n_lr > 0) {
     hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, gc, f, n_lr,
                        s.keys, s.slot, s.counts);
@@ -602,7 +639,7 @@ static hipError_t build_grid(const GridConst& gc, const FramePair& f, const uint
   }
   if (n_lr > 0) {
     hipLaunchKernelGGL(k_stable, dim3(blocks_for(n_lr)), dim3(kBlock), 0, st, s.tmp, s.keys,
-                       s.cell_start, n_lr, f, lr_rigid, tag, s.perm, s.lr_sorted);
+                       s.cell_start, n_lr, f, lr_rigid, s.perm, s.lr_sorted);
   }
   return hipGetLastError();
 }
@@ -613,9 +650,25 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
   return build_grid(gc, FramePair{lr_x, lr_v, nullptr, nullptr, 0.0f}, lr_rigid, n_lr, n_cells, s, st);
 }
 
-hipError_t launch_build_grid_tagged(const GridConst& gc, const float* x, const int32_t* tag, int64_t n,
+hipError_t launch_build_grid_points(const GridConst& gc, const float* x, const int32_t* tag, int64_t n,
                                     int64_t n_cells, const GridScratch& s, hipStream_t st) {
-  return build_grid(gc, FramePair{x, x, nullptr, nullptr, 0.0f}, nullptr, n, n_cells, s, st, tag);
+  if (n > 0)
+    hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n)), dim3(kBlock), 0, st, gc,
+                       FramePair{x, x, nullptr, nullptr, 0.0f}, n, s.keys, s.slot, s.counts);
+  const int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);
+  const int64_t span = n > n_cells + 1 ? n : n_cells + 1;
+  if (n_chunks <= kBlock) {
+    hipLaunchKernelGGL(k_scan_chunks, dim3(n_chunks), dim3(kBlock), 0, st, s.counts, n_cells, s.local,
+                       s.chunk_sum);
+    hipLaunchKernelGGL(k_scatter_points<true>, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, n,
+                       s.local, s.chunk_sum, n_cells, n_chunks, x, tag, s.lr_sorted, s.cell_start);
+  } else {
+    const hipError_t e = scan_bins(s.counts, n_cells, s.local, s.chunk_sum, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter_points<false>, dim3(blocks_for(span)), dim3(kBlock), 0, st, s.keys, s.slot, n,
+                       s.local, s.chunk_sum, n_cells, n_chunks, x, tag, s.lr_sorted, s.cell_start);
+  }
+  return hipGetLastError();
 }
 
 // The sorted LR copy as structure-of-arrays [3][n] (debug export).

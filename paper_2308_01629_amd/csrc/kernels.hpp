@@ -24,9 +24,11 @@ struct GridScratch {
 hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float* lr_v,
                              const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
                              const GridScratch& s, hipStream_t st);
-// The same build of positions only, with an int32 tag per particle in the
-// sorted copy's p.w (as bits) instead of the rigid flag; v holds x.
-hipError_t launch_build_grid_tagged(const GridConst& gc, const float* x, const int32_t* tag, int64_t n,
+// A build over positions alone (x [3][n]) without the stable fix: the sorted
+// copy holds x and an int32 tag per particle (as bits) in p, the index in
+// v.w, and inside a cell its order varies from run to run.  Leaves perm and
+// tmp untouched.
+hipError_t launch_build_grid_points(const GridConst& gc, const float* x, const int32_t* tag, int64_t n,
                                     int64_t n_cells, const GridScratch& s, hipStream_t st);
 // The same build of the LR state between two frames: x0 + theta (x1 - x0)
 // (and v alike), each float32 operation rounded separately, fused into the

@@ -10,7 +10,7 @@
 // its contact list: a pair's two sides are evaluated by the two particles
 // with the same arithmetic, so no atomics are needed and the result does not
 // depend on scheduling.  The contact lists come from the LR grid build (a
-// uniform grid of cells at least 2r wide, stable counting sort).
+// uniform grid of cells at least 2r wide, counting sort).
 //
 // Per step: k_pbd_predict, grid + k_pbd_pairs on the start positions,
 // stab_iters x k_pbd_stab, grid + k_pbd_pairs on the predicted positions,
@@ -72,15 +72,34 @@ constexpr int kIterLanes = 4;
 // Contact list of each particle: the other particles closer than 2r
 // (squared distance rounded as in the upsampling's membership predicate,
 // against fl32(4 r^2)), without static-static and same-body pairs, ordered by
-// stencil row (dz, then dy) and sorted slot.  Groups of kPairLanes lanes take
-// the sorted slots in order (the sorted copy carries each particle's body id
-// in p.w and its index in v.w).  Each row lane reads its candidates four at
-// a time and keeps its first kRowStage matches in LDS; the group forms the
-// exclusive prefix of the lanes' counts and copies the staged ids to the
-// list.  A lane with more matches than it staged scans its row once more for
-// the rest.  A list longer than K sets *overflow and keeps its first K
-// entries.
+// stencil row (dz, then dy) and, inside a row, by particle index.  The grid's
+// order inside a cell varies from run to run; this order does not, so the
+// iterations sum each particle's constraints in the same order every time.
+// Groups of kPairLanes lanes take the sorted slots in order (the sorted copy
+// carries each particle's body id in p.w and its index in v.w).  Each row
+// lane reads its candidates four at a time and stages its first kRowStage
+// matches in LDS; the group forms the exclusive prefix of the lanes' counts,
+// and a lane with at most kRowStage matches sorts them in registers (a
+// 19-comparator network) and copies them to the list.  A lane with more
+// matches emits all of them in increasing order, one scan of its row for
+// each.  A list longer than K sets *overflow and keeps its first K entries.
 constexpr int kRowStage = 8;
+
+__device__ __forceinline__ void cmp_swap(uint32_t& a, uint32_t& b) {
+  const uint32_t lo = min(a, b);
+  b = max(a, b);
+  a = lo;
+}
+
+// Sorts eight values (Batcher's odd-even merge sort network for 8 inputs).
+__device__ __forceinline__ void sort8(uint32_t (&s)[8]) {
+  cmp_swap(s[0], s[2]); cmp_swap(s[1], s[3]); cmp_swap(s[4], s[6]); cmp_swap(s[5], s[7]);
+  cmp_swap(s[0], s[4]); cmp_swap(s[1], s[5]); cmp_swap(s[2], s[6]); cmp_swap(s[3], s[7]);
+  cmp_swap(s[0], s[1]); cmp_swap(s[2], s[3]); cmp_swap(s[4], s[5]); cmp_swap(s[6], s[7]);
+  cmp_swap(s[2], s[4]); cmp_swap(s[3], s[5]);
+  cmp_swap(s[1], s[4]); cmp_swap(s[3], s[6]);
+  cmp_swap(s[1], s[2]); cmp_swap(s[3], s[4]); cmp_swap(s[5], s[6]);
+}
 
 __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoint* __restrict__ sorted,
                                                       const uint32_t* __restrict__ cell_start, int64_t n, int K,
@@ -133,14 +152,26 @@ __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoin
   }
   const uint32_t total = __shfl(incl, kPairLanes - 1, kPairLanes);
   const uint32_t o0 = incl - c;
-  const uint32_t staged = min(c, (uint32_t)kRowStage);
-  for (uint32_t k = 0; k < staged && o0 + k < (uint32_t)K; ++k) ids[(int64_t)i * K + o0 + k] = stage[k][threadIdx.x];
-  if (c > (uint32_t)kRowStage) {  // rare: the matches beyond the staged ones
-    uint32_t seen = 0, o = o0 + (uint32_t)kRowStage;
-    for (uint32_t q = b; q < e && o < (uint32_t)K; ++q) {
-      const LRPoint L = sorted[q];
-      if (!match(L)) continue;
-      if (++seen > (uint32_t)kRowStage) ids[(int64_t)i * K + o++] = __float_as_uint(L.v.w);
+  uint32_t* list = ids + (int64_t)i * K;
+  if (c <= (uint32_t)kRowStage) {
+    uint32_t sv[kRowStage];
+#pragma unroll
+    for (int k = 0; k < kRowStage; ++k) sv[k] = (uint32_t)k < c ? stage[k][threadIdx.x] : 0xffffffffu;
+    sort8(sv);
+#pragma unroll
+    for (int k = 0; k < kRowStage; ++k)
+      if ((uint32_t)k < c && o0 + (uint32_t)k < (uint32_t)K) list[o0 + (uint32_t)k] = sv[k];
+  } else {  // rare: more matches than staged, emitted smallest index first
+    uint32_t last = 0u;
+    for (uint32_t k = 0; k < c && o0 + k < (uint32_t)K; ++k) {
+      uint32_t next = 0xffffffffu;
+      for (uint32_t q = b; q < e; ++q) {
+        const LRPoint L = sorted[q];
+        const uint32_t j = __float_as_uint(L.v.w);
+        if ((k == 0u || j > last) && j < next && match(L)) next = j;
+      }
+      list[o0 + k] = next;
+      last = next;
     }
   }
   if (lane == 0) {
@@ -703,7 +734,7 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
     e = hipGetLastError();
   }
   if (h->p.stab_iters > 0) {
-    if (e == hipSuccess) e = launch_build_grid_tagged(h->gc, x, h->body, n, h->n_cells, h->g, st);
+    if (e == hipSuccess) e = launch_build_grid_points(h->gc, x, h->body, n, h->n_cells, h->g, st);
     if (e == hipSuccess)
       hipLaunchKernelGGL(k_pbd_pairs, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start,
                          n, K, h->cnt, h->ids, h->overflow);
@@ -722,7 +753,7 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
   // 3. solver iterations on x~
   float* ta = h->xt;
   float* tb = h->xt2;
-  if (e == hipSuccess) e = launch_build_grid_tagged(h->gc, ta, h->body, n, h->n_cells, h->g, st);
+  if (e == hipSuccess) e = launch_build_grid_points(h->gc, ta, h->body, n, h->n_cells, h->g, st);
   if (e == hipSuccess)
     hipLaunchKernelGGL(k_pbd_pairs, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start, n,
                        K, h->cnt, h->ids, h->overflow);

@@ -24,7 +24,9 @@ scene with two rigid bodies, and the drain (65,536 granular LR on 14,505
 static samples of its silo and hopper) running out through its orifice, at
 fresh and moving states.  Plus the frames of a
 multi-step call against single steps, the free fall of a rigid body in closed
-form, invariants over a long run, and edge cases."""
+form, invariants over a long run, edge cases, and the order of the pair lists
+in a deeply overlapping cluster (rows in order, indices increasing inside a
+row, a repeated step bit-identical)."""
 import itertools
 
 import numpy as np
@@ -272,6 +274,63 @@ def test_free_fall_and_invariants(LRSim):
     assert worst < 0.25 * sc.r, f"rigid bodies deform by {worst / sc.r:.3f} r"
     assert not sim.overflow()
     log(f"pbd free fall: {free} steps in closed form; rigid residual {worst / sc.r:.4f} r over 120 steps")
+    sim.close()
+
+
+def _rows_and_order_ok(cnt, ids, X, r, lo):
+    """Each list runs through the stencil rows in the kernel's order ((dz, dy)
+    from (-1, -1) on) and, inside a row, by increasing index; returns the
+    largest number of partners one particle has in one row."""
+    cs = 2.0 * float(F32(r)) * 1.0001
+    inv_cs, X = F32(1.0 / cs), np.asarray(X, F32)
+    cells = []
+    for a in (1, 2):  # y and z cell coordinates, float32 as the grid forms them
+        t = (X[a] - F32(lo[a])).astype(F32) * inv_cs
+        cells.append(np.floor(t.astype(F32)).astype(np.int64))
+    most = 0
+    for i in range(X.shape[1]):
+        lst = ids[i, :cnt[i]].astype(np.int64)
+        row = (cells[1][lst] - cells[1][i] + 1) * 3 + (cells[0][lst] - cells[0][i] + 1)
+        assert row.min(initial=0) >= 0 and row.max(initial=0) <= 8, f"particle {i}: partner outside the stencil"
+        key = row * X.shape[1] + lst
+        assert np.all(np.diff(key) > 0), f"particle {i}: list not in (row, index) order"
+        if lst.size:
+            most = max(most, int(np.bincount(row).max()))
+    return most
+
+
+def test_pair_lists_canonical_in_dense_cluster(LRSim):
+    """Overlapping granular particles (spacing 0.8 r, some rows holding more
+    partners than the kernel stages): the lists equal the oracle's pairs, run
+    through the rows in order and by index inside a row, and a step is
+    bit-identical when repeated (the grid's order inside a cell is not)."""
+    r = 0.01
+    rng = np.random.default_rng(41)
+    ax = np.arange(7) * 0.8 * r
+    g = np.stack(np.meshgrid(ax, ax, ax, indexing="ij")).reshape(3, -1) + 0.5
+    X = (g + rng.uniform(-0.05 * r, 0.05 * r, g.shape)).astype(F32)
+    n = X.shape[1]
+    body = np.full(n, -1, np.int32)
+    sim = LRSim(body, np.ones(n, F32), np.zeros((3, n), F32), r, (0, 0, 0), (1, 1, 1), max_neighbors=128)
+    V = np.zeros_like(X)
+    outs = []
+    for _ in range(2):
+        x, v = dev(X, torch), dev(V, torch)
+        outs.append((sim.debug_step(x, v), host(x), host(v)))
+    (tr, xa, va), (tr2, xb, vb) = outs
+    most = 0
+    for ph, pos in ((0, X), (1, tr["xt_pred"] if not tr["stab"] else tr["stab"][-1][1])):
+        cnt, ids = tr["pairs"][ph]
+        _check_pairs(cnt, ids, pos, body, r, f"phase {ph} pairs")
+        most = max(most, _rows_and_order_ok(cnt, ids, pos, r, (0, 0, 0)))
+        cnt2, ids2 = tr2["pairs"][ph]
+        assert np.array_equal(cnt, cnt2)
+        assert all(np.array_equal(ids[i, :cnt[i]], ids2[i, :cnt[i]]) for i in range(n))
+    assert most > 8, f"no row held more partners than the kernel stages ({most})"
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb), "a repeated step differs"
+    assert not sim.overflow()
+    log(f"pbd dense cluster: {n} particles, up to {int(tr['pairs'][1][0].max())} partners, "
+        f"up to {most} in one row")
     sim.close()
 
 
