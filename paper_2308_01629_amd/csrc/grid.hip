@@ -19,33 +19,6 @@
 namespace ups {
 namespace {
 
-__device__ __forceinline__ uint32_t cell_key(const GridConst& gc, float x, float y, float z) {
-  int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
-  int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
-  int cz = cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2]);
-  return (uint32_t)cx + (uint32_t)gc.dims[0] * ((uint32_t)cy + (uint32_t)gc.dims[1] * (uint32_t)cz);
-}
-
-// Arrival slot of key k inside its bin.  Lanes whose key equals the key of the
-// lane before them join that lane's run; the first lane of each run claims
-// the whole run with one atomic add.  Nearly sorted input (the HR reorder)
-// then costs a handful of atomics per wave instead of 64.
-__device__ __forceinline__ uint32_t claim_slot(uint32_t k, bool valid, uint32_t* counts) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t kk = valid ? k : 0xffffffffu;
-  const uint32_t prev = __shfl_up(kk, 1, 64);
-  const bool head = (lane == 0) || (prev != kk);
-  const uint64_t heads = __ballot(head);
-  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-  const int start = 63 - __clzll(heads & upto);
-  const uint64_t above = heads & ~upto;
-  const int next = above ? (__ffsll((long long)above) - 1) : 64;
-  uint32_t base = 0u;
-  if (head && valid) base = atomicAdd(&counts[kk], (uint32_t)(next - lane));
-  base = __shfl(base, start, 64);
-  return base + (uint32_t)(lane - start);
-}
-
 // An LR frame at the HR time level: frame a, or with a second frame b the
 // linear interpolation a + theta (b - a) in time, each operation rounded
 // separately (the boundary's float32 arithmetic; the key and the sorted copy
@@ -651,8 +624,8 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
 }
 
 hipError_t launch_build_grid_points(const GridConst& gc, const float* x, const int32_t* tag, int64_t n,
-                                    int64_t n_cells, const GridScratch& s, hipStream_t st) {
-  if (n > 0)
+                                    int64_t n_cells, const GridScratch& s, hipStream_t st, bool keys_ready) {
+  if (n > 0 && !keys_ready)
     hipLaunchKernelGGL(k_keys_count, dim3(blocks_for(n)), dim3(kBlock), 0, st, gc,
                        FramePair{x, x, nullptr, nullptr, 0.0f}, n, s.keys, s.slot, s.counts);
   const int n_chunks = (int)((n_cells + kScanChunk - 1) / kScanChunk);

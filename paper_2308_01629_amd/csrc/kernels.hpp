@@ -1,4 +1,5 @@
-// Host-side launchers of the library's kernels (one translation unit each).
+// Host-side launchers of the library's kernels (one translation unit each)
+// and the device helpers that several of them share.
 #pragma once
 
 #include <string>
@@ -6,6 +7,37 @@
 #include "common.hpp"
 
 namespace ups {
+
+// Key of the cell holding a position: x fastest, coordinates clamped into the
+// grid.
+__device__ __forceinline__ uint32_t cell_key(const GridConst& gc, float x, float y, float z) {
+  int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
+  int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
+  int cz = cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2]);
+  return (uint32_t)cx + (uint32_t)gc.dims[0] * ((uint32_t)cy + (uint32_t)gc.dims[1] * (uint32_t)cz);
+}
+
+// Arrival slot of key k inside its bin.  Lanes whose key equals the key of the
+// lane before them join that lane's run; the first lane of each run claims
+// the whole run with one atomic add.  Nearly sorted input (the HR reorder)
+// then costs a handful of atomics per wave instead of 64.  Every lane of the
+// wave calls it (invalid lanes with valid = false): it shuffles and votes
+// across the whole wave.
+__device__ __forceinline__ uint32_t claim_slot(uint32_t k, bool valid, uint32_t* counts) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t kk = valid ? k : 0xffffffffu;
+  const uint32_t prev = __shfl_up(kk, 1, 64);
+  const bool head = (lane == 0) || (prev != kk);
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int start = 63 - __clzll(heads & upto);
+  const uint64_t above = heads & ~upto;
+  const int next = above ? (__ffsll((long long)above) - 1) : 64;
+  uint32_t base = 0u;
+  if (head && valid) base = atomicAdd(&counts[kk], (uint32_t)(next - lane));
+  base = __shfl(base, start, 64);
+  return base + (uint32_t)(lane - start);
+}
 
 // Scratch of one grid build (device pointers, owned by a handle).
 struct GridScratch {
@@ -27,9 +59,12 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
 // A build over positions alone (x [3][n]) without the stable fix: the sorted
 // copy holds x and an int32 tag per particle (as bits) in p, the index in
 // v.w, and inside a cell its order varies from run to run.  Leaves perm and
-// tmp untouched.
+// tmp untouched.  keys_ready: a kernel before it on the stream has already
+// written s.keys and s.slot and counted into s.counts (claim_slot on the
+// cell_key of these same positions), so the build starts at the scan.
 hipError_t launch_build_grid_points(const GridConst& gc, const float* x, const int32_t* tag, int64_t n,
-                                    int64_t n_cells, const GridScratch& s, hipStream_t st);
+                                    int64_t n_cells, const GridScratch& s, hipStream_t st,
+                                    bool keys_ready = false);
 // The same build of the LR state between two frames: x0 + theta (x1 - x0)
 // (and v alike), each float32 operation rounded separately, fused into the
 // keys and the sorted copy.

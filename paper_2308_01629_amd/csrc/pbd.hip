@@ -13,7 +13,8 @@
 // uniform grid of cells at least 2r wide, counting sort).
 //
 // Per step: k_pbd_predict, grid + k_pbd_pairs on the start positions,
-// stab_iters x k_pbd_stab, grid + k_pbd_pairs on the predicted positions,
+// stab_iters x k_pbd_stab, grid + k_pbd_pairs on the predicted positions
+// (each grid build's keys and counts come from the kernel before it),
 // solve_iters x (k_pbd_shape per rigid body, k_pbd_solve), k_pbd_finish.
 #include <algorithm>
 #include <cmath>
@@ -43,22 +44,44 @@ struct PbdConst {
 };
 
 // 1. v += dt g (dynamic), x~ = x + dt v; scaled inverse mass w* = w exp(h).
+// KEYS 1 / 2 also start the next grid build: the cell keys of x / of the new
+// x~, counted into the build's bins (claim_slot), so the build begins at its
+// scan.
+enum { kKeysNone = 0, kKeysOfX = 1, kKeysOfXt = 2 };
+
+template <int KEYS>
 __global__ __launch_bounds__(kBlock) void k_pbd_predict(PbdConst pc, int64_t n, const float* __restrict__ x,
                                                         float* __restrict__ v, float* __restrict__ xt,
                                                         const int32_t* __restrict__ body,
-                                                        const float* __restrict__ inv_m, float* __restrict__ w) {
+                                                        const float* __restrict__ inv_m, float* __restrict__ w,
+                                                        GridConst gc, uint32_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ slot, uint32_t* __restrict__ counts) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const bool stat = body[i] == kStatic;
+  const bool valid = i < n;
+  float P[3] = {0.f, 0.f, 0.f}, T[3] = {0.f, 0.f, 0.f};
+  if (valid) {
+    const bool stat = body[i] == kStatic;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float va = stat ? 0.0f : fmaf(pc.dt, pc.g[a], v[a * n + i]);
-    v[a * n + i] = va;
-    xt[a * n + i] = fmaf(pc.dt, va, x[a * n + i]);
+    for (int a = 0; a < 3; ++a) {
+      P[a] = x[a * n + i];
+      const float va = stat ? 0.0f : fmaf(pc.dt, pc.g[a], v[a * n + i]);
+      v[a * n + i] = va;
+      T[a] = fmaf(pc.dt, va, P[a]);
+      xt[a * n + i] = T[a];
+    }
+    float wi = stat ? 0.0f : inv_m[i];
+    if (pc.mass_scaling) wi *= expf(P[1] - pc.ground_y);
+    w[i] = wi;
   }
-  float wi = stat ? 0.0f : inv_m[i];
-  if (pc.mass_scaling) wi *= expf(x[n + i] - pc.ground_y);
-  w[i] = wi;
+  if (KEYS != kKeysNone) {
+    const float* K3 = KEYS == kKeysOfX ? P : T;
+    const uint32_t k = valid ? cell_key(gc, K3[0], K3[1], K3[2]) : 0u;
+    const uint32_t sl = claim_slot(k, valid, counts);
+    if (valid) {
+      keys[i] = k;
+      slot[i] = sl;
+    }
+  }
 }
 
 // Lanes per particle: the pair search gives each of the 9 stencil rows (dy,
@@ -215,43 +238,62 @@ __device__ __forceinline__ void load3(const float* a, int64_t n, int64_t i, floa
 
 // 2. One stabilization iteration on the start positions: the averaged
 // contact displacement goes to x (xs_out) and to x~ (in place, by the
-// particle's first lane).
+// particle's first lane).  KEYS: the last iteration also starts the solver
+// phase's grid build on the new x~ (as k_pbd_predict does).
+template <bool KEYS>
 __global__ __launch_bounds__(kBlock) void k_pbd_stab(PbdConst pc, int64_t n, const float* __restrict__ xs_in,
                                                      float* __restrict__ xs_out, float* __restrict__ xt,
                                                      const float* __restrict__ w, int K,
                                                      const uint32_t* __restrict__ cnt,
-                                                     const uint32_t* __restrict__ ids) {
+                                                     const uint32_t* __restrict__ ids, GridConst gc,
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ slot,
+                                                     uint32_t* __restrict__ counts) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = g / kIterLanes;
   const int l = (int)(g % kIterLanes);
-  if (i >= n) return;  // the lanes of a particle leave together
-  float Pi[3];
-  load3(xs_in, n, i, Pi);
-  const float wi = w[i];
+  if (!KEYS && i >= n) return;  // the lanes of a particle leave together
+  const bool valid = i < n;     // with KEYS every lane of the wave reaches claim_slot
+  float Pi[3] = {0.f, 0.f, 0.f};
   float acc[3] = {0.f, 0.f, 0.f};
   float na = 0.0f;
-  const uint32_t c = cnt[i];
-  for (uint32_t k = (uint32_t)l; k < c; k += kIterLanes) {
-    const int64_t j = ids[i * K + k];
-    float Pj[3];
-    load3(xs_in, n, j, Pj);
-    const float wj = w[j];
-    PairGeo gg;
-    if (!contact_geo(Pi, Pj, wi, wj, pc.r2, gg)) continue;
-    const float mi = wi / (wi + wj);
+  if (valid) {
+    load3(xs_in, n, i, Pi);
+    const float wi = w[i];
+    const uint32_t c = cnt[i];
+    for (uint32_t k = (uint32_t)l; k < c; k += kIterLanes) {
+      const int64_t j = ids[i * K + k];
+      float Pj[3];
+      load3(xs_in, n, j, Pj);
+      const float wj = w[j];
+      PairGeo gg;
+      if (!contact_geo(Pi, Pj, wi, wj, pc.r2, gg)) continue;
+      const float mi = wi / (wi + wj);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) acc[a] -= mi * gg.s * gg.xij[a];
-    na += 1.0f;
+      for (int a = 0; a < 3; ++a) acc[a] -= mi * gg.s * gg.xij[a];
+      na += 1.0f;
+    }
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) acc[a] = group_sum(acc[a]);
   na = group_sum(na);
-  if (l != 0) return;
+  float T[3] = {0.f, 0.f, 0.f};
+  if (valid && l == 0) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float u = na > 0.0f ? acc[a] / na : 0.0f;
-    xs_out[a * n + i] = Pi[a] + u;
-    xt[a * n + i] += u;
+    for (int a = 0; a < 3; ++a) {
+      const float u = na > 0.0f ? acc[a] / na : 0.0f;
+      xs_out[a * n + i] = Pi[a] + u;
+      T[a] = xt[a * n + i] + u;
+      xt[a * n + i] = T[a];
+    }
+  }
+  if (KEYS) {
+    const bool own = valid && l == 0;
+    const uint32_t k = own ? cell_key(gc, T[0], T[1], T[2]) : 0u;
+    const uint32_t sl = claim_slot(k, own, counts);
+    if (own) {
+      keys[i] = k;
+      slot[i] = sl;
+    }
   }
 }
 
@@ -721,7 +763,14 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
     e = copy_async(rec, src, m, st);
     rec += m;
   };
-  hipLaunchKernelGGL(k_pbd_predict, dim3(nb), dim3(kBlock), 0, st, pc, n, x, v, h->xt, h->body, h->inv_m, h->w);
+  // the prediction starts the first grid build: the stabilization's on x, or
+  // without stabilization the solver's on x~
+  if (h->p.stab_iters > 0)
+    hipLaunchKernelGGL(k_pbd_predict<kKeysOfX>, dim3(nb), dim3(kBlock), 0, st, pc, n, x, v, h->xt, h->body,
+                       h->inv_m, h->w, h->gc, h->g.keys, h->g.slot, h->g.counts);
+  else
+    hipLaunchKernelGGL(k_pbd_predict<kKeysOfXt>, dim3(nb), dim3(kBlock), 0, st, pc, n, x, v, h->xt, h->body,
+                       h->inv_m, h->w, h->gc, h->g.keys, h->g.slot, h->g.counts);
   e = hipGetLastError();
   record(h->w, n);
   record(v, 3 * n);
@@ -734,15 +783,20 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
     e = hipGetLastError();
   }
   if (h->p.stab_iters > 0) {
-    if (e == hipSuccess) e = launch_build_grid_points(h->gc, x, h->body, n, h->n_cells, h->g, st);
+    if (e == hipSuccess) e = launch_build_grid_points(h->gc, x, h->body, n, h->n_cells, h->g, st, true);
     if (e == hipSuccess)
       hipLaunchKernelGGL(k_pbd_pairs, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start,
                          n, K, h->cnt, h->ids, h->overflow);
     if (e == hipSuccess && tr != nullptr) e = copy_pairs(h, tr, 0, st);
     float* out = h->xs;
     for (int it = 0; it < h->p.stab_iters && e == hipSuccess; ++it) {
-      hipLaunchKernelGGL(k_pbd_stab, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, x0, out, h->xt, h->w, K, h->cnt,
-                         h->ids);
+      // the last iteration starts the solver phase's grid build on its x~
+      if (it == h->p.stab_iters - 1)
+        hipLaunchKernelGGL(k_pbd_stab<true>, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, x0, out, h->xt, h->w, K,
+                           h->cnt, h->ids, h->gc, h->g.keys, h->g.slot, h->g.counts);
+      else
+        hipLaunchKernelGGL(k_pbd_stab<false>, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, x0, out, h->xt, h->w, K,
+                           h->cnt, h->ids, h->gc, h->g.keys, h->g.slot, h->g.counts);
       e = hipGetLastError();
       x0 = out;
       out = out == h->xs ? h->xs2 : h->xs;
@@ -753,7 +807,7 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
   // 3. solver iterations on x~
   float* ta = h->xt;
   float* tb = h->xt2;
-  if (e == hipSuccess) e = launch_build_grid_points(h->gc, ta, h->body, n, h->n_cells, h->g, st);
+  if (e == hipSuccess) e = launch_build_grid_points(h->gc, ta, h->body, n, h->n_cells, h->g, st, true);
   if (e == hipSuccess)
     hipLaunchKernelGGL(k_pbd_pairs, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start, n,
                        K, h->cnt, h->ids, h->overflow);
