@@ -272,7 +272,10 @@ int upsample_run_multirate(upsample_handle h, const float* lr_x, const float* lr
  * the particle's old index.  The order inside a sub-cell is unspecified.
  * Later steps compute the same per-particle results in any order, up to
  * float32 rounding (the weights of a compact wave are taken relative to its
- * box centre).
+ * box centre).  In the Hilbert mode the first reorder (and the first after
+ * the tuning changes sort_sub) also ranks the grid's fine cells along the
+ * curve on the stream, into a table the handle allocates then
+ * (4 B per fine cell) and keeps: later reorders count one bin per fine cell.
  */
 int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, float* hr_x_out,
                      float* hr_v_out, int64_t n_hr, int32_t* perm_out, void* stream);

@@ -408,6 +408,24 @@ struct SceneHrKey {
   }
 };
 
+// The reorder key of HR particle i of one scene by rank table: the Hilbert
+// rank of its fine cell among the grid's fine cells (the order of mode 2 on
+// F bins instead of a padded 2^(3b) cube).
+struct RankHrKey {
+  GridConst gc;
+  const float* x;
+  int64_t ld;
+  int sub;
+  int fdims[3];
+  const uint32_t* rank;
+  __device__ __forceinline__ uint32_t operator()(int64_t i) const {
+    const uint32_t fx = fine_coord(x[i], gc.lo[0], gc.inv_cs, gc.dims[0], sub);
+    const uint32_t fy = fine_coord(x[ld + i], gc.lo[1], gc.inv_cs, gc.dims[1], sub);
+    const uint32_t fz = fine_coord(x[2 * ld + i], gc.lo[2], gc.inv_cs, gc.dims[2], sub);
+    return rank[fx + (uint32_t)fdims[0] * (fy + (uint32_t)fdims[1] * fz)];
+  }
+};
+
 // The key of column i of a batch whose scenes own consecutive column ranges
 // (start[s] .. start[s + 1]): the scene's first bin plus the Hilbert rank of
 // the particle's fine cell among all fine cells of that scene's grid, so the
@@ -698,17 +716,26 @@ hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& 
 
 hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
                           float* out_v, int64_t n_hr, int sub, int mode, const HRSortScratch& s,
-                          int32_t* perm_out, hipStream_t st, int64_t ld, int32_t perm_base) {
+                          int32_t* perm_out, hipStream_t st, int64_t ld, int32_t perm_base,
+                          const uint32_t* rank) {
   if (n_hr == 0) return hipSuccess;
   if (ld < 0) ld = n_hr;
   // a strided state is sorted in place only (through the scratch copy)
   if (ld != n_hr && (out_x != hr_x || out_v != hr_v)) return hipErrorInvalidValue;
   int bits[3];
   for (int a = 0; a < 3; ++a) bits[a] = sort_bits((int64_t)gc.dims[a] * sub);
-  const int64_t n_bins = sort_bins(gc.dims, sub, mode);
-  const SceneHrKey kf{gc, hr_x, ld, sub, mode, bits[0], bits[1], bits[2]};
-  hipLaunchKernelGGL(k_hr_keys_count<SceneHrKey>, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)),
-                     dim3(kBlock), 0, st, kf, n_hr, s.keys, s.slot, s.src, s.counts);
+  int64_t n_bins = sort_bins(gc.dims, sub, mode);
+  const unsigned nb = (unsigned)((n_hr + kHrSpan - 1) / kHrSpan);
+  if (mode == 2 && rank != nullptr) {
+    const RankHrKey kf{gc, hr_x, ld, sub, {gc.dims[0] * sub, gc.dims[1] * sub, gc.dims[2] * sub}, rank};
+    n_bins = (int64_t)kf.fdims[0] * kf.fdims[1] * kf.fdims[2];
+    hipLaunchKernelGGL(k_hr_keys_count<RankHrKey>, dim3(nb), dim3(kBlock), 0, st, kf, n_hr, s.keys, s.slot, s.src,
+                       s.counts);
+  } else {
+    const SceneHrKey kf{gc, hr_x, ld, sub, mode, bits[0], bits[1], bits[2]};
+    hipLaunchKernelGGL(k_hr_keys_count<SceneHrKey>, dim3(nb), dim3(kBlock), 0, st, kf, n_hr, s.keys, s.slot, s.src,
+                       s.counts);
+  }
   hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
   if (e != hipSuccess) return e;
   const bool in_place = out_x == hr_x || out_v == hr_v;

@@ -162,10 +162,13 @@ inline int64_t sort_bins(const int dims[3], int sub, int mode) {
 // out_x / out_v may alias hr_x / hr_v (then the permuted copy goes through scratch).
 // ld: the stride between the components of hr_x / hr_v (n_hr if negative); a
 // strided state is sorted in place, and perm_out receives perm_base + the old
-// column.
+// column.  rank (mode 2 only, else ignored): the Hilbert ranks of the grid's
+// fine cells at this sub (launch_hilbert_ranks), which sort the same order on
+// one bin per fine cell.
 hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
                           float* out_v, int64_t n_hr, int sub, int mode, const HRSortScratch& s,
-                          int32_t* perm_out, hipStream_t st, int64_t ld = -1, int32_t perm_base = 0);
+                          int32_t* perm_out, hipStream_t st, int64_t ld = -1, int32_t perm_base = 0,
+                          const uint32_t* rank = nullptr);
 
 // One scene of a batched HR reorder: its grid, sub-cells per axis, fine grid
 // dims (dims * sub) and first bin (also its offset in the rank table).

@@ -43,6 +43,9 @@ struct upsample_handle_s {
   bool grid_valid;
   bool counts_dirty;     // an interrupted build may have left counts non-zero
   bool hr_counts_dirty;  // same for the HR sort bins
+  uint32_t* hr_rank;     // Hilbert ranks of the fine cells at hr_rank_sub (reorder mode 2), built at first use
+  int64_t hr_rank_cap;
+  int hr_rank_sub;       // 0: not built
   bool g_sorted_dirty;   // a failed backward may have left g_sorted non-zero
   int64_t grid_n_lr;
   bool has_rigid;
@@ -71,6 +74,34 @@ int hip_fail(upsample_handle h, hipError_t e, const char* where) {
 }
 
 bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// The Hilbert ranks of the grid's fine cells at the tuned sub-cell count, for
+// a reorder in mode 2: built on the stream at the first such reorder and
+// again after the tuning changes the count (the HR bins serve as the
+// marking cube and are left zero).  Other modes need none.
+hipError_t ensure_hr_ranks(upsample_handle h, hipStream_t st) {
+  if (h->tune.sort_mode != 2 || h->hr_rank_sub == h->tune.sort_sub) return hipSuccess;
+  const int sub = h->tune.sort_sub;
+  const int fd[3] = {h->gi.dims[0] * sub, h->gi.dims[1] * sub, h->gi.dims[2] * sub};
+  const int64_t F = (int64_t)fd[0] * fd[1] * fd[2];
+  hipError_t e = hipSuccess;
+  if (F > h->hr_rank_cap) {
+    if (h->hr_rank != nullptr) e = hipFree(h->hr_rank);
+    h->hr_rank = nullptr;
+    h->hr_rank_cap = 0;
+    if (e == hipSuccess) e = hipMalloc((void**)&h->hr_rank, sizeof(uint32_t) * (size_t)F);
+    if (e != hipSuccess) return e;
+    h->hr_rank_cap = F;
+  }
+  h->hr_rank_sub = 0;
+  e = launch_hilbert_ranks(fd, h->hr_rank, h->hs.counts, h->hs.local, h->hs.chunk_sum, st);
+  if (e != hipSuccess) {
+    h->hr_counts_dirty = true;
+    return e;
+  }
+  h->hr_rank_sub = sub;
+  return hipSuccess;
+}
 
 // The grid definition (see upsample_grid_info in the header).
 int compute_grid(const upsample_params* p, upsample_grid_info* gi, std::string* why) {
@@ -162,7 +193,7 @@ void free_scratch(upsample_handle h) {
   void* ptrs[] = {h->g.keys, h->g.slot, h->g.tmp, h->g.perm, h->g.counts, h->g.local, h->g.chunk_sum,
                   h->g.cell_start, h->g.lr_sorted, h->hs.keys, h->hs.slot, h->hs.src, h->hs.x,
                   h->hs.v, h->hs.perm, h->hs.counts, h->hs.local, h->hs.chunk_sum,
-                  h->finite_flag, h->run_perm, h->wall_mask, h->g_sorted, h->det_coef};
+                  h->finite_flag, h->run_perm, h->wall_mask, h->g_sorted, h->det_coef, h->hr_rank};
   for (void* q : ptrs)
     if (q != nullptr) (void)hipFree(q);
   for (const GridScratch& g : h->run_g) {
@@ -892,8 +923,10 @@ static int run_impl(upsample_handle h, const float* lr_x, const float* lr_v, con
         e = timing_close(h, st);  // the reorder stays outside the timed stretch
         if (e != hipSuccess) break;
         int32_t* p = perm_io != nullptr ? h->run_perm : nullptr;
-        e = launch_sort_hr(gc, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, h->tune.sort_sub, h->tune.sort_mode, h->hs, p,
-                           st);
+        e = ensure_hr_ranks(h, st);
+        if (e == hipSuccess)
+          e = launch_sort_hr(gc, hr_x, hr_v, h->hs.x, h->hs.v, n_hr, h->tune.sort_sub, h->tune.sort_mode, h->hs,
+                             p, st, -1, 0, h->hr_rank);
         if (e == hipSuccess && p != nullptr) e = launch_compose_perm(perm_io, p, n_hr, h->hs.slot, st);
         if (e != hipSuccess) {
           h->hr_counts_dirty = true;
@@ -953,8 +986,10 @@ int upsample_sort_hr(upsample_handle h, const float* hr_x, const float* hr_v, fl
     if (e != hipSuccess) return hip_fail(h, e, "sort_hr");
     h->hr_counts_dirty = false;
   }
-  hipError_t e = launch_sort_hr(grid_const(h), hr_x, hr_v, hr_x_out, hr_v_out, n_hr, h->tune.sort_sub,
-                                h->tune.sort_mode, h->hs, perm_out, st);
+  hipError_t e = ensure_hr_ranks(h, st);
+  if (e == hipSuccess)
+    e = launch_sort_hr(grid_const(h), hr_x, hr_v, hr_x_out, hr_v_out, n_hr, h->tune.sort_sub, h->tune.sort_mode,
+                       h->hs, perm_out, st, -1, 0, h->hr_rank);
   if (e != hipSuccess) {
     h->hr_counts_dirty = true;
     return hip_fail(h, e, "sort_hr");
