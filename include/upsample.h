@@ -471,7 +471,7 @@ int upsample_step_noalloc(const upsample_params* p,
  * *n_out (host) receives their number; when it exceeds max_out the first
  * max_out are written and UPSAMPLE_ERR_CAPACITY is returned.  A set-up routine,
  * not a step: it allocates temporary device memory (about 36 B per cell and
- * 48 B per candidate) and synchronises the stream.  Errors: INVALID_ARG (bad
+ * 40 B per candidate) and synchronises the stream.  Errors: INVALID_ARG (bad
  * r, box or pointers), GRID_TOO_LARGE (2^31 cells or more, or an axis of 2^20),
  * CAPACITY, NO_DEVICE, OOM, HIP.
  */

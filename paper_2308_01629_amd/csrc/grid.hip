@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_points(const uint32_t* __res
     const uint32_t pos = cell_offset(local, csum, keys[t]) + slot[t];
     if (pos < (uint64_t)n) {  // always true when counts started at zero
       LRPoint o;
-      o.p = make_float4(x[t], x[n + t], x[2 * n + t], __int_as_float(tag[t]));
+      o.p = make_float4(x[t], x[n + t], x[2 * n + t], tag != nullptr ? __int_as_float(tag[t]) : 0.0f);
       o.v = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float((uint32_t)t));
       out[pos] = o;
     }

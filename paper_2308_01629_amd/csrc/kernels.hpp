@@ -57,8 +57,9 @@ hipError_t launch_build_grid(const GridConst& gc, const float* lr_x, const float
                              const uint8_t* lr_rigid, int64_t n_lr, int64_t n_cells,
                              const GridScratch& s, hipStream_t st);
 // A build over positions alone (x [3][n]) without the stable fix: the sorted
-// copy holds x and an int32 tag per particle (as bits) in p, the index in
-// v.w, and inside a cell its order varies from run to run.  Leaves perm and
+// copy holds x and an int32 tag per particle (as bits; 0 without a tag
+// array) in p, the index in v.w, and inside a cell its order varies from
+// run to run.  Leaves perm and
 // tmp untouched.  keys_ready: a kernel before it on the stream has already
 // written s.keys and s.slot and counted into s.counts (claim_slot on the
 // cell_key of these same positions), so the build starts at the scan.

@@ -18,10 +18,11 @@
 // alone (none in the first phase, 62 on average), nearest first so that a
 // candidate that conflicts is rejected early.
 //
-// Candidates go through the LR grid build (keys, stable counting sort by
-// cell: a cell's candidates stay in input order), so the whole routine is
-// the grid machinery plus 27 launches of k_sample_phase and a compaction of
-// the per-cell samples in key order.
+// Candidates go through the LR grid build over positions (keys, counting
+// sort by cell; the order inside a cell is left as the slot claims give it,
+// and each candidate carries its input index), so the whole routine is the
+// grid machinery plus 27 launches of k_sample_phase and a compaction of the
+// per-cell samples in key order.
 #include <cmath>
 #include <string>
 
@@ -43,9 +44,11 @@ struct PhaseOffsets {
   uint32_t off[124];
 };
 
-// One colour phase: cells (a + 3 i, b + 3 j, c + 3 k).  A cell tries its
-// candidates in order and keeps the first whose separately rounded squared
-// distance to every sample of the listed neighbour cells is >= d2 = fl(4 r^2).
+// One colour phase: cells (a + 3 i, b + 3 j, c + 3 k).  A cell keeps, of its
+// candidates whose separately rounded squared distance to every sample of
+// the listed neighbour cells is >= d2 = fl(4 r^2), the one first in input
+// order (the smallest index: whether a candidate fits does not depend on the
+// cell's other candidates, so this is the sequential visit's choice).
 __global__ __launch_bounds__(kBlock) void k_sample_phase(GridConst gc, const uint32_t* __restrict__ cell_start,
                                                          const LRPoint* __restrict__ cand, float4* __restrict__ smp,
                                                          int a, int b, int c, int ni, int nj, int nk, float d2,
@@ -57,8 +60,13 @@ __global__ __launch_bounds__(kBlock) void k_sample_phase(GridConst gc, const uin
   const int Gx = gc.dims[0], Gy = gc.dims[1], Gz = gc.dims[2];
   const uint32_t key = (uint32_t)cx + (uint32_t)Gx * ((uint32_t)cy + (uint32_t)Gy * (uint32_t)cz);
   const uint32_t e = cell_start[key + 1u];
+  uint32_t best = 0xffffffffu;
+  float4 pick = make_float4(0.f, 0.f, 0.f, 0.f);
   for (uint32_t q = cell_start[key]; q < e; ++q) {
-    const float4 P = cand[q].p;
+    const LRPoint C = cand[q];
+    const uint32_t idx = __float_as_uint(C.v.w);
+    if (idx >= best) continue;  // an earlier candidate already fits
+    const float4 P = C.p;
     bool ok = true;
     for (int o = 0; o < po.n; ++o) {
       const uint32_t w = po.off[o];
@@ -71,10 +79,11 @@ __global__ __launch_bounds__(kBlock) void k_sample_phase(GridConst gc, const uin
       }
     }
     if (ok) {
-      smp[key] = make_float4(P.x, P.y, P.z, 1.0f);
-      return;
+      best = idx;
+      pick = make_float4(P.x, P.y, P.z, 1.0f);
     }
   }
+  if (best != 0xffffffffu) smp[key] = pick;
 }
 
 // The neighbour offsets of phase (a, b, c) whose cells have an earlier
@@ -167,8 +176,6 @@ extern "C" int upsample_sample_volume(const float* cand, int64_t n_cand, float r
   if (e == hipSuccess) e = alloc(&(ptr), (n));
   ALLOC(g.keys, n_cand)
   ALLOC(g.slot, n_cand)
-  ALLOC(g.tmp, n_cand)
-  ALLOC(g.perm, n_cand)
   ALLOC(g.counts, n_cells)
   ALLOC(g.local, n_cells)
   ALLOC(g.chunk_sum, n_chunks + 1)
@@ -180,7 +187,7 @@ extern "C" int upsample_sample_volume(const float* cand, int64_t n_cand, float r
   ALLOC(csum, n_chunks + 1)
 #undef ALLOC
   if (e == hipSuccess) e = hipMemsetAsync(g.counts, 0, sizeof(uint32_t) * (size_t)n_cells, st);
-  if (e == hipSuccess) e = launch_build_grid(gc, cand, cand, nullptr, n_cand, n_cells, g, st);
+  if (e == hipSuccess) e = launch_build_grid_points(gc, cand, nullptr, n_cand, n_cells, g, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_zero_f4, dim3(blocks_of(n_cells)), dim3(kBlock), 0, st, smp, n_cells);
     e = hipGetLastError();
