@@ -86,11 +86,14 @@ __global__ __launch_bounds__(kBlock) void k_pbd_predict(PbdConst pc, int64_t n, 
 
 // Lanes per particle: the pair search gives each of the 9 stencil rows (dy,
 // dz in {-1, 0, 1}) its own lane; the iterations split a particle's pair
-// list over kIterLanes lanes and sum them by a fixed butterfly.  Small LR
-// systems (tens of thousands of particles) would otherwise leave the chip
-// with about one wave per CU and every wave waiting on memory.
+// list over L lanes (8 up to kIterLanes8Max particles, 4 above) and sum them
+// by a fixed butterfly.  Small LR systems (tens of thousands of particles)
+// would otherwise leave the chip with about one wave per CU and every wave
+// waiting on memory; with 8 lanes a system of kIterLanes8Max particles
+// still fits about 8 waves per SIMD in one round.
 constexpr int kPairLanes = 16;
-constexpr int kIterLanes = 4;
+constexpr int64_t kIterLanes8Max = 65536;
+inline int iter_lanes(int64_t n) { return n <= kIterLanes8Max ? 8 : 4; }
 
 // Contact list of each particle: the other particles closer than 2r
 // (squared distance rounded as in the upsampling's membership predicate,
@@ -203,10 +206,11 @@ __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoin
   }
 }
 
-// Sum of a float over the kIterLanes lanes of a particle, in a fixed order.
+// Sum of a float over the L lanes of a particle, in a fixed order.
+template <int L>
 __device__ __forceinline__ float group_sum(float a) {
 #pragma unroll
-  for (int off = kIterLanes / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kIterLanes);
+  for (int off = L / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, L);
   return a;
 }
 
@@ -240,7 +244,7 @@ __device__ __forceinline__ void load3(const float* a, int64_t n, int64_t i, floa
 // contact displacement goes to x (xs_out) and to x~ (in place, by the
 // particle's first lane).  KEYS: the last iteration also starts the solver
 // phase's grid build on the new x~ (as k_pbd_predict does).
-template <bool KEYS>
+template <bool KEYS, int L>
 __global__ __launch_bounds__(kBlock) void k_pbd_stab(PbdConst pc, int64_t n, const float* __restrict__ xs_in,
                                                      float* __restrict__ xs_out, float* __restrict__ xt,
                                                      const float* __restrict__ w, int K,
@@ -249,8 +253,8 @@ __global__ __launch_bounds__(kBlock) void k_pbd_stab(PbdConst pc, int64_t n, con
                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ slot,
                                                      uint32_t* __restrict__ counts) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t i = g / kIterLanes;
-  const int l = (int)(g % kIterLanes);
+  const int64_t i = g / L;
+  const int l = (int)(g % L);
   if (!KEYS && i >= n) return;  // the lanes of a particle leave together
   const bool valid = i < n;     // with KEYS every lane of the wave reaches claim_slot
   float Pi[3] = {0.f, 0.f, 0.f};
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_pbd_stab(PbdConst pc, int64_t n, con
     load3(xs_in, n, i, Pi);
     const float wi = w[i];
     const uint32_t c = cnt[i];
-    for (uint32_t k = (uint32_t)l; k < c; k += kIterLanes) {
+    for (uint32_t k = (uint32_t)l; k < c; k += L) {
       const int64_t j = ids[i * K + k];
       float Pj[3];
       load3(xs_in, n, j, Pj);
@@ -274,8 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_pbd_stab(PbdConst pc, int64_t n, con
     }
   }
 #pragma unroll
-  for (int a = 0; a < 3; ++a) acc[a] = group_sum(acc[a]);
-  na = group_sum(na);
+  for (int a = 0; a < 3; ++a) acc[a] = group_sum<L>(acc[a]);
+  na = group_sum<L>(na);
   float T[3] = {0.f, 0.f, 0.f};
   if (valid && l == 0) {
 #pragma unroll
@@ -535,7 +539,7 @@ struct FinishArgs {
   float* fv;
 };
 
-template <bool FINISH>
+template <bool FINISH, int L>
 __global__ __launch_bounds__(kBlock) void k_pbd_solve(PbdConst pc, int64_t n, const float* __restrict__ xt_in,
                                                       float* __restrict__ xt_out, const float* __restrict__ x0,
                                                       const float* __restrict__ w, int K,
@@ -545,8 +549,8 @@ __global__ __launch_bounds__(kBlock) void k_pbd_solve(PbdConst pc, int64_t n, co
                                                       const float* __restrict__ rest, const float* __restrict__ cr,
                                                       FinishArgs fin) {
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t i = g / kIterLanes;
-  const int l = (int)(g % kIterLanes);
+  const int64_t i = g / L;
+  const int l = (int)(g % L);
   if (i >= n) return;  // the lanes of a particle leave together
   float Pi[3], X0i[3];
   load3(xt_in, n, i, Pi);
@@ -555,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_pbd_solve(PbdConst pc, int64_t n, co
   float acc[3] = {0.f, 0.f, 0.f};
   float na = 0.0f;
   const uint32_t c = cnt[i];
-  for (uint32_t k = (uint32_t)l; k < c; k += kIterLanes) {
+  for (uint32_t k = (uint32_t)l; k < c; k += L) {
     const int64_t j = ids[i * K + k];
     float Pj[3], X0j[3];
     load3(xt_in, n, j, Pj);
@@ -583,8 +587,8 @@ __global__ __launch_bounds__(kBlock) void k_pbd_solve(PbdConst pc, int64_t n, co
     na += 1.0f;
   }
 #pragma unroll
-  for (int a = 0; a < 3; ++a) acc[a] = group_sum(acc[a]);
-  na = group_sum(na);
+  for (int a = 0; a < 3; ++a) acc[a] = group_sum<L>(acc[a]);
+  na = group_sum<L>(na);
   if (l != 0) return;
   const int bi = body[i];
   if (bi >= 0) {
@@ -754,7 +758,8 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
   const PbdConst pc = pbd_const(h->p);
   const unsigned nb = nblocks(n);
   const unsigned nb_pairs = nblocks(n * kPairLanes);
-  const unsigned nb_iter = nblocks(n * kIterLanes);
+  const bool lanes8 = iter_lanes(n) == 8;
+  const unsigned nb_iter = nblocks(n * iter_lanes(n));
   const int K = h->K;
   float* rec = tr != nullptr ? tr->base : nullptr;
   hipError_t e = hipSuccess;
@@ -791,12 +796,11 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
     float* out = h->xs;
     for (int it = 0; it < h->p.stab_iters && e == hipSuccess; ++it) {
       // the last iteration starts the solver phase's grid build on its x~
-      if (it == h->p.stab_iters - 1)
-        hipLaunchKernelGGL(k_pbd_stab<true>, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, x0, out, h->xt, h->w, K,
-                           h->cnt, h->ids, h->gc, h->g.keys, h->g.slot, h->g.counts);
-      else
-        hipLaunchKernelGGL(k_pbd_stab<false>, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, x0, out, h->xt, h->w, K,
-                           h->cnt, h->ids, h->gc, h->g.keys, h->g.slot, h->g.counts);
+      const bool keys = it == h->p.stab_iters - 1;
+      auto kern = keys ? (lanes8 ? k_pbd_stab<true, 8> : k_pbd_stab<true, 4>)
+                       : (lanes8 ? k_pbd_stab<false, 8> : k_pbd_stab<false, 4>);
+      hipLaunchKernelGGL(kern, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, x0, out, h->xt, h->w, K, h->cnt, h->ids,
+                         h->gc, h->g.keys, h->g.slot, h->g.counts);
       e = hipGetLastError();
       x0 = out;
       out = out == h->xs ? h->xs2 : h->xs;
@@ -818,12 +822,11 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
     if (h->n_bodies > 0)
       hipLaunchKernelGGL(k_pbd_shape, dim3((unsigned)h->n_bodies), dim3(kShapeThreads), 0, st, n, ta, h->members,
                          h->body_ptr, h->rest, h->osum, h->cr);
-    if (fuse && it == h->p.solve_iters - 1)
-      hipLaunchKernelGGL(k_pbd_solve<true>, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, ta, tb, x0, h->w, K, h->cnt,
-                         h->ids, h->body, h->rest, h->cr, fin);
-    else
-      hipLaunchKernelGGL(k_pbd_solve<false>, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, ta, tb, x0, h->w, K,
-                         h->cnt, h->ids, h->body, h->rest, h->cr, fin);
+    const bool last = fuse && it == h->p.solve_iters - 1;
+    auto kern = last ? (lanes8 ? k_pbd_solve<true, 8> : k_pbd_solve<true, 4>)
+                     : (lanes8 ? k_pbd_solve<false, 8> : k_pbd_solve<false, 4>);
+    hipLaunchKernelGGL(kern, dim3(nb_iter), dim3(kBlock), 0, st, pc, n, ta, tb, x0, h->w, K, h->cnt, h->ids,
+                       h->body, h->rest, h->cr, fin);
     e = hipGetLastError();
     float* t = ta;
     ta = tb;
