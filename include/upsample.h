@@ -575,7 +575,8 @@ int upsample_batch_info(upsample_batch b, int64_t* out);
  * cells: correct, only slower); the pair predicate is the float32 squared
  * distance (each operation rounded) against fl32(4 r^2).  Each particle keeps
  * at most max_neighbors pairs per phase; a longer list sets a sticky overflow
- * flag read by upsample_pbd_status (the extra pairs are dropped).
+ * flag read by upsample_pbd_status (the extra pairs are dropped, which ones
+ * unspecified).
  */
 #define UPSAMPLE_PBD_GRANULAR (-1)
 #define UPSAMPLE_PBD_STATIC   (-2)
