@@ -276,16 +276,27 @@ __device__ __forceinline__ uint32_t xcd_contiguous_block() {
   const uint32_t x = p % kXcdCount, base = nb / kXcdCount, rem = nb % kXcdCount;
   return x * base + min(x, rem) + p / kXcdCount;
 }
+// SCAN_TOTALS: chunk_sum holds the chunks' raw totals (n_chunks <= kBlock),
+// and every block scans them in LDS itself (no one-block launch over them).
+template <bool SCAN_TOTALS>
 __global__ __launch_bounds__(kBlock) void k_hr_scatter(const uint32_t* __restrict__ keys,
                                                        const uint32_t* __restrict__ slot,
                                                        const uint32_t* __restrict__ src, int64_t n,
                                                        const uint32_t* __restrict__ local,
-                                                       const uint32_t* __restrict__ chunk_sum,
+                                                       const uint32_t* __restrict__ chunk_sum, int n_chunks,
                                                        const float* __restrict__ x,
                                                        const float* __restrict__ v, int64_t ld,
                                                        float* __restrict__ xs, float* __restrict__ vs,
                                                        int32_t* __restrict__ perm) {
   __shared__ float stage[6][kHrSpan];
+  __shared__ uint32_t offs[SCAN_TOTALS ? kBlock : 1];
+  const uint32_t* csum = chunk_sum;
+  if (SCAN_TOTALS) {
+    const uint32_t t = (int)threadIdx.x < n_chunks ? chunk_sum[threadIdx.x] : 0u;
+    uint32_t total;
+    offs[threadIdx.x] = block_exclusive_scan(t, &total);
+    csum = offs;  // read after the barrier that follows the staging below
+  }
   const int64_t block0 = (int64_t)xcd_contiguous_block() * kHrSpan;
 #pragma unroll
   for (int j = 0; j < kHrItems; ++j) {
@@ -306,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_hr_scatter(const uint32_t* __restric
     if (q >= n) continue;
     const uint32_t i = src[q];
     const uint32_t l = (uint32_t)((int64_t)i - block0);
-    const uint32_t dst = cell_offset(local, chunk_sum, keys[q]) + slot[q];
+    const uint32_t dst = cell_offset(local, csum, keys[q]) + slot[q];
     // defensive: counts started at zero, sources stay inside the block
     if (dst >= (uint64_t)n || i >= (uint64_t)n || l >= (uint32_t)kHrSpan) continue;
     if (perm != nullptr) perm[dst] = (int32_t)i;
@@ -714,6 +725,26 @@ hipError_t launch_build_grid_batched(const BatchGridArgs& b, const GridScratch& 
   return hipGetLastError();
 }
 
+// The scan of the HR reorder's bins and the scatter: with at most kBlock
+// scan chunks the scatter's blocks scan the chunk totals themselves.
+static hipError_t launch_hr_scatter(const HRSortScratch& s, int64_t n, int64_t n_bins, const float* x,
+                                    const float* v, int64_t ld, float* xs, float* vs, int32_t* perm,
+                                    hipStream_t st) {
+  const int n_chunks = (int)((n_bins + kScanChunk - 1) / kScanChunk);
+  const unsigned nb = (unsigned)((n + kHrSpan - 1) / kHrSpan);
+  if (n_chunks <= kBlock) {
+    hipLaunchKernelGGL(k_scan_chunks, dim3(n_chunks), dim3(kBlock), 0, st, s.counts, n_bins, s.local, s.chunk_sum);
+    hipLaunchKernelGGL(k_hr_scatter<true>, dim3(nb), dim3(kBlock), 0, st, s.keys, s.slot, s.src, n, s.local,
+                       s.chunk_sum, n_chunks, x, v, ld, xs, vs, perm);
+  } else {
+    const hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hr_scatter<false>, dim3(nb), dim3(kBlock), 0, st, s.keys, s.slot, s.src, n, s.local,
+                       s.chunk_sum, n_chunks, x, v, ld, xs, vs, perm);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* hr_v, float* out_x,
                           float* out_v, int64_t n_hr, int sub, int mode, const HRSortScratch& s,
                           int32_t* perm_out, hipStream_t st, int64_t ld, int32_t perm_base,
@@ -736,15 +767,12 @@ hipError_t launch_sort_hr(const GridConst& gc, const float* hr_x, const float* h
     hipLaunchKernelGGL(k_hr_keys_count<SceneHrKey>, dim3(nb), dim3(kBlock), 0, st, kf, n_hr, s.keys, s.slot, s.src,
                        s.counts);
   }
-  hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
-  if (e != hipSuccess) return e;
   const bool in_place = out_x == hr_x || out_v == hr_v;
   // the old index of each new position is written only when it is asked for
   int32_t* perm = perm_out == nullptr ? nullptr : (in_place ? s.perm : perm_out);
-  hipLaunchKernelGGL(k_hr_scatter, dim3((unsigned)((n_hr + kHrSpan - 1) / kHrSpan)), dim3(kBlock), 0, st,
-                     s.keys, s.slot, s.src, n_hr,
-                     s.local, s.chunk_sum, hr_x, hr_v, ld, in_place ? s.x : out_x, in_place ? s.v : out_v,
-                     perm);
+  hipError_t e = launch_hr_scatter(s, n_hr, n_bins, hr_x, hr_v, ld, in_place ? s.x : out_x,
+                                   in_place ? s.v : out_v, perm, st);
+  if (e != hipSuccess) return e;
   if (in_place) {
     hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n_hr)), dim3(kBlock), 0, st, s.x, s.v, s.perm,
                        n_hr, out_x, out_v, ld, perm_out, perm_base);
@@ -795,10 +823,9 @@ hipError_t launch_sort_hr_batched(float* hr_x, float* hr_v, int64_t n, const int
   const unsigned nb = (unsigned)((n + kHrSpan - 1) / kHrSpan);
   hipLaunchKernelGGL(k_hr_keys_count<BatchHrKey>, dim3(nb), dim3(kBlock), 0, st, kf, n, s.keys, s.slot, s.src,
                      s.counts);
-  hipError_t e = scan_bins(s.counts, n_bins, s.local, s.chunk_sum, st);
+  const hipError_t e = launch_hr_scatter(s, n, n_bins, hr_x, hr_v, n, s.x, s.v,
+                                         perm_out != nullptr ? s.perm : nullptr, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_hr_scatter, dim3(nb), dim3(kBlock), 0, st, s.keys, s.slot, s.src, n, s.local, s.chunk_sum,
-                     hr_x, hr_v, n, s.x, s.v, perm_out != nullptr ? s.perm : nullptr);
   hipLaunchKernelGGL(k_copy_back, dim3(blocks_for(n)), dim3(kBlock), 0, st, s.x, s.v, s.perm, n,
                      hr_x, hr_v, n, perm_out, 0);
   return hipGetLastError();
