@@ -522,7 +522,9 @@ def test_sort_hr_key_table_follows_tuning(U):
     shuffle = np.random.default_rng(21).permutation(sc.n_hr)
     hx = dev(sc.hr_x0[:, shuffle].copy(), torch)
     hv = dev(np.random.default_rng(22).normal(size=sc.hr_x0.shape).astype(np.float32), torch)
-    for sub, mode in ((2, 2), (1, 0), (2, 1), (1, 2), (2, 2)):
+    # Hilbert at one sub-cell first and two after it: the handle's rank table
+    # of the fine cells is built, grown, rebuilt smaller and rebuilt again
+    for sub, mode in ((1, 2), (2, 2), (1, 0), (2, 1), (1, 2), (2, 2)):
         up.set_tuning(sort_sub=sub, sort_mode=mode)
         ox, ov = torch.empty_like(hx), torch.empty_like(hv)
         perm = up.sort_hr(hx, hv, out_x=ox, out_v=ov).long()
