@@ -682,6 +682,7 @@ struct upsample_pbd_s {
   float* cr;
   float *w, *xt, *xt2, *xs, *xs2;
   uint32_t *cnt, *ids, *overflow;
+  bool counts_dirty;  // a step that failed part way may have left grid counts non-zero
   std::string last_error;
 };
 
@@ -766,6 +767,12 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
   const int K = h->K;
   float* rec = tr != nullptr ? tr->base : nullptr;
   hipError_t e = hipSuccess;
+  if (h->counts_dirty) {  // every grid build expects zero counts (its scan leaves them so)
+    hipLaunchKernelGGL(k_zero_u32, dim3(nblocks(h->n_cells)), dim3(kBlock), 0, st, h->g.counts, h->n_cells);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    h->counts_dirty = false;
+  }
   auto record = [&](const float* src, int64_t m) {
     if (rec == nullptr || e != hipSuccess) return;
     e = copy_async(rec, src, m, st);
@@ -997,6 +1004,7 @@ int upsample_pbd_step(upsample_pbd h, float* x, float* v, int32_t n_steps, float
     float* fx = frames_x != nullptr ? frames_x + (size_t)s * 3 * (size_t)n : nullptr;
     float* fv = frames_v != nullptr ? frames_v + (size_t)s * 3 * (size_t)n : nullptr;
     e = pbd_step_one(h, x, v, fx, fv, nullptr, st);
+    if (e != hipSuccess) h->counts_dirty = true;
   }
   if (e != hipSuccess) return pbd_fail(h, UPSAMPLE_ERR_HIP, std::string("pbd_step: ") + hipGetErrorString(e));
   return UPSAMPLE_OK;
@@ -1012,6 +1020,7 @@ int upsample_pbd_debug_step(upsample_pbd h, float* x, float* v, float* trace, in
   hipStream_t st = (hipStream_t)stream;
   const PbdTrace tr{trace, pair_cnt, pair_ids};
   hipError_t e = pbd_step_one(h, x, v, nullptr, nullptr, &tr, st);
+  if (e != hipSuccess) h->counts_dirty = true;
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return pbd_fail(h, UPSAMPLE_ERR_HIP, std::string("pbd_debug_step: ") + hipGetErrorString(e));
   return UPSAMPLE_OK;
