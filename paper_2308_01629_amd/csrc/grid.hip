@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
 // The scatter of a build over positions alone that writes the sorted copy
 // itself: position, the caller's int32 tag (as bits) in p.w, the particle's
 // index in v.w.  Inside a cell the particles keep the order of their slot
-// claims, which varies from run to run; a caller of this build makes its
+// claims, which varies from run to run; a caller of this grid build makes its
 // results independent of that order.
 template <bool SCAN_TOTALS>
 __global__ __launch_bounds__(kBlock) void k_scatter_points(const uint32_t* __restrict__ keys,
