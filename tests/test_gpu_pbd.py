@@ -213,8 +213,8 @@ def test_stages_against_oracle(LRSim, name, warm):
     check_debug_step(LRSim, _scene(name), warm, **({"max_neighbors": 64} if name == "drain" else {}))
 
 
-@pytest.mark.parametrize("kw", [dict(stab_iters=0), dict(solve_iters=0), dict(mass_scaling=False),
-                                dict(stab_iters=1, solve_iters=3)])
+@pytest.mark.parametrize("kw", [dict(stab_iters=0), dict(solve_iters=0), dict(stab_iters=0, solve_iters=0),
+                                dict(mass_scaling=False), dict(stab_iters=1, solve_iters=3)])
 def test_stage_variants(LRSim, kw):
     check_debug_step(LRSim, _scene("impact_small"), 10, **kw)
 
