@@ -334,6 +334,20 @@ def test_pair_lists_canonical_in_dense_cluster(LRSim):
     sim.close()
 
 
+def test_particles_outside_the_pair_grid(LRSim):
+    """A pair grid over only part of the scene: most particles lie outside its
+    box and are clamped into the border cells, whose rows then hold long runs
+    of candidates.  The pair lists and every stage still match the oracle,
+    which finds pairs without a grid."""
+    import dataclasses
+    sc = _scene("impact_small")
+    lo, hi = np.array([0.1, 0.0, 0.1], F32), np.array([0.3, 0.1, 0.3], F32)
+    sc = dataclasses.replace(sc, domain_lo=lo, domain_hi=hi)
+    outside = ((sc.x < lo[:, None]) | (sc.x > hi[:, None])).any(axis=0)
+    assert outside.mean() > 0.5
+    check_debug_step(LRSim, sc, 8)
+
+
 def test_overflow_flag_and_edges(LRSim):
     sc = _scene("impact_small")
     sim = _sim(LRSim, sc, max_neighbors=1)
