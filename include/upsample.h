@@ -628,8 +628,10 @@ int upsample_pbd_info(upsample_pbd h, int64_t* out);
  * [3][n] each.  trace_len must equal out[4] of upsample_pbd_info.  pair_cnt
  * (device uint32 [2][n]) and pair_ids (device uint32 [2][n][max_neighbors])
  * receive the pair lists of the stabilization (0) and solver (1) phases:
- * particle i's partners are pair_ids[phase][i][0 .. pair_cnt[phase][i]); with
- * stab_iters = 0 no stabilization pairs are formed and phase 0's counts are 0.
+ * particle i's partners are pair_ids[phase][i][0 .. pair_cnt[phase][i]) (a
+ * static particle keeps no list: every constraint moves it by zero, and its
+ * partners list the pair); with stab_iters = 0 no stabilization pairs are
+ * formed and phase 0's counts are 0.
  * Synchronises the stream.  A debug entry point. */
 int upsample_pbd_debug_step(upsample_pbd h, float* x, float* v, float* trace, int64_t trace_len,
                             uint32_t* pair_cnt, uint32_t* pair_ids, void* stream);

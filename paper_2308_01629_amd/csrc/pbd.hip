@@ -96,7 +96,9 @@ constexpr int64_t kIterLanes8Max = 65536;
 inline int iter_lanes(int64_t n) { return n <= kIterLanes8Max ? 8 : 4; }
 
 // Contact list of each particle: the other particles closer than 2r
-// (squared distance rounded as in the upsampling's membership predicate,
+// (a static particle keeps none: with zero inverse mass every constraint
+// moves it by exactly zero, and its partners list the pair themselves;
+// squared distance rounded as in the upsampling's membership predicate,
 // against fl32(4 r^2)), without static-static and same-body pairs, ordered by
 // stencil row (dz, then dy) and, inside a row, by particle index.  The grid's
 // order inside a cell varies from run to run; this order does not, so the
@@ -142,6 +144,10 @@ __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoin
   const LRPoint me = sorted[t];
   const uint32_t i = __float_as_uint(me.v.w);
   const int bi = __float_as_int(me.p.w);
+  if (bi == kStatic) {  // its own constraints move it by exactly zero: no list
+    if (lane == 0) cnt[i] = 0u;
+    return;  // all lanes of the particle leave together
+  }
   const int cx = cell_coord(me.p.x, gc.lo[0], gc.inv_cs, gc.dims[0]);
   const int cy = cell_coord(me.p.y, gc.lo[1], gc.inv_cs, gc.dims[1]);
   const int cz = cell_coord(me.p.z, gc.lo[2], gc.inv_cs, gc.dims[2]);

@@ -76,15 +76,19 @@ def _f64(a):
 
 
 def _check_pairs(cnt, ids, Pos, body, r, what):
-    """The GPU's per-particle lists equal the oracle's float32 pairs; returns
-    the oracle's pairs (i < j)."""
+    """The GPU's per-particle lists equal the oracle's float32 pairs, each pair
+    in the lists of its non-static particles (a static particle keeps no list:
+    its own constraints move it by zero); returns the oracle's pairs (i < j)."""
     n = Pos.shape[1]
     pairs = P.contact_pairs(np.asarray(Pos, F32), body, F32(r), f32=True)
     K = ids.shape[1]
     assert cnt.max(initial=0) <= K
+    assert not cnt[body == S.STATIC].any(), f"{what}: a static particle has a list"
     owner = np.repeat(np.arange(n, dtype=np.int64), cnt.astype(np.int64))
     got = owner * n + ids[np.arange(K)[None, :] < cnt[:, None]].astype(np.int64)
-    want = np.concatenate([pairs[:, 0] * n + pairs[:, 1], pairs[:, 1] * n + pairs[:, 0]])
+    a, b = pairs[:, 0], pairs[:, 1]
+    fa, fb = body[a] != S.STATIC, body[b] != S.STATIC
+    want = np.concatenate([a[fa] * n + b[fa], b[fb] * n + a[fb]])
     got.sort()
     want.sort()
     assert got.shape == want.shape and np.array_equal(got, want), \
