@@ -15,7 +15,8 @@
 // Per step: k_pbd_predict, grid + k_pbd_pairs on the start positions,
 // stab_iters x k_pbd_stab, grid + k_pbd_pairs on the predicted positions
 // (each grid build's keys and counts come from the kernel before it),
-// solve_iters x (k_pbd_shape per rigid body, k_pbd_solve), k_pbd_finish.
+// solve_iters x (k_pbd_shape per rigid body, k_pbd_solve), and k_pbd_finish
+// unless the last k_pbd_solve writes the velocities itself.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
