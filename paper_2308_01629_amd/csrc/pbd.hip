@@ -85,28 +85,32 @@ __global__ __launch_bounds__(kBlock) void k_pbd_predict(PbdConst pc, int64_t n, 
   }
 }
 
-// Lanes per particle: the pair search gives each of the 9 stencil rows (dy,
-// dz in {-1, 0, 1}) its own lane; the iterations split a particle's pair
-// list over L lanes (8 up to kIterLanes8Max particles, 4 above) and sum them
-// by a fixed butterfly.  Small LR systems (tens of thousands of particles)
-// would otherwise leave the chip with about one wave per CU and every wave
-// waiting on memory; with 8 lanes a system of kIterLanes8Max particles
-// still fits about 8 waves per SIMD in one round.
-constexpr int kPairLanes = 16;
+// Lanes per particle: up to kIterLanes8Max particles the pair search gives
+// each of the 9 stencil rows (dy, dz in {-1, 0, 1}) its own lane of 16, and
+// the iterations split a particle's pair list over 8 lanes and sum them by a
+// fixed butterfly.  Small LR systems (tens of thousands of particles) would
+// otherwise leave the chip with about one wave per CU and every wave waiting
+// on memory; with 8 lanes a system of kIterLanes8Max particles still fits
+// about 8 waves per SIMD in one round.  Larger systems take 8 lanes in the
+// pair search (the first lane scanning the ninth row too) and 4 in the
+// iterations, which then fill the chip with fewer waves.
 constexpr int64_t kIterLanes8Max = 65536;
 inline int iter_lanes(int64_t n) { return n <= kIterLanes8Max ? 8 : 4; }
+inline int pair_lanes(int64_t n) { return n <= kIterLanes8Max ? 16 : 8; }
 
 // Contact list of each particle: the other particles closer than 2r
 // (a static particle keeps none: with zero inverse mass every constraint
 // moves it by exactly zero, and its partners list the pair themselves;
 // squared distance rounded as in the upsampling's membership predicate,
 // against fl32(4 r^2)), without static-static and same-body pairs, ordered by
-// stencil row (dz, then dy) and, inside a row, by particle index.  The grid's
-// order inside a cell varies from run to run; this order does not, so the
-// iterations sum each particle's constraints in the same order every time.
-// Groups of kPairLanes lanes take the sorted slots in order (the sorted copy
-// carries each particle's body id in p.w and its index in v.w).  Each row
-// lane reads its candidates four at a time and stages its first kRowStage
+// the lane that scans them and, inside a lane's rows, by particle index: with
+// PL = 16 lanes that is by stencil row (dz, then dy); with 8 the first lane
+// takes the first and the ninth row together.  The grid's order inside a cell
+// varies from run to run; this order does not, so the iterations sum each
+// particle's constraints in the same order every time.  Groups of PL lanes
+// take the sorted slots in order (the sorted copy carries each particle's
+// body id in p.w and its index in v.w).  Each lane reads its candidates four
+// at a time and stages its first kRowStage
 // matches in LDS; the group forms the exclusive prefix of the lanes' counts,
 // and a lane with at most kRowStage matches sorts them in registers (a
 // 19-comparator network) and copies them to the list.  A lane with more
@@ -133,14 +137,15 @@ __device__ __forceinline__ void sort8(uint32_t (&s)[8]) {
   cmp_swap(s[1], s[2]); cmp_swap(s[3], s[4]); cmp_swap(s[5], s[6]);
 }
 
+template <int PL>
 __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoint* __restrict__ sorted,
                                                       const uint32_t* __restrict__ cell_start, int64_t n, int K,
                                                       uint32_t* __restrict__ cnt, uint32_t* __restrict__ ids,
                                                       uint32_t* overflow) {
   __shared__ uint32_t stage[kRowStage][kBlock];
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t t = g / kPairLanes;
-  const int lane = (int)(g % kPairLanes);
+  const int64_t t = g / PL;
+  const int lane = (int)(g % PL);
   if (t >= n) return;  // the 16 lanes of a particle leave together
   const LRPoint me = sorted[t];
   const uint32_t i = __float_as_uint(me.v.w);
@@ -152,15 +157,18 @@ __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoin
   const int cx = cell_coord(me.p.x, gc.lo[0], gc.inv_cs, gc.dims[0]);
   const int cy = cell_coord(me.p.y, gc.lo[1], gc.inv_cs, gc.dims[1]);
   const int cz = cell_coord(me.p.z, gc.lo[2], gc.inv_cs, gc.dims[2]);
-  uint32_t b = 0, e = 0;
-  if (lane < 9) {
-    const int yy = cy + lane % 3 - 1, zz = cz + lane / 3 - 1;
-    if (yy >= 0 && yy < gc.dims[1] && zz >= 0 && zz < gc.dims[2]) {
+  auto row_range = [&](int r, uint32_t& rb, uint32_t& re) {
+    rb = re = 0u;
+    const int yy = cy + r % 3 - 1, zz = cz + r / 3 - 1;
+    if (r < 9 && yy >= 0 && yy < gc.dims[1] && zz >= 0 && zz < gc.dims[2]) {
       const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
-      b = cell_start[row + (uint32_t)max(cx - 1, 0)];
-      e = cell_start[row + (uint32_t)min(cx + 1, gc.dims[0] - 1) + 1u];
+      rb = cell_start[row + (uint32_t)max(cx - 1, 0)];
+      re = cell_start[row + (uint32_t)min(cx + 1, gc.dims[0] - 1) + 1u];
     }
-  }
+  };
+  uint32_t b, e, b2 = 0u, e2 = 0u;
+  row_range(lane, b, e);
+  if (PL < 9 && lane == 0) row_range(8, b2, e2);  // the ninth row goes to the first lane
   auto match = [&](const LRPoint& L) -> bool {
     const uint32_t j = __float_as_uint(L.v.w);
     const int bj = __float_as_int(L.p.w);
@@ -168,25 +176,29 @@ __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoin
     return sq_dist(L.p.x, L.p.y, L.p.z, me.p.x, me.p.y, me.p.z) < gc.h2;
   };
   uint32_t c = 0;
-  for (uint32_t q0 = b; q0 < e; q0 += 4) {
-    LRPoint L[4];
+  auto scan = [&](uint32_t rb, uint32_t re) {
+    for (uint32_t q0 = rb; q0 < re; q0 += 4) {
+      LRPoint L[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (q0 + u < e) L[u] = sorted[q0 + u];
+      for (int u = 0; u < 4; ++u)
+        if (q0 + u < re) L[u] = sorted[q0 + u];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (q0 + u < e && match(L[u])) {
-        if (c < (uint32_t)kRowStage) stage[c][threadIdx.x] = __float_as_uint(L[u].v.w);
-        ++c;
-      }
-  }
+      for (int u = 0; u < 4; ++u)
+        if (q0 + u < re && match(L[u])) {
+          if (c < (uint32_t)kRowStage) stage[c][threadIdx.x] = __float_as_uint(L[u].v.w);
+          ++c;
+        }
+    }
+  };
+  scan(b, e);
+  if (PL < 9) scan(b2, e2);
   uint32_t incl = c;
 #pragma unroll
-  for (int d = 1; d < kPairLanes; d <<= 1) {
-    const uint32_t u = __shfl_up(incl, d, kPairLanes);
+  for (int d = 1; d < PL; d <<= 1) {
+    const uint32_t u = __shfl_up(incl, d, PL);
     if (lane >= d) incl += u;
   }
-  const uint32_t total = __shfl(incl, kPairLanes - 1, kPairLanes);
+  const uint32_t total = __shfl(incl, PL - 1, PL);
   const uint32_t o0 = incl - c;
   uint32_t* list = ids + (int64_t)i * K;
   if (c <= (uint32_t)kRowStage) {
@@ -200,6 +212,10 @@ __global__ __launch_bounds__(kBlock) void k_pbd_pairs(GridConst gc, const LRPoin
   } else {  // rare: more matches than staged; all of them by one more scan, then sorted in place
     uint32_t o = o0;
     for (uint32_t q = b; q < e && o < (uint32_t)K; ++q) {
+      const LRPoint L = sorted[q];
+      if (match(L)) list[o++] = __float_as_uint(L.v.w);
+    }
+    for (uint32_t q = b2; q < e2 && o < (uint32_t)K; ++q) {
       const LRPoint L = sorted[q];
       if (match(L)) list[o++] = __float_as_uint(L.v.w);
     }
@@ -768,7 +784,8 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
   const int64_t n = h->n;
   const PbdConst pc = pbd_const(h->p);
   const unsigned nb = nblocks(n);
-  const unsigned nb_pairs = nblocks(n * kPairLanes);
+  const bool lanes16 = pair_lanes(n) == 16;
+  const unsigned nb_pairs = nblocks(n * pair_lanes(n));
   const bool lanes8 = iter_lanes(n) == 8;
   const unsigned nb_iter = nblocks(n * iter_lanes(n));
   const int K = h->K;
@@ -807,8 +824,8 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
   if (h->p.stab_iters > 0) {
     if (e == hipSuccess) e = launch_build_grid_points(h->gc, x, h->body, n, h->n_cells, h->g, st, true);
     if (e == hipSuccess)
-      hipLaunchKernelGGL(k_pbd_pairs, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start,
-                         n, K, h->cnt, h->ids, h->overflow);
+      hipLaunchKernelGGL(lanes16 ? k_pbd_pairs<16> : k_pbd_pairs<8>, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc,
+                         h->g.lr_sorted, h->g.cell_start, n, K, h->cnt, h->ids, h->overflow);
     if (e == hipSuccess && tr != nullptr) e = copy_pairs(h, tr, 0, st);
     float* out = h->xs;
     for (int it = 0; it < h->p.stab_iters && e == hipSuccess; ++it) {
@@ -830,8 +847,8 @@ hipError_t pbd_step_one(upsample_pbd_s* h, float* x, float* v, float* fx, float*
   float* tb = h->xt2;
   if (e == hipSuccess) e = launch_build_grid_points(h->gc, ta, h->body, n, h->n_cells, h->g, st, true);
   if (e == hipSuccess)
-    hipLaunchKernelGGL(k_pbd_pairs, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc, h->g.lr_sorted, h->g.cell_start, n,
-                       K, h->cnt, h->ids, h->overflow);
+    hipLaunchKernelGGL(lanes16 ? k_pbd_pairs<16> : k_pbd_pairs<8>, dim3(nb_pairs), dim3(kBlock), 0, st, h->gc,
+                       h->g.lr_sorted, h->g.cell_start, n, K, h->cnt, h->ids, h->overflow);
   if (e == hipSuccess && tr != nullptr) e = copy_pairs(h, tr, 1, st);
   const bool fuse = x0 != x && h->p.solve_iters > 0;
   const FinishArgs fin{x, v, fx, fv};

@@ -169,6 +169,7 @@ def check_debug_step(cls, sc, warm_steps, **sim_kw):
     # 2. stabilization
     if prm.stab_iters:
         sp = _check_pairs(*tr["pairs"][0], x_in, body, r, "stabilization pairs")
+        _rows_and_order_ok(*tr["pairs"][0], x_in, r, sc.domain_lo, sc.domain_hi)
     else:
         assert not tr["pairs"][0][0].any()
         sp = np.zeros((0, 2), np.int64)
@@ -183,6 +184,7 @@ def check_debug_step(cls, sc, warm_steps, **sim_kw):
     x0 = xs
     # 3. solver
     pairs = _check_pairs(*tr["pairs"][1], xts, body, r, "solver pairs")
+    _rows_and_order_ok(*tr["pairs"][1], xts, r, sc.domain_lo, sc.domain_hi)
     cur = xts
     n_act = 0
     for k, (frames, xtg) in enumerate(tr["solve"]):
@@ -281,26 +283,31 @@ def test_free_fall_and_invariants(LRSim):
     sim.close()
 
 
-def _rows_and_order_ok(cnt, ids, X, r, lo):
-    """Each list runs through the stencil rows in the kernel's order ((dz, dy)
-    from (-1, -1) on) and, inside a row, by increasing index; returns the
-    largest number of partners one particle has in one row."""
+def _rows_and_order_ok(cnt, ids, X, r, lo, hi):
+    """Each list runs through the stencil rows in the order of the lanes that
+    scan them, (dz, dy) from (-1, -1) on (16 lanes up to 65,536 particles;
+    above, 8 lanes, the first taking the first and the ninth row), and by
+    increasing index inside a lane's rows; returns the largest number of
+    partners one particle has in one row."""
     cs = 2.0 * float(F32(r)) * 1.0001
     inv_cs, X = F32(1.0 / cs), np.asarray(X, F32)
+    n = X.shape[1]
     cells = []
-    for a in (1, 2):  # y and z cell coordinates, float32 as the grid forms them
+    for a in (1, 2):  # y and z cell coordinates, float32 as the grid forms them, clamped into it
+        dims = max(1, int(np.ceil((float(F32(hi[a])) - float(F32(lo[a]))) / cs)))
         t = (X[a] - F32(lo[a])).astype(F32) * inv_cs
-        cells.append(np.floor(t.astype(F32)).astype(np.int64))
-    most = 0
-    for i in range(X.shape[1]):
-        lst = ids[i, :cnt[i]].astype(np.int64)
-        row = (cells[1][lst] - cells[1][i] + 1) * 3 + (cells[0][lst] - cells[0][i] + 1)
-        assert row.min(initial=0) >= 0 and row.max(initial=0) <= 8, f"particle {i}: partner outside the stencil"
-        key = row * X.shape[1] + lst
-        assert np.all(np.diff(key) > 0), f"particle {i}: list not in (row, index) order"
-        if lst.size:
-            most = max(most, int(np.bincount(row).max()))
-    return most
+        cells.append(np.clip(np.floor(t.astype(F32)).astype(np.int64), 0, dims - 1))
+    K = ids.shape[1]
+    own = np.repeat(np.arange(n, dtype=np.int64), cnt.astype(np.int64))
+    lst = ids[np.arange(K)[None, :] < cnt[:, None]].astype(np.int64)
+    row = (cells[1][lst] - cells[1][own] + 1) * 3 + (cells[0][lst] - cells[0][own] + 1)
+    assert row.min(initial=0) >= 0 and row.max(initial=0) <= 8, "a partner outside the stencil"
+    group = np.where(row == 8, 0, row) if n > 65536 else row
+    key = group * n + lst
+    same = own[1:] == own[:-1]
+    bad = np.nonzero(same & (np.diff(key) <= 0))[0]
+    assert bad.size == 0, f"particle {own[bad[0]] if bad.size else -1}: list not in (lane rows, index) order"
+    return int(np.bincount(own * 9 + row, minlength=9 * n).max(initial=0))
 
 
 def test_pair_lists_canonical_in_dense_cluster(LRSim):
@@ -326,7 +333,7 @@ def test_pair_lists_canonical_in_dense_cluster(LRSim):
     for ph, pos in ((0, X), (1, tr["xt_pred"] if not tr["stab"] else tr["stab"][-1][1])):
         cnt, ids = tr["pairs"][ph]
         _check_pairs(cnt, ids, pos, body, r, f"phase {ph} pairs")
-        most = max(most, _rows_and_order_ok(cnt, ids, pos, r, (0, 0, 0)))
+        most = max(most, _rows_and_order_ok(cnt, ids, pos, r, (0, 0, 0), (1, 1, 1)))
         cnt2, ids2 = tr2["pairs"][ph]
         assert np.array_equal(cnt, cnt2)
         assert all(np.array_equal(ids[i, :cnt[i]], ids2[i, :cnt[i]]) for i in range(n))
