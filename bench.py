@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--sort-mode", type=int, default=-1,
                     help="HR reorder key: 0 cell then Morton, 1 Morton, 2 Hilbert (-1: library default)")
     ap.add_argument("--groups", type=int, default=0, help="gather lane groups per wave (0: library default)")
+    ap.add_argument("--tile-max", type=int, default=0,
+                    help="candidates above which a wave walks per lane (0: library default)")
     ap.add_argument("--cell-factor", type=float, default=0.0, help="fixed kappa (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the autotuner")
     ap.add_argument("--step-loop", action="store_true",
@@ -175,6 +177,8 @@ def drain_leg(args, torch, Upsampler, name="drain", steps=None, warmup=None, rep
         up.set_tuning(sort_mode=args.sort_mode)
     if args.groups:
         up.set_tuning(gather_groups=args.groups)
+    if args.tile_max:
+        up.set_tuning(tile_max=args.tile_max)
     gi = up.grid_info()
     log(f"{name}: setup {time.time() - t0:.1f}s, grid {gi['dims']} reach {gi['reach']} tuning {up.get_tuning()}")
     up.sort_hr(hx, hv, with_perm=False)

@@ -103,6 +103,27 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
   return r;
 }
 
+// Candidates of the longest per-lane walk of the wave: each lane counts its
+// own stencil rows (the rows gather() walks), and the wave takes the maximum.
+// Wave-uniform.
+__device__ __forceinline__ uint32_t lane_walk_max(const GridConst& gc, const uint32_t* __restrict__ cell_start,
+                                                  float x, float y, float z) {
+  const int R = gc.reach;
+  const int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
+  const int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
+  const int cz = cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2]);
+  const int x0 = max(cx - R, 0), x1 = min(cx + R, gc.dims[0] - 1);
+  const int y0 = max(cy - R, 0), y1 = min(cy + R, gc.dims[1] - 1);
+  const int z0 = max(cz - R, 0), z1 = min(cz + R, gc.dims[2] - 1);
+  uint32_t s = 0u;
+  for (int zz = z0; zz <= z1; ++zz)
+    for (int yy = y0; yy <= y1; ++yy) {
+      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
+      s += cell_start[row + (uint32_t)x1 + 1u] - cell_start[row + (uint32_t)x0];
+    }
+  return (uint32_t)__builtin_amdgcn_readlane(group_max<1>((int)s), 63);
+}
+
 // Element o of the array at p, addressed as a base pointer (uniform across
 // the wave, so in scalar registers) plus a 32-bit lane offset, instead of a
 // 64-bit address per lane.
@@ -281,6 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_advance(AdvanceArgs a, WallTable wt)
 // list,   d = X_j - x_i,  t = 1 - |d|^2 / h^2,  w = max(t, 0)^3,
 // accumulating S, U, M; the per-lane stencil walk covers spread-out waves.
 constexpr int kGatherListEntries = 128;  // per wave, split over the G group lists
+constexpr uint32_t kLaneWalkShare = 4;  // see advance_tile
 constexpr int kGatherRows = 64;
 
 template <int G>
@@ -443,8 +465,17 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
     dw.max_k = a.dbg_max_k;
   }
   const TileSetup<G> ts = tile_setup<G>(gc, a.cell_start, x, y, z, lane, wid, lds);
-  if (ts.nrows > lds.kRows || ts.total > (uint32_t)a.tile_max) {
-    // spread-out wave: every lane walks its own stencil
+  // The per-lane walk: for waves whose rows overflow the LDS, and for waves
+  // streaming more than tile_max candidates whose lanes' own stencils hold
+  // fewer than 1 / kLaneWalkShare of them (spread-out waves).  A compact wave
+  // in dense LR keeps the shared list: its lanes would each walk nearly all
+  // of the candidates one dependent load at a time.  tile_max 0 sends every
+  // wave with candidates to the per-lane walk.
+  bool per_lane = ts.nrows > lds.kRows;
+  if (!per_lane && ts.total > (uint32_t)a.tile_max)
+    per_lane = a.tile_max == 0 || kLaneWalkShare * lane_walk_max(gc, a.cell_start, x, y, z) < ts.total;
+  if (per_lane) {
+    // every lane walks its own stencil
     const Sums s = gather<DBG, RIGID, TAPE>(gc, a.lr, a.cell_start, x, y, z, dw.ids, dw.max_k);
     S = s.S; Ux = s.Ux; Uy = s.Uy; Uz = s.Uz; M = s.M; arg = s.arg;
     if (DBG) {
