@@ -261,8 +261,12 @@ def test_gather_group_variants_match_oracle(U, groups):
 def test_wave_paths_agree(U, rigid):
     # each wave either tiles its candidates through LDS (sums on the matrix
     # cores) or walks per lane (sums in the vector unit), chosen by how many
-    # candidates it would stream; the choice changes a particle's result by
-    # rounding only, with or without rigid LR particles
+    # candidates it would stream and how many its lanes' own stencils hold;
+    # the choice changes a particle's result by rounding only, with or
+    # without rigid LR particles.  tile_max 0: every wave per lane; 16: the
+    # stencil test decides for nearly every wave (on the drain at 1/16 about
+    # 20 of 4,096 waves then walk per lane); 2^30: every wave that fits the
+    # LDS rows tiles.
     if rigid:
         sc = build_scene("heap", 1500, 30001, seed=[21, 3], rigid_floor=True)
         X, V = sc.lr_frame(1)
@@ -276,7 +280,7 @@ def test_wave_paths_agree(U, rigid):
     hx, hv = dev(sc.hr_x0, torch), dev(np.random.default_rng(6).normal(size=sc.hr_x0.shape).astype(np.float32), torch)
     up.sort_hr(hx, hv, with_perm=False)
     out = []
-    for tmax in (0, up.get_tuning()["tile_max"], 1 << 30):
+    for tmax in (0, 16, up.get_tuning()["tile_max"], 1 << 30):
         up.set_tuning(tile_max=tmax)
         out.append(up.step(dev(X, torch), dev(V, torch), rig, hx, hv))
     torch.cuda.synchronize()

@@ -78,14 +78,15 @@ def _members_check(up, X, hx, hv, spec, n_sample, seed, label, rigid=None):
 
 CASES = [
     ("drain", 1, 0, None), ("drain", 1, 9, None), ("drain", 2, 9, None), ("drain", 4, 9, None),
-    ("column", 1, 9, None), ("diff", 1, 9, None), ("drain_small", 1, 9, 0),
+    ("column", 1, 9, None), ("diff", 1, 9, None), ("drain_small", 1, 9, 0), ("drain_small", 1, 9, 16),
 ]
 
 
 @pytest.mark.parametrize("name,groups,age,tile_max", CASES)
 def test_timed_kernel_members_bitexact(U, name, groups, age, tile_max):
     """Full-size workloads (the drain at 1/16 for the per-lane walk of every
-    wave): HR reordered as the timed run reorders, then ``age`` steps of
+    wave, and at tile_max 16 for waves sent either way by their lanes'
+    stencils): HR reordered as the timed run reorders, then ``age`` steps of
     upsample_run without a reorder (waves spread as particles drift), then the
     members of the next frame's step."""
     if name == "drain_small":
