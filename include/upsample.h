@@ -63,7 +63,7 @@ extern "C" {
  * particle's gradient is summed by one wave over its HR neighbours in a fixed
  * order with a fixed lane reduction, then added by one writer.  No float
  * atomics: repeated calls give the same bits.  Costs a per-lane HR pass, the HR
- * sort and the LR pass; init allocates 8 B per cell and 56 B per HR particle
+ * sort and the LR pass; init allocates 8 B per cell and 76 B per HR particle
  * (max_hr) more. */
 #define UPSAMPLE_FLAG_DETERMINISTIC_BWD 2u
 

@@ -252,6 +252,23 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_det(AdjointArgs a, WallTable
   adjoint_lane<true>(a, wt, i);
 }
 
+// The HR coefficients in the HR grid's sorted order, so that the LR pass
+// reads them with the sorted positions instead of by original index: slot q
+// of the sorted copy gets (dL/dU, dL/dS) in v and the argmax bits in p.w
+// (its velocity and flag are not used by that pass), and dL/dM goes to row 6
+// of the coefficient array.
+__global__ __launch_bounds__(kBlock) void k_det_sort_coef(const uint32_t* __restrict__ perm,
+                                                           float* __restrict__ coef, int64_t n,
+                                                           LRPoint* __restrict__ hs) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const uint32_t i = perm[q];
+  if (i >= (uint64_t)n) return;  // defensive: perm is a permutation of [0, n)
+  hs[q].v = make_float4(coef[i], coef[n + i], coef[2 * n + i], coef[3 * n + i]);
+  hs[q].p.w = coef[5 * n + i];
+  coef[6 * n + q] = coef[4 * n + i];
+}
+
 // Sum over the wave by a fixed butterfly: the same inputs give the same bits.
 __device__ __forceinline__ float wave_sum_fixed(float v) {
 #pragma unroll
@@ -263,7 +280,8 @@ __device__ __forceinline__ float wave_sum_fixed(float v) {
 // neighbours come from the HR grid (stable cell order) over the stencil of
 // its own cell, each lane taking every 64th candidate of the walk; the terms
 // of a member pair are those of adjoint_lane, from the pair's HR coefficients
-// and the same separately rounded squared distance.  Lane 0 adds the wave's
+// (sorted with the HR particles by k_det_sort_coef) and the same separately
+// rounded squared distance.  Lane 0 adds the wave's
 // sums into the caller's gradients (one writer per LR particle).
 __global__ __launch_bounds__(kBlock) void k_adjoint_det_lr(AdjointArgs a) {
   const int lane = threadIdx.x & 63;
@@ -274,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_det_lr(AdjointArgs a) {
   const uint32_t id = __float_as_uint(L.v.w);
   const uint32_t* hcs = a.hr_cell_start;
   const LRPoint* hs = a.hr_sorted;
-  const int64_t n = a.n;
+  const float* gm = a.det_coef + 6 * a.n;  // dL/dM by sorted slot
   const float k2 = -6.0f * gc.inv_h2;
   int lo[3], hi[3];
   stencil_bounds(gc, L.p.x, L.p.y, L.p.z, lo, hi);
@@ -284,17 +302,16 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_det_lr(AdjointArgs a) {
       const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
       const uint32_t b = hcs[row + (uint32_t)lo[0]], e = hcs[row + (uint32_t)hi[0] + 1u];
       for (uint32_t q = b + (uint32_t)lane; q < e; q += 64u) {
-        const float4 H = hs[q].p;
+        const float4 H = hs[q].p;  // (x, y, z, argmax bits)
         const float s = sq_dist(L.p.x, L.p.y, L.p.z, H.x, H.y, H.z);
         if (s < gc.h2) {
-          const int64_t i = (int64_t)__float_as_uint(hs[q].v.w);
-          const float gUx = a.det_coef[i], gUy = a.det_coef[n + i], gUz = a.det_coef[2 * n + i];
-          const float gS = a.det_coef[3 * n + i], gM = a.det_coef[4 * n + i];
-          const uint32_t arg = __float_as_uint(a.det_coef[5 * n + i]);
+          const float4 C = hs[q].v;  // (dL/dUx, dL/dUy, dL/dUz, dL/dS)
+          const float gUx = C.x, gUy = C.y, gUz = C.z, gS = C.w;
+          const uint32_t arg = __float_as_uint(H.w);
           const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
           const float w = t * t * t;
           float gw = fmaf(gUz, L.v.z, fmaf(gUy, L.v.y, gUx * L.v.x)) + gS;
-          if (id == arg) gw += gM;
+          if (id == arg) gw += gm[q];
           const float c = gw * k2 * t * t;
           acc[0] += w * gUx;
           acc[1] += w * gUy;
@@ -684,6 +701,8 @@ hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStrea
       const int64_t n_cells = (int64_t)a.gc.dims[0] * a.gc.dims[1] * a.gc.dims[2];
       hipError_t e = launch_build_grid(a.gc, a.hx, a.hv, nullptr, a.n, n_cells, *hr_grid, st);
       if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_det_sort_coef, dim3(blocks), dim3(kBlock), 0, st, hr_grid->perm, a.det_coef, a.n,
+                         hr_grid->lr_sorted);
       AdjointArgs b = a;
       b.hr_cell_start = hr_grid->cell_start;
       b.hr_sorted = hr_grid->lr_sorted;

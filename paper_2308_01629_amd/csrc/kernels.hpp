@@ -304,8 +304,8 @@ struct AdjointArgs {
   int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
   const float* tape;  // forward record [6][n] (skips the recomputation of the sums) or null
   // deterministic LR gradients (all null otherwise): per HR particle its
-  // adjoint coefficients [6][n] (dL/dU, dL/dS, dL/dM, argmax bits), and
-  // the HR particles sorted by the same cells
+  // adjoint coefficients [7][n] (dL/dU, dL/dS, dL/dM, argmax bits; row 6:
+  // dL/dM by sorted slot), and the HR particles sorted by the same cells
   float* det_coef;
   const uint32_t* hr_cell_start;  // set by launch_adjoint from hr_grid
   const LRPoint* hr_sorted;

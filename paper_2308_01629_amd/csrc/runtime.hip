@@ -37,7 +37,7 @@ struct upsample_handle_s {
   uint32_t* finite_flag;
   float* g_sorted;      // [6][max_lr] adjoint LR gradients by sorted index, zero between calls
   GridScratch hr_g;     // DETERMINISTIC_BWD: HR particles sorted by cell (max_hr)
-  float* det_coef;      // DETERMINISTIC_BWD: [6][max_hr] adjoint coefficients per HR particle
+  float* det_coef;      // DETERMINISTIC_BWD: [7][max_hr] adjoint coefficients per HR particle
   bool hr_g_dirty;      // a failed deterministic backward may have left hr_g.counts non-zero
   uint32_t* wall_mask;  // [n_cells] walls near each cell's neighbourhood, or null
   bool grid_valid;
@@ -465,7 +465,7 @@ int upsample_init(const upsample_params* p, upsample_handle* out) {
     ALLOC(h->hr_g.chunk_sum, h->n_chunks + 1)
     ALLOC(h->hr_g.cell_start, h->n_cells + 1)
     ALLOC(h->hr_g.lr_sorted, nh)
-    ALLOC(h->det_coef, 6 * nh)
+    ALLOC(h->det_coef, 7 * nh)
   }
 #undef ALLOC
   if (e == hipSuccess && cull_walls) {
