@@ -16,8 +16,10 @@
 //                    to global memory by six lanes (two atomic instructions);
 //   k_adjoint        one particle per lane, its own stencil walk, atomics per
 //                    pair: spread-out waves and scenes with rigid LR particles.
-// Deterministic LR gradients take a third route: k_adjoint_det writes each HR
-// particle's adjoint coefficients, and k_adjoint_det_lr gives every LR
+// Deterministic LR gradients take a third route: k_adjoint_det_tiled (the
+// tiled HR pass) or k_adjoint_det (per lane) writes each HR particle's
+// adjoint coefficients, k_det_sort_coef puts them in the HR grid's sorted
+// order, and k_adjoint_det_lr gives every LR
 // particle one wave that walks its HR neighbours (HR sorted by cell, stable)
 // in a fixed order and reduces over the lanes in a fixed pattern; each LR
 // gradient then has one writer and no float atomic is involved.
@@ -688,6 +690,91 @@ __global__ __launch_bounds__(kBlock) void k_lr_grad_unsort(const LRPoint* __rest
   }
 }
 
+// Deterministic LR gradients, scenes without rigid LR particles: the HR
+// pass of k_adjoint_tiled (the same sums, replay and pull-back, and the HR
+// position terms in the same list order and arithmetic, so the HR gradients
+// are that kernel's bits) without its LR accumulation; each particle's
+// coefficients go to a.det_coef for the LR pass.  Spread waves walk per lane.
+__global__ __launch_bounds__(kBlock) void k_adjoint_det_tiled(AdjointArgs a, WallTable wt) {
+  __shared__ TileLDS<1, kAdjListCap, kAdjRows> lds;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t n = a.n;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + tid;
+  const bool live = i0 < n;
+  const int64_t i = live ? i0 : n - 1;  // idle lanes shadow the last particle
+  const float x = a.hx[i], y = a.hx[n + i], z = a.hx[2 * n + i];
+  const GridConst& gc = a.gc;
+
+  const TileSetup<1> ts = tile_setup<1>(gc, a.cell_start, x, y, z, lane, wid, lds);
+  if (ts.nrows > kAdjRows || ts.total > (uint32_t)a.tile_max) {
+    if (live) adjoint_lane<true>(a, wt, i);
+    return;  // wave-uniform: no block barrier follows
+  }
+  const float inv_h2 = gc.inv_h2;
+  float S = 0.f, Ux = 0.f, Uy = 0.f, Uz = 0.f, M = 0.f;
+  uint32_t arg = 0xffffffffu;
+  if (a.tape != nullptr) {
+    S = a.tape[i];
+    Ux = a.tape[n + i];
+    Uy = a.tape[2 * n + i];
+    Uz = a.tape[3 * n + i];
+    M = a.tape[4 * n + i];
+    arg = __float_as_uint(a.tape[5 * n + i]);
+  } else {
+    uint64_t key = 0ull;  // (weight bits << 32 | ~index): unsigned maximum = argmax
+    tile_visit<1>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
+      for (uint32_t c = 0; c < nc; ++c) {
+        const float4 Q = lp[c];
+        const float4 W = lv[c];
+        const float dx = Q.x - x, dy = Q.y - y, dz = Q.z - z;
+        const float sq = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float u = __builtin_amdgcn_fmed3f(fmaf(-sq, inv_h2, 1.0f), 0.0f, 1.0f);
+        const float w = u * u * u;
+        const uint32_t id = __float_as_uint(W.w);
+        S += w;
+        Ux = fmaf(w, W.x, Ux);
+        Uy = fmaf(w, W.y, Uy);
+        Uz = fmaf(w, W.z, Uz);
+        const uint64_t kk = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~id);
+        key = kk > key ? kk : key;
+      }
+    });
+    M = __uint_as_float((uint32_t)(key >> 32));
+    arg = ~(uint32_t)key;
+  }
+  const float vx = a.hv[i], vy = a.hv[n + i], vz = a.hv[2 * n + i];
+  const float z0 = 0.0f;
+  Back bk = backprop(a.sc, wt, x, y, z, vx, vy, vz, S, Ux, Uy, Uz, M,
+                     live ? a.gx_out[i] : z0, live ? a.gx_out[n + i] : z0, live ? a.gx_out[2 * n + i] : z0,
+                     live ? a.gv_out[i] : z0, live ? a.gv_out[n + i] : z0, live ? a.gv_out[2 * n + i] : z0);
+  if (live) {
+    a.det_coef[i] = bk.gUx;
+    a.det_coef[n + i] = bk.gUy;
+    a.det_coef[2 * n + i] = bk.gUz;
+    a.det_coef[3 * n + i] = bk.gS;
+    a.det_coef[4 * n + i] = bk.gM;
+    a.det_coef[5 * n + i] = __uint_as_float(arg);
+  }
+  const float k2 = -6.0f * inv_h2;  // dw/ds = -3 t^2 / h2, times 2 for ds/dX
+  tile_visit<1>(ts, gc, a.lr, lane, wid, lds, [&](uint32_t nc, const float4* lp, const float4* lv) {
+    for (uint32_t c = 0; c < nc; ++c) {
+      const PairGeom pg = pair_geom(lp[c], x, y, z, inv_h2);
+      if (__builtin_amdgcn_ballot_w64(pg.t > 0.0f) == 0ull) continue;
+      (void)pair_contrib(pg, lv[c], k2, arg, bk);  // the HR position terms
+    }
+  });
+  if (live) {
+    a.gx_in[i] = bk.gx;
+    a.gx_in[n + i] = bk.gy;
+    a.gx_in[2 * n + i] = bk.gz;
+    a.gv_in[i] = bk.gvx;
+    a.gv_in[n + i] = bk.gvy;
+    a.gv_in[2 * n + i] = bk.gvz;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStream_t st,
@@ -696,7 +783,10 @@ hipError_t launch_adjoint(const AdjointArgs& a, const WallTable& walls, hipStrea
   const unsigned blocks = (unsigned)((a.n + kBlock - 1) / kBlock);
   if (a.det_coef != nullptr) {
     if (hr_grid == nullptr) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_adjoint_det, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    if (a.sc.has_rigid || !a.tiled)
+      hipLaunchKernelGGL(k_adjoint_det, dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    else
+      hipLaunchKernelGGL(k_adjoint_det_tiled, dim3(blocks), dim3(kBlock), 0, st, a, walls);
     if (a.n_lr > 0) {
       const int64_t n_cells = (int64_t)a.gc.dims[0] * a.gc.dims[1] * a.gc.dims[2];
       hipError_t e = launch_build_grid(a.gc, a.hx, a.hv, nullptr, a.n, n_cells, *hr_grid, st);

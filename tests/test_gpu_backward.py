@@ -255,9 +255,10 @@ def test_adjoint_scratch_cleared_between_calls(U):
 @pytest.mark.parametrize("case", ["plain", "rigid", "diff"])
 def test_deterministic_backward(U, case):
     """UPSAMPLE_FLAG_DETERMINISTIC_BWD: repeated backward calls (recomputing
-    and taped) give the same bits, the HR gradients equal the per-lane
-    adjoint's bit for bit, LR gradients are added to what the caller passes,
-    and everything matches the oracle's reference gradient."""
+    and taped) give the same bits, the HR gradients equal the atomic
+    adjoint's bit for bit (its tiled HR pass, and the per-lane one with
+    adjoint_tiled 0), LR gradients are added to what the caller passes, and
+    everything matches the oracle's reference gradient."""
     rig = None
     if case == "rigid":
         sc = build_scene("heap", 1500, 30001, seed=[21, 3], rigid_floor=True)
@@ -271,8 +272,7 @@ def test_deterministic_backward(U, case):
         X, V = sc.lr_frame(3)
     kw = dict(max_lr=X.shape[1])
     up = U.from_scene(sc, deterministic_bwd=True, **kw)
-    ref = U.from_scene(sc, **kw)
-    ref.set_tuning(adjoint_tiled=0)
+    ref = U.from_scene(sc, **kw)  # the atomic adjoint, the same HR pass
     rng = np.random.default_rng(21)
     hx = dev(sc.hr_x0, torch)
     hv = dev(rng.normal(0, 0.5, sc.hr_x0.shape).astype(np.float32), torch)
@@ -294,7 +294,15 @@ def test_deterministic_backward(U, case):
     taped = [up.step_backward(Xd, Vd, rd, hx, hv, *g, tape=tape) for _ in range(2)]
     ones = (torch.ones_like(Xd), torch.ones_like(Vd))
     added = up.step_backward(Xd, Vd, rd, hx, hv, *g, g_lr_x=ones[0].clone(), g_lr_v=ones[1].clone())
+    # the per-lane HR pass on both sides
+    up.set_tuning(adjoint_tiled=0)
+    ref.set_tuning(adjoint_tiled=0)
+    lane = up.step_backward(Xd, Vd, rd, hx, hv, *g)
+    lane_ref = ref.step_backward(Xd, Vd, rd, hx, hv, *g)
     torch.cuda.synchronize()
+    assert torch.equal(lane[0], lane_ref[0]) and torch.equal(lane[1], lane_ref[1])
+    for p_, q_ in zip(lane[2:], runs[0][2:]):
+        assert rel(host(p_), host(q_).astype(np.float64)) < 1e-5
     for r in runs[1:]:
         for p_, q_ in zip(runs[0], r):
             assert torch.equal(p_, q_), "deterministic backward differs between calls"
