@@ -303,11 +303,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_det_lr(AdjointArgs a) {
     for (int yy = lo[1]; yy <= hi[1]; ++yy) {
       const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
       const uint32_t b = hcs[row + (uint32_t)lo[0]], e = hcs[row + (uint32_t)hi[0] + 1u];
-      for (uint32_t q = b + (uint32_t)lane; q < e; q += 64u) {
-        const float4 H = hs[q].p;  // (x, y, z, argmax bits)
+      // candidate q: H = (x, y, z, argmax bits), C = (dL/dU, dL/dS)
+      auto term = [&](const float4 H, const float4 C, uint32_t q) {
         const float s = sq_dist(L.p.x, L.p.y, L.p.z, H.x, H.y, H.z);
         if (s < gc.h2) {
-          const float4 C = hs[q].v;  // (dL/dUx, dL/dUy, dL/dUz, dL/dS)
           const float gUx = C.x, gUy = C.y, gUz = C.z, gS = C.w;
           const uint32_t arg = __float_as_uint(H.w);
           const float t = fmaxf(fmaf(-s, gc.inv_h2, 1.0f), 0.0f);
@@ -322,6 +321,20 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_det_lr(AdjointArgs a) {
           acc[4] += c * (L.p.y - H.y);
           acc[5] += c * (L.p.z - H.z);
         }
+      };
+      // the lane's candidates q, q + 64, ... in order; four at a time, so
+      // that their loads are in flight together
+      uint32_t q = b + (uint32_t)lane;
+      for (; q + 192u < e; q += 256u) {
+        const LRPoint P0 = hs[q], P1 = hs[q + 64u], P2 = hs[q + 128u], P3 = hs[q + 192u];
+        term(P0.p, P0.v, q);
+        term(P1.p, P1.v, q + 64u);
+        term(P2.p, P2.v, q + 128u);
+        term(P3.p, P3.v, q + 192u);
+      }
+      for (; q < e; q += 64u) {
+        const LRPoint P = hs[q];
+        term(P.p, P.v, q);
       }
     }
 #pragma unroll
