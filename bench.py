@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--groups", type=int, default=0, help="gather lane groups per wave (0: library default)")
     ap.add_argument("--tile-max", type=int, default=0,
                     help="candidates above which a wave walks per lane (0: library default)")
+    ap.add_argument("--adjoint-tile-max", type=int, default=0,
+                    help="the adjoint's candidate limit for the diff leg (0: library default)")
     ap.add_argument("--cell-factor", type=float, default=0.0, help="fixed kappa (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the autotuner")
     ap.add_argument("--step-loop", action="store_true",
@@ -281,6 +283,8 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
     LX = torch.from_numpy(np.stack([f[0] for f in frames])).cuda()
     LV = torch.from_numpy(np.stack([f[1] for f in frames])).cuda()
     up = Upsampler.from_scene(sc)
+    if args.adjoint_tile_max:
+        up.set_tuning(adjoint_tile_max=args.adjoint_tile_max)
     n_cells = up.grid_info()["n_cells"]
     x0 = torch.from_numpy(sc.hr_x0).cuda()
     v0 = torch.from_numpy(sc.hr_v0).cuda()

@@ -364,8 +364,8 @@ int upsample_debug_step_members(upsample_handle h, const float* hr_x, const floa
  * kernel whose stencil rows hold more LR candidates than this walks per lane
  * when its longest per-lane stencil holds fewer than a quarter of them (a
  * compact wave in dense LR keeps its shared list); 0 sends every wave with
- * candidates to the per-lane walk.  adjoint_tile_max: an adjoint wave whose
- * stencil rows hold more LR candidates than this walks per lane.
+ * candidates to the per-lane walk.  adjoint_tile_max: the same for the
+ * adjoint's waves, with a share of an eighth.
  * wall_cull: 1 (default) lets a wave of the step kernel skip the walls whose
  * planes lie farther than r_hr from the neighbourhood of the cells its
  * particles occupy (a per-cell table built at init for grids of up to 2^22

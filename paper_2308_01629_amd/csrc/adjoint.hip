@@ -435,6 +435,20 @@ constexpr int kBlockRows = 256;     // at most one row per thread
 constexpr int kAdjListCap = 64;     // LDS candidate entries per wave and flush
 constexpr int kAdjRows = 64;        // stencil rows of one wave
 
+// A wave of the adjoint tiles its candidates unless its rows overflow the
+// LDS, or it would stream more than tile_max candidates while its lanes' own
+// stencils hold fewer than 1 / kAdjLaneWalkShare of them (spread-out waves
+// walk per lane; compact waves in dense LR keep the shared list).  tile_max 0
+// sends every wave with candidates to the per-lane walk.  Wave-uniform; the
+// tiled and the deterministic kernels decide alike.
+constexpr uint32_t kAdjLaneWalkShare = 8;
+__device__ __forceinline__ bool adjoint_wave_tiled(const TileSetup<1>& ts, const AdjointArgs& a, float x,
+                                                   float y, float z) {
+  if (ts.nrows > kAdjRows) return false;
+  if (ts.total <= (uint32_t)a.tile_max) return true;
+  return a.tile_max != 0 && kAdjLaneWalkShare * lane_walk_max(a.gc, a.cell_start, x, y, z) >= ts.total;
+}
+
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* wsum) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t inc = wave_incl_scan(v);
@@ -474,7 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_tiled(AdjointArgs a, WallTab
   const int64_t nl = a.n_lr;
 
   const TileSetup<1> ts = tile_setup<1>(gc, a.cell_start, x, y, z, lane, wid, lds);
-  const bool wave_tiled = ts.nrows <= kAdjRows && ts.total <= (uint32_t)a.tile_max;
+  const bool wave_tiled = adjoint_wave_tiled(ts, a, x, y, z);
 
   // ---- block box and block rows
   if (lane == 0) {
@@ -721,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_det_tiled(AdjointArgs a, Wal
   const GridConst& gc = a.gc;
 
   const TileSetup<1> ts = tile_setup<1>(gc, a.cell_start, x, y, z, lane, wid, lds);
-  if (ts.nrows > kAdjRows || ts.total > (uint32_t)a.tile_max) {
+  if (!adjoint_wave_tiled(ts, a, x, y, z)) {
     if (live) adjoint_lane<true>(a, wt, i);
     return;  // wave-uniform: no block barrier follows
   }

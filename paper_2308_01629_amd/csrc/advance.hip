@@ -103,27 +103,6 @@ __device__ __forceinline__ Sums gather(const GridConst& gc, const LRPoint* __res
   return r;
 }
 
-// Candidates of the longest per-lane walk of the wave: each lane counts its
-// own stencil rows (the rows gather() walks), and the wave takes the maximum.
-// Wave-uniform.
-__device__ __forceinline__ uint32_t lane_walk_max(const GridConst& gc, const uint32_t* __restrict__ cell_start,
-                                                  float x, float y, float z) {
-  const int R = gc.reach;
-  const int cx = cell_coord(x, gc.lo[0], gc.inv_cs, gc.dims[0]);
-  const int cy = cell_coord(y, gc.lo[1], gc.inv_cs, gc.dims[1]);
-  const int cz = cell_coord(z, gc.lo[2], gc.inv_cs, gc.dims[2]);
-  const int x0 = max(cx - R, 0), x1 = min(cx + R, gc.dims[0] - 1);
-  const int y0 = max(cy - R, 0), y1 = min(cy + R, gc.dims[1] - 1);
-  const int z0 = max(cz - R, 0), z1 = min(cz + R, gc.dims[2] - 1);
-  uint32_t s = 0u;
-  for (int zz = z0; zz <= z1; ++zz)
-    for (int yy = y0; yy <= y1; ++yy) {
-      const uint32_t row = (uint32_t)gc.dims[0] * ((uint32_t)yy + (uint32_t)gc.dims[1] * (uint32_t)zz);
-      s += cell_start[row + (uint32_t)x1 + 1u] - cell_start[row + (uint32_t)x0];
-    }
-  return (uint32_t)__builtin_amdgcn_readlane(group_max<1>((int)s), 63);
-}
-
 // Element o of the array at p, addressed as a base pointer (uniform across
 // the wave, so in scalar registers) plus a 32-bit lane offset, instead of a
 // 64-bit address per lane.

@@ -103,9 +103,17 @@ def test_adjoint_tiled_matches_per_lane(U):
     for tiled in (0, 1):
         up.set_tuning(adjoint_tiled=tiled)
         out[tiled] = [host(t) for t in up.step_backward(X, V, None, hx, hv, *g)]
+    # tiled, with the per-lane walk for every wave, for waves sent either way
+    # by their lanes' stencils (limit 16), and for none
+    for tmax in (0, 16, 1 << 30):
+        up.set_tuning(adjoint_tiled=1, adjoint_tile_max=tmax)
+        out[("limit", tmax)] = [host(t) for t in up.step_backward(X, V, None, hx, hv, *g)]
     torch.cuda.synchronize()
-    for a, b in zip(out[0], out[1]):
-        assert rel(b, a.astype(np.float64)) < 1e-5
+    for k, o in out.items():
+        if k == 0:
+            continue
+        for a, b in zip(out[0], o):
+            assert rel(b, a.astype(np.float64)) < 1e-5, k
 
 
 def test_rollout_gradient(U):
