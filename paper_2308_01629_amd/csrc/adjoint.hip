@@ -322,9 +322,16 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_det_lr(AdjointArgs a) {
           acc[5] += c * (L.p.z - H.z);
         }
       };
-      // the lane's candidates q, q + 64, ... in order; four at a time, so
-      // that their loads are in flight together
+      // the lane's candidates q, q + 64, ... in order; eight (then four) at a
+      // time, so that their loads are in flight together
       uint32_t q = b + (uint32_t)lane;
+      for (; q + 448u < e; q += 512u) {
+        LRPoint P[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) P[k] = hs[q + 64u * (uint32_t)k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) term(P[k].p, P[k].v, q + 64u * (uint32_t)k);
+      }
       for (; q + 192u < e; q += 256u) {
         const LRPoint P0 = hs[q], P1 = hs[q + 64u], P2 = hs[q + 128u], P3 = hs[q + 192u];
         term(P0.p, P0.v, q);

@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_stable(const uint32_t* __restrict__ 
   uint32_t rank = 0;
   // independent loads: unrolled, several are in flight at once (HR cells of
   // the deterministic backward hold hundreds of particles)
-#pragma unroll 8
+#pragma unroll 16
   for (uint32_t q = b; q < e; ++q) rank += (tmp[q] < i) ? 1u : 0u;
   const uint32_t dst = b + rank;
   if (dst >= e) return;

@@ -216,7 +216,7 @@ struct AdvanceArgs {
   // wave tests every wall
   const uint32_t* wall_mask;
   int groups;    // lane groups per wave in the tiled gather: 1, 2 or 4 (a tuning knob)
-  int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
+  int tile_max;  // a spread-out wave streaming more LR candidates than this walks per lane
   float* tape;   // [6][n] (S, Ux, Uy, Uz, M, argmax bits) or null
 };
 // debug: 0 the step kernel, 1 the per-lane walk with member exports, 2 the
@@ -301,7 +301,7 @@ struct AdjointArgs {
   int64_t n;
   int64_t n_lr;
   int tiled;     // 1: wave-tiled kernel (non-rigid scenes), 0: one particle per lane
-  int tile_max;  // a wave streaming more LR candidates than this walks per lane instead
+  int tile_max;  // a spread-out wave streaming more LR candidates than this walks per lane
   const float* tape;  // forward record [6][n] (skips the recomputation of the sums) or null
   // deterministic LR gradients (all null otherwise): per HR particle its
   // adjoint coefficients [7][n] (dL/dU, dL/dS, dL/dM, argmax bits; row 6:
