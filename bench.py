@@ -342,10 +342,26 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
             up.step_backward(LX[t], LV[t], None, xs[t], vs[t], gx, gv, g_lr_x=glx, g_lr_v=glv,
                              gx_in=bx, gv_in=bv, tape=tapes[t])
 
+    # the taped pair with the forward's grid saved for the adjoint (no
+    # rebuild in the backward; the forward pays one device copy per step)
+    grids = torch.empty((steps, up.grid_snapshot_bytes()), dtype=torch.uint8, device="cuda")
+
+    def fwd_taped_grid():
+        for t in range(steps):
+            up.step(LX[t], LV[t], None, xs[t], vs[t], out_x=ox, out_v=ov, tape=tapes[t])
+            up.grid_snapshot(grids[t])
+
+    def bwd_taped_grid():
+        for t in range(steps - 1, -1, -1):
+            up.step_backward(LX[t], LV[t], None, xs[t], vs[t], gx, gv, g_lr_x=glx, g_lr_v=glv,
+                             gx_in=bx, gv_in=bv, tape=tapes[t], grid=grids[t])
+
     fwd()
     bwd()
     fwd_taped()
     bwd_taped()
+    fwd_taped_grid()
+    bwd_taped_grid()
     # the gather kernel alone on the plain forward (HIP events per launch)
     up.timing_enable(True)
     fwd()
@@ -366,7 +382,9 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
     upd.close()
     t_ft = timed(fwd_taped) / steps
     t_bt = timed(bwd_taped) / steps
-    del tapes
+    t_ftg = timed(fwd_taped_grid) / steps
+    t_btg = timed(bwd_taped_grid) / steps
+    del tapes, grids
     LXg = LX.clone().requires_grad_(True)
     LVg = LV.clone().requires_grad_(True)
 
@@ -383,7 +401,7 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
     t_rfb = timed(roll_fb, 2)
     up.close()
     log(f"diff: taped forward {t_ft * 1e3:.1f} us/step, taped backward {t_bt * 1e3:.1f} us/step, ratio "
-        f"{t_bt / t_ft:.2f}; plain forward {t_f * 1e3:.1f}, recomputing backward {t_b * 1e3:.1f} (ratio "
+        f"{t_bt / t_ft:.2f}; with saved grids {t_ftg * 1e3:.1f} / {t_btg * 1e3:.1f}; plain forward {t_f * 1e3:.1f}, recomputing backward {t_b * 1e3:.1f} (ratio "
         f"{t_b / t_f:.2f}), deterministic {t_bd * 1e3:.1f}; rollout fwd {t_rf:.2f} ms, fwd+bwd {t_rfb:.2f} ms")
     return {"workload": "diff", "n_lr": sc.n_lr, "n_hr": sc.n_hr,
             "ratio": t_b / t_f,
@@ -393,6 +411,8 @@ def diff_leg(args, torch, Upsampler, steps=40, every=8, reorder_every=4):
             "ratio_taped": t_bt / t_ft,
             "backward_deterministic_us_per_step": t_bd * 1e3, "ratio_deterministic": t_bd / t_f,
             "forward_taped_us_per_step": t_ft * 1e3, "backward_taped_us_per_step": t_bt * 1e3,
+            "forward_taped_saved_grid_us_per_step": t_ftg * 1e3,
+            "backward_taped_saved_grid_us_per_step": t_btg * 1e3, "ratio_taped_saved_grid": t_btg / t_ftg,
             "forward_gather_roofline": roofline(adv_ms / 1e3 / max(launches, 1), sc.n_hr, sc.n_lr, n_cells),
             "rollout_steps": steps, "checkpoint_every": every, "reorder_every": reorder_every,
             "rollout_forward_ms": t_rf,

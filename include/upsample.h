@@ -217,6 +217,43 @@ int upsample_step_backward_taped(upsample_handle h,
                                  void* stream);
 
 /*
+ * Saved grids (not in the paper): the adjoint of a step needs that step's LR
+ * grid (the uniform-grid neighbour search of Section 5.1: cell ranges and the
+ * LR copy in sorted order).  upsample_step_backward(_taped) rebuilds it from
+ * the LR frame; a caller that keeps the taped forward's grid skips that
+ * rebuild.
+ *
+ * upsample_grid_snapshot_bytes: bytes of one snapshot for this handle (the
+ * sorted LR copy for max_lr particles, 32 B each, then the n_cells + 1 cell
+ * starts, each part padded to 256 B).  It depends on max_lr and on the grid
+ * dimensions, so a change of the cell size (upsample_set_tuning,
+ * upsample_autotune) changes it and invalidates earlier snapshots.
+ *
+ * upsample_grid_snapshot: copy the handle's current grid (that of the last
+ * upsample_build_grid, step or backward) into grid, caller-owned device
+ * memory of upsample_grid_snapshot_bytes bytes, 256-byte aligned, on stream.
+ * Returns STATE if no grid has been built, INVALID_ARG for a NULL or
+ * misaligned pointer.
+ *
+ * upsample_step_backward_taped_grid: upsample_step_backward_taped with the
+ * grid read from a snapshot of the same LR frame (taken on this handle, with
+ * the same grid parameters, after the taped step) instead of rebuilt.  Only
+ * whether lr_rigid is NULL is read (the rigid flags are in the snapshot's LR
+ * copy); n_lr must be the frame's particle count.  The handle's own grid is
+ * left as it was.  Results are bitwise those of upsample_step_backward_taped
+ * on the same inputs (the same grid, the same kernels).  A snapshot of
+ * another frame or handle gives wrong gradients; its contents are not checked.
+ */
+int upsample_grid_snapshot_bytes(upsample_handle h, int64_t* bytes);
+int upsample_grid_snapshot(upsample_handle h, void* grid, void* stream);
+int upsample_step_backward_taped_grid(upsample_handle h, const void* grid,
+                                      const uint8_t* lr_rigid, int64_t n_lr,
+                                      const float* hr_x, const float* hr_v, int64_t n_hr,
+                                      const float* tape, const float* gx_out, const float* gv_out,
+                                      float* gx_in, float* gv_in, float* g_lr_x, float* g_lr_v,
+                                      void* stream);
+
+/*
  * Multi-step run: advances the HR state in place through n_frames
  * consecutive LR frames (lr_x, lr_v: device [n_frames][3][n_lr]; lr_rigid, if
  * given, applies to every frame), i.e. n_frames upsample_step calls.  Before

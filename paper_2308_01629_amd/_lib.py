@@ -112,6 +112,10 @@ SIGNATURES = {
     "upsample_step_taped": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _P, _P]),
     "upsample_step_backward_taped": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
                                             _P]),
+    "upsample_grid_snapshot_bytes": (_INT, [_P, ctypes.POINTER(_I64)]),
+    "upsample_grid_snapshot": (_INT, [_P, _P, _P]),
+    "upsample_step_backward_taped_grid": (_INT, [_P, _P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P,
+                                                 _P]),
     "upsample_run": (_INT, [_P, _P, _P, _P, _I64, _I32, _P, _P, _I64, _I32, _P, _P]),
     "upsample_run_multirate": (_INT, [_P, _P, _P, _P, _I64, _I32, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, _I32, _P, _P, _I64, _I32, _P, _P]),

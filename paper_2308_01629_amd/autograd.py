@@ -5,7 +5,9 @@ kernel; its forward records the per-particle sums the adjoint needs (a
 "tape", upsample_step_taped).  ``UpsampleRollout`` advances the HR state
 through a sequence of LR frames, keeping the state every ``checkpoint_every``
 steps; its backward replays one segment at a time from its checkpoint
-(recording tapes) and runs the adjoint steps of that segment in reverse, so
+(recording tapes and saving each replayed step's LR grid, so that its
+adjoint does not rebuild it) and runs the adjoint steps of that segment in
+reverse, so
 memory grows with T / checkpoint_every + the segment length instead of T.  Gradients reach the LR positions and velocities
 of every frame and the initial HR state.  The LR simulation itself is not
 differentiated (its frames are leaves).
@@ -106,17 +108,22 @@ class UpsampleRollout(torch.autograd.Function):
             # the segment is not replayed, its adjoint recomputes them
             states = [ctx.checkpoints[seg]]
             n = states[0][0].shape[1]
-            tapes = torch.empty((max(end - start - 1, 1), 6, n), dtype=torch.float32, device=states[0][0].device)
+            k = max(end - start - 1, 1)
+            tapes = torch.empty((k, 6, n), dtype=torch.float32, device=states[0][0].device)
+            # each replayed step's LR grid, kept for its adjoint (no rebuild)
+            grids = torch.empty((k, up.grid_snapshot_bytes()), dtype=torch.uint8, device=states[0][0].device)
             for t in range(start, end - 1):
                 x, v = up.step(lr_x[t], lr_v[t], ctx.rigid, *states[-1], tape=tapes[t - start])
+                up.grid_snapshot(grids[t - start])
                 if t + 1 in perms:
                     x, v = up.permute(x, perms[t + 1], v)
                 states.append((x, v))
             for t in range(end - 1, start - 1, -1):
                 x, v = states[t - start]
                 tape = tapes[t - start] if t < end - 1 else None
+                grid = grids[t - start] if t < end - 1 else None
                 gx, gv, _, _ = up.step_backward(lr_x[t], lr_v[t], ctx.rigid, x, v, gx, gv,
-                                                g_lr_x=g_lr_x[t], g_lr_v=g_lr_v[t], tape=tape)
+                                                g_lr_x=g_lr_x[t], g_lr_v=g_lr_v[t], tape=tape, grid=grid)
                 if t in perms:
                     gx, gv = up.permute(gx, perms[t], gv, scatter=True)
         ctx.checkpoints = None

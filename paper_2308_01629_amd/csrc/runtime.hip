@@ -665,10 +665,22 @@ int upsample_step_taped(upsample_handle h, const float* lr_x, const float* lr_v,
                       tape);
 }
 
+// A saved grid: the LR copy in sorted order (max_lr entries of 32 B), then
+// the cell ranges (n_cells + 1 words), each part 256-byte aligned.
+static int64_t snapshot_lr_bytes(const upsample_handle h) {
+  return (h->p.max_lr * (int64_t)sizeof(LRPoint) + 255) / 256 * 256;
+}
+static int64_t snapshot_bytes(const upsample_handle h) {
+  return snapshot_lr_bytes(h) + ((h->n_cells + 1) * (int64_t)sizeof(uint32_t) + 255) / 256 * 256;
+}
+
+// grid: null rebuilds the grid from lr_x / lr_v / lr_rigid; otherwise a saved
+// grid of the same frame (upsample_grid_snapshot), and only n_lr and whether
+// lr_rigid is null are read of the LR arguments.
 static int backward_impl(upsample_handle h, const float* lr_x, const float* lr_v, const uint8_t* lr_rigid,
                          int64_t n_lr, const float* hr_x, const float* hr_v, int64_t n_hr, const float* tape,
                          const float* gx_out, const float* gv_out, float* gx_in, float* gv_in, float* g_lr_x,
-                         float* g_lr_v, void* stream) {
+                         float* g_lr_v, void* stream, const void* grid = nullptr) {
   if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
   if (n_hr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_hr < 0");
   if (n_hr > h->p.max_hr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_hr exceeds max_hr");
@@ -677,8 +689,25 @@ static int backward_impl(upsample_handle h, const float* lr_x, const float* lr_v
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "HR pointer is NULL");
   if (n_lr > 0 && n_hr > 0 && (g_lr_x == nullptr || g_lr_v == nullptr))
     return fail(h, UPSAMPLE_ERR_INVALID_ARG, "LR gradient pointer is NULL");
-  int rc = upsample_build_grid(h, lr_x, lr_v, lr_rigid, n_lr, stream);
-  if (rc != UPSAMPLE_OK) return rc;
+  const LRPoint* lr_sorted = h->g.lr_sorted;
+  const uint32_t* cell_start = h->g.cell_start;
+  bool has_rigid = h->has_rigid;
+  int rc;
+  if (grid == nullptr) {
+    rc = upsample_build_grid(h, lr_x, lr_v, lr_rigid, n_lr, stream);
+    if (rc != UPSAMPLE_OK) return rc;
+    has_rigid = h->has_rigid;
+  } else {
+    if (n_lr < 0) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "n_lr < 0");
+    if (n_lr > h->p.max_lr) return fail(h, UPSAMPLE_ERR_CAPACITY, "n_lr exceeds max_lr");
+    if ((reinterpret_cast<uintptr_t>(grid) & 255u) != 0u)
+      return fail(h, UPSAMPLE_ERR_INVALID_ARG, "grid snapshot is not 256-byte aligned");
+    rc = check_device(h);
+    if (rc != UPSAMPLE_OK) return rc;
+    lr_sorted = static_cast<const LRPoint*>(grid);
+    cell_start = reinterpret_cast<const uint32_t*>(static_cast<const char*>(grid) + snapshot_lr_bytes(h));
+    has_rigid = lr_rigid != nullptr;
+  }
   hipStream_t st = (hipStream_t)stream;
   const float* arrs[2] = {gx_out, gv_out};
   const int64_t sizes[2] = {3 * n_hr, 3 * n_hr};
@@ -686,9 +715,9 @@ static int backward_impl(upsample_handle h, const float* lr_x, const float* lr_v
   if (rc != UPSAMPLE_OK) return rc;
   AdjointArgs a;
   a.gc = grid_const(h);
-  a.sc = step_const(h);
-  a.lr = h->g.lr_sorted;
-  a.cell_start = h->g.cell_start;
+  a.sc = make_step_const(h->p, has_rigid);
+  a.lr = lr_sorted;
+  a.cell_start = cell_start;
   a.hx = hr_x;
   a.hv = hr_v;
   a.gx_out = gx_out;
@@ -741,6 +770,43 @@ int upsample_step_backward_taped(upsample_handle h, const float* lr_x, const flo
   if (n_hr > 0 && tape == nullptr) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "tape is NULL");
   return backward_impl(h, lr_x, lr_v, lr_rigid, n_lr, hr_x, hr_v, n_hr, tape, gx_out, gv_out, gx_in, gv_in,
                        g_lr_x, g_lr_v, stream);
+}
+
+int upsample_grid_snapshot_bytes(upsample_handle h, int64_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "NULL argument");
+  *bytes = snapshot_bytes(h);
+  return UPSAMPLE_OK;
+}
+
+int upsample_grid_snapshot(upsample_handle h, void* grid, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (grid == nullptr) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "grid snapshot is NULL");
+  if ((reinterpret_cast<uintptr_t>(grid) & 255u) != 0u)
+    return fail(h, UPSAMPLE_ERR_INVALID_ARG, "grid snapshot is not 256-byte aligned");
+  if (!h->grid_valid) return fail(h, UPSAMPLE_ERR_STATE, "no grid has been built");
+  int rc = check_device(h);
+  if (rc != UPSAMPLE_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  char* dst = static_cast<char*>(grid);
+  hipError_t e = hipSuccess;
+  if (h->grid_n_lr > 0)
+    e = hipMemcpyAsync(dst, h->g.lr_sorted, sizeof(LRPoint) * (size_t)h->grid_n_lr, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst + snapshot_lr_bytes(h), h->g.cell_start, sizeof(uint32_t) * (size_t)(h->n_cells + 1),
+                       hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(h, e, "grid_snapshot");
+  return UPSAMPLE_OK;
+}
+
+int upsample_step_backward_taped_grid(upsample_handle h, const void* grid, const uint8_t* lr_rigid, int64_t n_lr,
+                                      const float* hr_x, const float* hr_v, int64_t n_hr, const float* tape,
+                                      const float* gx_out, const float* gv_out, float* gx_in, float* gv_in,
+                                      float* g_lr_x, float* g_lr_v, void* stream) {
+  if (h == nullptr) return UPSAMPLE_ERR_INVALID_ARG;
+  if (grid == nullptr) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "grid snapshot is NULL");
+  if (n_hr > 0 && tape == nullptr) return fail(h, UPSAMPLE_ERR_INVALID_ARG, "tape is NULL");
+  return backward_impl(h, nullptr, nullptr, lr_rigid, n_lr, hr_x, hr_v, n_hr, tape, gx_out, gv_out, gx_in, gv_in,
+                       g_lr_x, g_lr_v, stream, grid);
 }
 
 static int run_prepare(upsample_handle h, hipStream_t st) {

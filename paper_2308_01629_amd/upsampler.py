@@ -45,6 +45,14 @@ def _tape(t: torch.Tensor, n: int) -> torch.Tensor:
     return t
 
 
+def _snapshot(t: torch.Tensor, nbytes: int) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.uint8 and t.dim() == 1 and t.numel() >= nbytes and t.is_contiguous()
+            and t.data_ptr() % 256 == 0):
+        raise ValueError(f"grid snapshot must be a contiguous 256-byte aligned uint8 device tensor of at least "
+                         f"{nbytes} bytes")
+    return t
+
+
 def make_params(r_lr: float, r_hr: float, dt: float, g: Sequence[float], domain_lo, domain_hi,
                 walls=None, max_lr: int = 0, max_hr: int = 0, c1: float = 512.0 / 729.0,
                 c2: float = 0.6, cell_factor: float = 0.0, validate: bool = False,
@@ -231,11 +239,32 @@ class Upsampler:
                                                     _ptr(tape), _stream()))
         return out_x, out_v
 
+    def grid_snapshot_bytes(self) -> int:
+        """Bytes of one saved grid (upsample_grid_snapshot_bytes)."""
+        b = ctypes.c_int64()
+        self._check(self._L.upsample_grid_snapshot_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def grid_snapshot(self, out=None):
+        """Copy the handle's current LR grid into ``out`` (a uint8 device
+        tensor of grid_snapshot_bytes() bytes, 256-byte aligned; allocated when
+        None) and return it: upsample_grid_snapshot."""
+        nb = self.grid_snapshot_bytes()
+        if out is None:
+            out = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        _snapshot(out, nb)
+        self._check(self._L.upsample_grid_snapshot(self._h, _ptr(out), _stream()))
+        return out
+
     def step_backward(self, lr_x, lr_v, lr_rigid, hr_x, hr_v, gx_out, gv_out,
-                      g_lr_x=None, g_lr_v=None, gx_in=None, gv_in=None, tape=None):
+                      g_lr_x=None, g_lr_v=None, gx_in=None, gv_in=None, tape=None, grid=None):
         """Returns (gx_in, gv_in, g_lr_x, g_lr_v); LR gradients are ADDED into
         g_lr_x / g_lr_v when given (zeros otherwise).  ``tape``: the record of
-        the taped forward step on the same inputs (skips the recomputation)."""
+        the taped forward step on the same inputs (skips the recomputation).
+        ``grid`` (with ``tape``): a grid_snapshot() taken after that taped
+        step (skips the grid rebuild)."""
+        if grid is not None and tape is None:
+            raise ValueError("grid needs tape: only the taped adjoint reads a saved grid")
         nl = _soa(lr_x, "lr_x").shape[1]
         _soa(lr_v, "lr_v")
         _u8(lr_rigid, nl, "lr_rigid")
@@ -249,6 +278,12 @@ class Upsampler:
         if tape is None:
             self._check(self._L.upsample_step_backward(
                 self._h, _ptr(lr_x), _ptr(lr_v), _ptr(lr_rigid), nl, _ptr(hr_x), _ptr(hr_v), n,
+                _ptr(gx_out), _ptr(gv_out), _ptr(gx_in), _ptr(gv_in), _ptr(g_lr_x), _ptr(g_lr_v), _stream()))
+        elif grid is not None:
+            _tape(tape, n)
+            _snapshot(grid, self.grid_snapshot_bytes())
+            self._check(self._L.upsample_step_backward_taped_grid(
+                self._h, _ptr(grid), _ptr(lr_rigid), nl, _ptr(hr_x), _ptr(hr_v), n, _ptr(tape),
                 _ptr(gx_out), _ptr(gv_out), _ptr(gx_in), _ptr(gv_in), _ptr(g_lr_x), _ptr(g_lr_v), _stream()))
         else:
             _tape(tape, n)

@@ -99,6 +99,10 @@ def test_null_handle_calls_rejected():
     assert L.upsample_step_taped(None, None, None, None, 0, None, None, None, None, 0, None, None) == inv
     assert L.upsample_step_backward_taped(None, None, None, None, 0, None, None, 0, None, None, None, None,
                                           None, None, None, None) == inv
+    assert L.upsample_grid_snapshot_bytes(None, None) == inv
+    assert L.upsample_grid_snapshot(None, None, None) == inv
+    assert L.upsample_step_backward_taped_grid(None, None, None, 0, None, None, 0, None, None, None, None, None,
+                                               None, None, None) == inv
     assert L.upsample_permute(None, None, None, None, None, 0, None, 0, None) == inv
     assert L.upsample_run(None, None, None, None, 0, 1, None, None, 0, 0, None, None) == inv
     assert L.upsample_autotune(None, None, None, None, 0, 1, None, None, 0, None, None, None) == inv

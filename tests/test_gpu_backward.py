@@ -238,6 +238,92 @@ def test_taped_step_and_adjoint(U, case):
     log(f"taped adjoint {case}: {errs}")
 
 
+@pytest.mark.parametrize("case", ["plain", "rigid", "drain"])
+def test_taped_adjoint_from_saved_grid(U, case):
+    """The taped adjoint on a saved grid (upsample_grid_snapshot after the
+    taped step, upsample_step_backward_taped_grid), with another frame's grid
+    built on the handle in between, against the taped adjoint that rebuilds
+    the grid: HR gradients bit for bit; LR gradients bit for bit with the
+    deterministic LR sums and to float32 rounding with the atomic ones.  The
+    saved-grid gradients are also checked against the oracle's."""
+    if case == "rigid":
+        sc = build_scene("heap", 1500, 30001, seed=[21, 3], rigid_floor=True)
+        X, V = sc.lr_frame(1)
+        X2, V2 = sc.lr_frame(2)
+        rig = sc.lr_rigid
+    else:
+        sc = configs.plain() if case == "plain" else configs.drain(scale=1 / 16)
+        X, V = sc.lr_frame(2)
+        X2, V2 = sc.lr_frame(3)
+        rig = None
+    rng = np.random.default_rng(33)
+    hx = dev(sc.hr_x0, torch)
+    hv = dev(rng.normal(0, 0.5, sc.hr_x0.shape).astype(np.float32), torch)
+    idx = None if sc.n_hr <= 65536 else np.sort(rng.choice(sc.n_hr, 4096, replace=False))
+    sel = slice(None) if idx is None else idx
+    gxo = np.zeros(sc.hr_x0.shape, np.float32)
+    gvo = np.zeros(sc.hr_x0.shape, np.float32)
+    gxo[:, sel] = rng.normal(size=gxo[:, sel].shape)
+    gvo[:, sel] = rng.normal(size=gvo[:, sel].shape)
+    Xd, Vd, X2d, V2d = dev(X, torch), dev(V, torch), dev(X2, torch), dev(V2, torch)
+    rd = None if rig is None else dev(rig, torch)
+    g = (dev(gxo, torch), dev(gvo, torch))
+    for det in (False, True):
+        up = U.from_scene(sc, deterministic_bwd=det, max_lr=X.shape[1])
+        if case == "drain":
+            up.sort_hr(hx, hv, with_perm=False)
+        tape = torch.empty((6, sc.n_hr), dtype=torch.float32, device="cuda")
+        up.step(Xd, Vd, rd, hx, hv, tape=tape)
+        grid = up.grid_snapshot()
+        assert grid.numel() == up.grid_snapshot_bytes() and up.grid_snapshot_bytes() % 256 == 0
+        up.step(X2d, V2d, rd, hx, hv)  # the handle's grid is now another frame's
+        a = up.step_backward(Xd, Vd, rd, hx, hv, *g, tape=tape)  # rebuilds frame (X, V)
+        up.step(X2d, V2d, rd, hx, hv)
+        b = up.step_backward(Xd, Vd, rd, hx, hv, *g, tape=tape, grid=grid)
+        c = up.step_backward(Xd, Vd, rd, hx, hv, *g, tape=tape, grid=grid)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), (case, det)
+        assert torch.equal(b[0], c[0]) and torch.equal(b[1], c[1]), (case, det)
+        for p_, q_ in zip(a[2:], b[2:]):
+            if det:
+                assert torch.equal(p_, q_), (case, "deterministic LR gradients differ")
+            else:
+                assert rel(host(q_), host(p_).astype(np.float64)) < 1e-5, case
+        o = O.step_backward(X, V, rig, host(hx)[:, sel], host(hv)[:, sel], sc.params(), gxo[:, sel],
+                            gvo[:, sel])
+        errs = {"g_lr_v": rel(host(b[3]), o["g_lr_v"]), "g_lr_x": rel(host(b[2]), o["g_lr_x"]),
+                "gx": rel(host(b[0])[:, sel], o["gx"]), "gv": rel(host(b[1])[:, sel], o["gv"])}
+        for k, e in errs.items():
+            assert e < 1e-4, (case, det, k, e, errs)
+        log(f"saved-grid taped adjoint {case} det={det}: {errs}")
+        up.close()
+
+
+def test_grid_snapshot_errors(U):
+    # a snapshot before any grid is a call-order error; misaligned or short
+    # snapshot buffers are rejected before any device work
+    from paper_2308_01629_amd import _lib
+    sc = configs.plain()
+    up = U.from_scene(sc)
+    nb = up.grid_snapshot_bytes()
+    buf = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    assert buf.data_ptr() % 256 == 0
+    L = _lib.lib()
+    assert L.upsample_grid_snapshot(up._h, buf.data_ptr(), None) == _lib.ERR_CODES["UPSAMPLE_ERR_STATE"]
+    X, V = sc.lr_frame(1)
+    hx, hv = dev(sc.hr_x0, torch), dev(sc.hr_v0, torch)
+    up.step(dev(X, torch), dev(V, torch), None, hx, hv)
+    inv = _lib.ERR_CODES["UPSAMPLE_ERR_INVALID_ARG"]
+    assert L.upsample_grid_snapshot(up._h, buf.data_ptr() + 16, None) == inv
+    assert L.upsample_step_backward_taped_grid(up._h, buf.data_ptr() + 16, None, X.shape[1], None, None, 0,
+                                               None, None, None, None, None, None, None, None) == inv
+    with pytest.raises(ValueError):
+        up.grid_snapshot(out=buf[:nb - 256])
+    assert L.upsample_grid_snapshot(up._h, buf.data_ptr(), None) == 0
+    torch.cuda.synchronize()
+    up.close()
+
+
 def test_adjoint_scratch_cleared_between_calls(U):
     # The tiled adjoint sums LR gradients by sorted index in handle scratch
     # that its last kernel empties again: repeated calls on one handle, and a
