@@ -392,6 +392,26 @@ __device__ __forceinline__ void quad_sums(v4f acc, int lane, float& Ux, float& U
   S = quad_pick<3>(acc, i1, i2, i3);
 }
 
+// The same transpose through the wave's LDS list (free once its walk is
+// done): lane 4q + n stores register r at float 16q + 4r + n, so particle
+// 4q + r's four sums sit at floats 4(4q + r) .. +3, one 16-byte read per lane.
+// Data movement only: the sums are those of quad_sums bit for bit.
+__device__ __forceinline__ void lds_quad_sums(v4f acc, int lane, float4* scratch, float& Ux, float& Uy,
+                                              float& Uz, float& S) {
+  float* t = reinterpret_cast<float*>(scratch) + 16 * (lane >> 2) + (lane & 3);
+  t[0] = acc[0];
+  t[4] = acc[1];
+  t[8] = acc[2];
+  t[12] = acc[3];
+  wave_lds_sync();
+  const float4 r = scratch[lane];
+  Ux = r.x;
+  Uy = r.y;
+  Uz = r.z;
+  S = r.w;
+  wave_lds_sync();  // the read is done before the wave writes the list again
+}
+
 // The lane's particle within the tile at first: threadIdx.x, or the tile's
 // last particle for idle lanes past n.
 __device__ __forceinline__ uint32_t lane_offset(const AdvanceArgs& a, int64_t first) {
@@ -555,7 +575,7 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
         tile_visit<G, 4>(ts, gc, a.lr, lane, wid, lds, walk, SortedTag(), Stage{});
       }
       if (!TAPE) M = __int_as_float(Mb);
-      quad_sums(acc, lane, Ux, Uy, Uz, S);
+      lds_quad_sums(acc, lane, &lds.p[wid][0][0], Ux, Uy, Uz, S);
     }
     if (TAPE) {
       M = __uint_as_float((uint32_t)(key >> 32));
