@@ -284,8 +284,12 @@ constexpr int kGatherListEntries = 128;  // per wave, split over the G group lis
 constexpr uint32_t kLaneWalkShare = 4;  // see advance_tile
 constexpr int kGatherRows = 64;
 
-template <int G>
-using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries / G : 64), kGatherRows>;
+// The single-scene step kernel runs blocks of two waves: a block's LDS is
+// released only when its slowest wave ends, so smaller blocks leave fewer
+// slots idle behind a long wave (the batched kernel keeps kBlock tiles).
+constexpr int kGatherThreads = 128;
+template <int G, int W = kWaves>
+using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries / G : 64), kGatherRows, W>;
 
 // The cull of a one-group wave in centred form: candidates are tested on
 // q = X - c against the wave box's centre c and half-extents (tile_visit),
@@ -441,9 +445,9 @@ __device__ __forceinline__ HRLane load_lane(const AdvanceArgs& a, int64_t first)
 // the exact predicate on every list entry (or stencil candidate), the count
 // of entries of positive computed weight and the largest weight on which the
 // two disagree.
-template <bool RIGID, int G, bool TAPE = false, bool DBG = false, class WP>
+template <bool RIGID, int G, bool TAPE = false, bool DBG = false, class WP, class LDS>
 __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
-                                             GatherLDS<G>& lds, int64_t first, const HRLane& st) {
+                                             LDS& lds, int64_t first, const HRLane& st) {
   static_assert(!(TAPE && DBG), "the debug instance records no tape");
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -612,9 +616,9 @@ __device__ __forceinline__ void advance_tile(const AdvanceArgs& a, WP walls,
 // Seven waves per SIMD asked of the register allocator; with four lane groups
 // the LDS lists (35 KB per block) allow four.
 template <bool RIGID, int G, bool TAPE = false, bool DBG = false>
-__global__ __launch_bounds__(kBlock, G == 4 ? 4 : 7) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
-  __shared__ GatherLDS<G> lds;
-  const int64_t first = (int64_t)blockIdx.x * kBlock;
+__global__ __launch_bounds__(kGatherThreads, G == 4 ? 4 : 7) void k_advance_tiled(AdvanceArgs a, WallTable wt) {
+  __shared__ GatherLDS<G, kGatherThreads / 64> lds;
+  const int64_t first = (int64_t)blockIdx.x * kGatherThreads;
   advance_tile<RIGID, G, TAPE, DBG>(a, wt.w, lds, first, load_lane(a, first));
 }
 
@@ -660,28 +664,29 @@ __global__ __launch_bounds__(kBlock, 7) void k_advance_batched(BatchAdvanceArgs 
 hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, int debug, hipStream_t st) {
   if (a.n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((a.n + kBlock - 1) / kBlock);
+  const unsigned tblocks = (unsigned)((a.n + kGatherThreads - 1) / kGatherThreads);
   if (debug == 1)
     hipLaunchKernelGGL(k_advance<true>, dim3(blocks), dim3(kBlock), 0, st, a, walls);
   else if (debug == 2 && a.sc.has_rigid)
-    hipLaunchKernelGGL((k_advance_tiled<true, 1, false, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<true, 1, false, true>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else if (debug == 2 && a.groups == 4)
-    hipLaunchKernelGGL((k_advance_tiled<false, 4, false, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<false, 4, false, true>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else if (debug == 2 && a.groups == 2)
-    hipLaunchKernelGGL((k_advance_tiled<false, 2, false, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<false, 2, false, true>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else if (debug == 2)
-    hipLaunchKernelGGL((k_advance_tiled<false, 1, false, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<false, 1, false, true>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else if (a.tape != nullptr && a.sc.has_rigid)
-    hipLaunchKernelGGL((k_advance_tiled<true, 1, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<true, 1, true>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else if (a.tape != nullptr)
-    hipLaunchKernelGGL((k_advance_tiled<false, 1, true>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<false, 1, true>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else if (a.sc.has_rigid)
-    hipLaunchKernelGGL((k_advance_tiled<true, 1>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<true, 1>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else if (a.groups == 4)
-    hipLaunchKernelGGL((k_advance_tiled<false, 4>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<false, 4>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else if (a.groups == 2)
-    hipLaunchKernelGGL((k_advance_tiled<false, 2>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<false, 2>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   else
-    hipLaunchKernelGGL((k_advance_tiled<false, 1>), dim3(blocks), dim3(kBlock), 0, st, a, walls);
+    hipLaunchKernelGGL((k_advance_tiled<false, 1>), dim3(tblocks), dim3(kGatherThreads), 0, st, a, walls);
   return hipGetLastError();
 }
 

@@ -126,21 +126,21 @@ __device__ __forceinline__ float box_dist2(const Box& b, float px, float py, flo
   return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
-// LDS of the wave tiles of one block: Cap list entries per group (32 B each)
-// and up to Rows stencil rows per wave (a multiple of 64; a wave with more
-// rows takes the per-lane walk).
-template <int G, int Cap, int Rows>
+// LDS of the wave tiles of one block of Waves waves: Cap list entries per
+// group (32 B each) and up to Rows stencil rows per wave (a multiple of 64; a
+// wave with more rows takes the per-lane walk).
+template <int G, int Cap, int Rows, int Waves = kWaves>
 struct TileLDS {
   static constexpr int kCap = Cap;
   static constexpr int kRows = Rows;
   static_assert(Rows % 64 == 0 && Rows <= 256, "rows are scanned 64 at a time");
   // one streaming pass appends up to 64 candidates to every group list
   static_assert(Cap >= 64, "a group list must hold one full pass");
-  float4 p[kWaves][G][kCap];  // (X_j, sorted index | rigid << 31)
-  float4 v[kWaves][G][kCap];  // (V_j, original index as bits)
-  uint32_t rb[kWaves][kRows];      // first sorted index of each stencil row
-  uint32_t rp[kWaves][kRows + 1];  // exclusive prefix of row lengths
-  uint32_t mark[kWaves][64];       // streaming: row starting at each position of a round
+  float4 p[Waves][G][kCap];  // (X_j, sorted index | rigid << 31)
+  float4 v[Waves][G][kCap];  // (V_j, original index as bits)
+  uint32_t rb[Waves][kRows];      // first sorted index of each stencil row
+  uint32_t rp[Waves][kRows + 1];  // exclusive prefix of row lengths
+  uint32_t mark[Waves][64];       // streaming: row starting at each position of a round
 };
 
 template <int G>
