@@ -284,10 +284,10 @@ constexpr int kGatherListEntries = 128;  // per wave, split over the G group lis
 constexpr uint32_t kLaneWalkShare = 4;  // see advance_tile
 constexpr int kGatherRows = 64;
 
-// The single-scene step kernel runs blocks of two waves: a block's LDS is
-// released only when its slowest wave ends, so smaller blocks leave fewer
-// slots idle behind a long wave (the batched kernel keeps kBlock tiles).
-constexpr int kGatherThreads = 128;
+// The single-scene step kernel runs blocks of one wave: a block's LDS is
+// released only when its slowest wave ends, so one-wave blocks leave no slot
+// idle behind a long wave (the batched kernel keeps kBlock tiles).
+constexpr int kGatherThreads = 64;
 template <int G, int W = kWaves>
 using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries / G : 64), kGatherRows, W>;
 
