@@ -582,8 +582,9 @@ int upsample_batch_step(upsample_batch b, const float* lr_x, const float* lr_v, 
 int upsample_batch_sort_hr(upsample_batch b, float* hr_x, float* hr_v, int32_t* perm, void* stream);
 int upsample_batch_destroy(upsample_batch b);  /* waits for the device; NULL is a no-op */
 const char* upsample_batch_last_error(upsample_batch b);
-/* out[0] total_lr, out[1] total_hr, out[2] HR tiles, out[3] blocks of the
- * step kernel's grid (one per tile), out[4] graphs captured so far */
+/* out[0] total_lr, out[1] total_hr, out[2] HR tiles, out[3] launch positions
+ * of the step kernel's grid (one per tile; each runs as one one-wave block
+ * per 64 particles of its tile), out[4] graphs captured so far */
 int upsample_batch_info(upsample_batch b, int64_t* out);
 
 /*

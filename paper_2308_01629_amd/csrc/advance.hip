@@ -286,7 +286,8 @@ constexpr int kGatherRows = 64;
 
 // The single-scene step kernel runs blocks of one wave: a block's LDS is
 // released only when its slowest wave ends, so one-wave blocks leave no slot
-// idle behind a long wave (the batched kernel keeps kBlock tiles).
+// idle behind a long wave (the batched kernel runs its kBlock-particle tiles
+// as one-wave blocks too).
 constexpr int kGatherThreads = 64;
 template <int G, int W = kWaves>
 using GatherLDS = TileLDS<G, (kGatherListEntries / G > 64 ? kGatherListEntries / G : 64), kGatherRows, W>;
@@ -438,8 +439,9 @@ __device__ __forceinline__ HRLane load_lane(const AdvanceArgs& a, int64_t first)
                 *col(pv, o), *col(pv + n, o), *col(pv + 2 * n, o)};
 }
 
-// One block-sized tile of HR particles first .. first + kBlock - 1 (those
-// below a.n are live; the rest shadow the last particle and write nothing).
+// One block of HR particles first .. first + blockDim.x - 1, one wave each 64
+// (those below a.n are live; the rest shadow the last particle and write
+// nothing).
 // TAPE: also record (S, Ux, Uy, Uz, M, argmax) per particle for the adjoint.
 // DBG: the same arithmetic, plus per-lane member exports (AdvanceArgs dbg_*):
 // the exact predicate on every list entry (or stencil candidate), the count
@@ -622,16 +624,28 @@ __global__ __launch_bounds__(kGatherThreads, G == 4 ? 4 : 7) void k_advance_tile
   advance_tile<RIGID, G, TAPE, DBG>(a, wt.w, lds, first, load_lane(a, first));
 }
 
-// Batched step: block k takes entries k, k + grid, ... of the (scene, first
-// particle) tile table (one entry when the grid has a block per tile); each
-// tile reads its scene's constants from the scene table.  7 blocks per CU:
-// 72 VGPRs without spills (the scene constants are in scalar registers).
+// Batched step over the (scene, first particle) tile table; each tile reads
+// its scene's constants from the scene table.  A kBlock-particle tile is run
+// by four one-wave blocks.  Blocks go to the 8 XCDs round robin and the tile
+// table is laid out so that tile position p runs on XCD p mod 8: block q
+// takes wave (q / 8) mod 4 of position 8 (q / 32) + q mod 8, which keeps each
+// tile on its XCD and its four waves within 32 consecutive blocks.  The
+// waves are those of the single-scene kernel, so the results are
+// bit-identical to it.  Seven waves per SIMD: 72 VGPRs without spills (the
+// scene constants are in scalar registers).
+constexpr int kTileWaves = kBlock / kGatherThreads;
+static_assert(kTileWaves == 4, "the block-to-wave map assumes four waves per tile");
 template <bool RIGID>
-__global__ __launch_bounds__(kBlock, 7) void k_advance_batched(BatchAdvanceArgs b) {
-  __shared__ GatherLDS<1> lds;
-  for (int64_t t = blockIdx.x; t < b.n_tiles; t += gridDim.x) {
-    const BatchTile tile = load_uniform(b.tiles + t);
+__global__ __launch_bounds__(kGatherThreads, 7) void k_advance_batched(BatchAdvanceArgs b) {
+  __shared__ GatherLDS<1, kGatherThreads / 64> lds;
+  const int64_t total = (b.n_tiles + 7) / 8 * 32;
+  for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
+    const int64_t pos = (q >> 5) * 8 + (q & 7);
+    if (pos >= b.n_tiles) continue;  // block-uniform
+    const BatchTile tile = load_uniform(b.tiles + pos);
     const BatchScene sc = load_uniform(b.scenes + tile.scene);
+    const int64_t first = (int64_t)tile.first + ((q >> 3) & 3) * kGatherThreads;
+    if (first >= sc.n_hr) continue;  // past the scene's last particle (block-uniform)
     AdvanceArgs a;
     a.gc = sc.gc;
     a.sc = sc.sc;
@@ -654,8 +668,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_advance_batched(BatchAdvanceArgs 
     a.tile_max = b.tile_max;
     a.tape = nullptr;
     typedef const __attribute__((address_space(4))) float* ConstFloat;  // scalar loads of the scene's walls
-    advance_tile<RIGID, 1>(a, (ConstFloat)(const void*)(b.walls + sc.wall_off), lds, (int64_t)tile.first,
-                           load_lane(a, (int64_t)tile.first));
+    advance_tile<RIGID, 1>(a, (ConstFloat)(const void*)(b.walls + sc.wall_off), lds, first, load_lane(a, first));
   }
 }
 
@@ -692,10 +705,11 @@ hipError_t launch_advance(const AdvanceArgs& a, const WallTable& walls, int debu
 
 hipError_t launch_advance_batched(const BatchAdvanceArgs& b, int grid, hipStream_t st) {
   if (b.n_tiles == 0) return hipSuccess;
+  const dim3 blocks((unsigned)((grid + 7) / 8 * 32));
   if (b.rigid)
-    hipLaunchKernelGGL(k_advance_batched<true>, dim3(grid), dim3(kBlock), 0, st, b);
+    hipLaunchKernelGGL(k_advance_batched<true>, blocks, dim3(kGatherThreads), 0, st, b);
   else
-    hipLaunchKernelGGL(k_advance_batched<false>, dim3(grid), dim3(kBlock), 0, st, b);
+    hipLaunchKernelGGL(k_advance_batched<false>, blocks, dim3(kGatherThreads), 0, st, b);
   return hipGetLastError();
 }
 

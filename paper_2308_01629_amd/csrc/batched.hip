@@ -238,9 +238,10 @@ int upsample_batch_init(const upsample_scene* scenes, int32_t n_scenes, uint32_t
     delete b;
     return UPSAMPLE_ERR_NO_DEVICE;
   }
-  // One block per tile: tiles differ in cost, and the hardware dispatcher
-  // balances them better than a resident grid striding over the table (that
-  // was 9% slower on the 64-scene workload).
+  // One launch position per tile (run as one one-wave block per 64 of its
+  // particles): tiles differ in cost, and the hardware dispatcher balances
+  // them better than a resident grid striding over the table (that was 9%
+  // slower on the 64-scene workload).
   b->grid_blocks = (int)std::max<int64_t>(b->n_tiles, 1);
 
   // tile table in XCD order: block k runs on XCD k % kXcds and walks a
